@@ -1,0 +1,191 @@
+/*
+ * impconv.h -- C ABI of libimpconv: implicitly dealiased convolutions on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operations are those of J. C. Bowman and M. Roberts, "Efficient
+ * dealiased convolutions without padding" (SIAM J. Sci. Comput., 2011):
+ * linear (non-cyclic) convolution sums computed from size-N FFTs of
+ * residue-split, twiddle-shifted subsequences instead of from explicitly
+ * zero-padded size-2N (complex, 1/2 rule) or size-3N (centered Hermitian,
+ * 2/3 rule) transforms.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Data pointers (f, g, e, h, work) are DEVICE pointers owned by the caller.
+ *   Complex values are interleaved (re, im): complex64 = 2 x float,
+ *   complex128 = 2 x double (the layout of torch.complex64/complex128).
+ *   Arrays are C-contiguous, last axis stride 1.
+ * - Inputs are read only.  h must not overlap f, g or e (E_ARG).
+ * - The result is the exact (unnormalized) convolution sum, as defined per
+ *   entry point below; only the summation order differs from the definition.
+ * - Work arrays are separate from the data and provided by the caller
+ *   (Sec. 1: decoupling data and work memory); query their size with the
+ *   *_workspace functions.  A size of 0 means work may be NULL.
+ * - All work is enqueued on `stream` (a hipStream_t; NULL = default stream).
+ *   Nothing synchronizes; device-side faults surface at the caller's next
+ *   synchronization.
+ * - The library allocates no data-sized memory.  On first use on a device it
+ *   allocates ~12 MB of twiddle tables (impconv_init); call impconv_init()
+ *   outside any stream capture before capturing calls into a hipGraph.
+ * - Every argument check happens on the host before any launch.  Errors:
+ *     IMPCONV_E_ARG        null pointer, bad kind/dtype/flags, aliasing
+ *     IMPCONV_E_SIZE       m < 1, batch < 0, M < 1, bad storage extents
+ *     IMPCONV_E_WORKSPACE  work_bytes smaller than the queried size
+ *     IMPCONV_E_ALIGN      pointer not aligned to its complex element size
+ *     IMPCONV_E_UNSUPPORTED a size beyond what this build implements
+ *     IMPCONV_E_HIP        a HIP call failed (text in impconv_last_error())
+ *   No exception crosses the ABI.  impconv_last_error() is thread-local.
+ * - Any m >= 1 is accepted.  The kernels use FFT sizes N = the next power of
+ *   two >= m (even N for the Hermitian rule); inputs read as zero beyond m,
+ *   which leaves every output k < m unchanged.
+ */
+#ifndef IMPCONV_H
+#define IMPCONV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum impconv_status {
+    IMPCONV_OK = 0,
+    IMPCONV_E_ARG = 1,
+    IMPCONV_E_SIZE = 2,
+    IMPCONV_E_WORKSPACE = 3,
+    IMPCONV_E_ALIGN = 4,
+    IMPCONV_E_UNSUPPORTED = 5,
+    IMPCONV_E_HIP = 6
+} impconv_status;
+
+typedef enum impconv_dtype { IMPCONV_C64 = 0, IMPCONV_C128 = 1 } impconv_dtype;
+
+typedef enum impconv_kind {
+    IMPCONV_COMPLEX = 0,   /* origin at index 0, 1/2 padding rule (Sec. 2.1, 3.1, 3.4) */
+    IMPCONV_HERMITIAN = 1, /* centered Hermitian, 2/3 padding rule (Sec. 2.3, 3.2, 3.4) */
+    IMPCONV_TERNARY = 2    /* centered Hermitian ternary (Sec. 4) */
+} impconv_kind;
+
+/* Flag bits. */
+#define IMPCONV_EXPLICIT_PADDED (1u << 0) /* comparator: explicitly zero-padded FFT convolution */
+#define IMPCONV_REV_F (1u << 1)           /* complex 1D: read f reversed, f'_k = f_{m-1-k} */
+#define IMPCONV_CONJ_G (1u << 2)          /* complex 1D: read g conjugated */
+#define IMPCONV_REV_OUT (1u << 3)         /* complex 1D: write h reversed */
+#define IMPCONV_NO_SYMMETRIZE (1u << 4)   /* Hermitian nD: trust the k_last = 0 plane (see conv2d) */
+
+/* Version as 10000*major + 100*minor + patch. */
+int impconv_version(void);
+
+/* Static description of a status code. */
+const char* impconv_status_string(int status);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char* impconv_last_error(void);
+
+/* Create the twiddle tables of the current HIP device (idempotent,
+ * thread-safe, synchronous).  Every entry point calls it implicitly. */
+impconv_status impconv_init(void);
+
+/* ----------------------------------------------------------------------
+ * 1D convolutions.  Layout: f, g are [batch][M][m], h is [batch][m]; the
+ * M axis is the dot-product width of Sec. 3.3 (f*g read as sum_i f_i*g_i).
+ * work may be NULL when impconv_conv1d_workspace reports 0 bytes.
+ * ---------------------------------------------------------------------- */
+
+/* Workspace bytes for a 1D call of the given kind (flags as for the call). */
+impconv_status impconv_conv1d_workspace(int kind, int dtype, int64_t batch, int64_t M, int64_t m,
+                                        uint32_t flags, size_t* bytes);
+
+/* Complex 1D convolution, Sec. 2.1 (fftpadBackward / fftpadForward / cconv):
+ *   h_k = sum_{i<M} sum_{p=0}^{k} f'_{i,p} g'_{i,k-p},   k = 0..m-1,
+ * with f' = f (or f reversed under IMPCONV_REV_F) and g' = g (or conj g under
+ * IMPCONV_CONJ_G); IMPCONV_REV_OUT stores h_{m-1-k} at index k.  These three
+ * flags express the adjoint: dL/df = REV_OUT(conv(REV_F(dL/dh), CONJ_G(g))).
+ * With IMPCONV_EXPLICIT_PADDED the same sum is computed by the conventional
+ * method (inputs copied zero-padded to 2N in work, size-2N cyclic FFT
+ * convolution, output cropped); REV/CONJ flags are not accepted with it. */
+impconv_status impconv_conv1d_complex(int dtype, int64_t batch, int64_t M, int64_t m,
+                                      const void* f, const void* g, void* h, void* work,
+                                      size_t work_bytes, uint32_t flags, void* stream);
+
+/* Centered Hermitian 1D convolution, Sec. 2.3 (2/3 rule, Fourier size 3N):
+ * f, g hold the non-negative wavenumbers 0..m-1 of fields with
+ * U_{-k} = conj U_k; Im f_0 and Im g_0 are ignored.
+ *   h_k = sum_{i<M} sum_{p=k-m+1}^{m-1} f_{i,p} g_{i,k-p},   k = 0..m-1.
+ * IMPCONV_EXPLICIT_PADDED: conventional comparator (half spectra copied into
+ * a real-FFT buffer of size 2^ceil(log2(3m-2)), physical-space product). */
+impconv_status impconv_conv1d_hermitian(int dtype, int64_t batch, int64_t M, int64_t m,
+                                        const void* f, const void* g, void* h, void* work,
+                                        size_t work_bytes, uint32_t flags, void* stream);
+
+/* Centered Hermitian ternary 1D convolution, Sec. 4 (Fourier size 4N):
+ * f, g, e are [batch][m] Hermitian halves (Im of entry 0 ignored);
+ *   h_k = sum_{p,q,r in [-m+1, m-1], p+q+r=k} f_p g_q e_r,   k = 0..m-1. */
+impconv_status impconv_conv1d_ternary(int dtype, int64_t batch, int64_t m, const void* f,
+                                      const void* g, const void* e, void* h, void* work,
+                                      size_t work_bytes, uint32_t flags, void* stream);
+
+/* ----------------------------------------------------------------------
+ * 2D / 3D convolutions (Secs. 3.1-3.4).  m[d] = logical modes per axis,
+ * n[d] = storage extent per axis.  f, g are [batch][M][n0][n1](...[n2]),
+ * h is [batch][n0][n1](...[n2]).
+ *   IMPCONV_COMPLEX:   n[d] = m[d];  h_k = sum_i sum_{0<=p<=k} f_{i,p} g_{i,k-p}
+ *                      for 0 <= k_d < m_d (componentwise).
+ *   IMPCONV_HERMITIAN: leading axes centered, n[d] in {2m[d]-1, 2m[d]},
+ *                      wavenumber k at index k + n[d] - m[d] (with n = 2m the
+ *                      index-0 slot is a zero slot); last axis = Hermitian
+ *                      half, n in {m, m+1}, wavenumber k at index k (index m
+ *                      a zero slot).  h_k = sum_i sum_{p in B, k-p in B}
+ *                      f_{i,p} g_{i,k-p} over the box B = prod [-m_d+1, m_d-1],
+ *                      k_last >= 0, the full fields defined by
+ *                      U_{-k} = conj U_k.  The k_last = 0 hyperplane is made
+ *                      Hermitian on load (concluding remarks of the paper):
+ *                      its authoritative half is the one whose first nonzero
+ *                      leading wavenumber is positive, the other half is read
+ *                      as its conjugate mirror and the origin as real.  With
+ *                      IMPCONV_NO_SYMMETRIZE the plane is read as its
+ *                      Hermitian projection (U_k + conj U_{-k}) / 2 instead
+ *                      (identical for already-symmetric input).  Zero slots
+ *                      of h are written as 0.
+ * Multidimensional Hermitian convolutions require m[d] <= 4096 per axis in
+ * this build; complex ones m[d] <= 8192.
+ * ---------------------------------------------------------------------- */
+impconv_status impconv_convnd_workspace(int kind, int dtype, int ndim, const int64_t* m,
+                                        const int64_t* n, int64_t batch, int64_t M,
+                                        uint32_t flags, size_t* bytes);
+
+impconv_status impconv_conv2d(int kind, int dtype, int64_t batch, int64_t M, const int64_t* m,
+                              const int64_t* n, const void* f, const void* g, void* h,
+                              void* work, size_t work_bytes, uint32_t flags, void* stream);
+
+impconv_status impconv_conv3d(int kind, int dtype, int64_t batch, int64_t M, const int64_t* m,
+                              const int64_t* n, const void* f, const void* g, void* h,
+                              void* work, size_t work_bytes, uint32_t flags, void* stream);
+
+/* ----------------------------------------------------------------------
+ * Ragged batch of complex 1D convolutions of uneven lengths (Sec. 2.1 sum
+ * per pair).  Pair j has length m_host[j] >= 1 and occupies elements
+ * offset_host[j] .. offset_host[j] + m_host[j] - 1 of the packed f, g and h
+ * arrays (pairs must not overlap).  The plan copies the descriptors to the
+ * device once (synchronously, at creation) and groups pairs by FFT size;
+ * executing it launches nothing but kernels, so it may be captured in a
+ * hipGraph.  The plan is immutable; concurrent executions need distinct
+ * workspaces.  REV_F / CONJ_G / REV_OUT apply per pair as in
+ * impconv_conv1d_complex.
+ * ---------------------------------------------------------------------- */
+typedef struct impconv_ragged_plan impconv_ragged_plan;
+
+impconv_status impconv_ragged_plan_create(int dtype, int64_t npairs, const int64_t* m_host,
+                                          const int64_t* offset_host, impconv_ragged_plan** plan);
+impconv_status impconv_ragged_workspace(const impconv_ragged_plan* plan, size_t* bytes);
+impconv_status impconv_ragged_execute(const impconv_ragged_plan* plan, const void* f,
+                                      const void* g, void* h, void* work, size_t work_bytes,
+                                      uint32_t flags, void* stream);
+impconv_status impconv_ragged_plan_destroy(impconv_ragged_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IMPCONV_H */

@@ -49,6 +49,7 @@ def _load():
             "orc_conv1d_centered": ([_i64, _p, _p, _p], None),
             "orc_conv1d_hermitian": ([_i64, _i64, _i64, _p, _p, _p], None),
             "orc_conv1d_ternary": ([_i64, _i64, _p, _p, _p, _p], None),
+            "orc_conv1d_ternary_at": ([_i64, _p, _p, _p, _i64, _p, _p], None),
             "orc_convnd_complex": ([ctypes.c_int, _p, _i64, _p, _p, _p], None),
             "orc_convnd_complex_at": ([ctypes.c_int, _p, _i64, _p, _p, _i64, _p, _p], None),
             "orc_convnd_hermitian": ([ctypes.c_int, _p, _p, _i64, ctypes.c_int, _p, _p, _p], None),
@@ -159,6 +160,15 @@ def conv1d_ternary(f, g, e) -> np.ndarray:
     h = np.empty((batch, m), np.complex128)
     _load().orc_conv1d_ternary(m, batch, _ptr(f), _ptr(g), _ptr(e), _ptr(h))
     return h[0] if squeeze else h.reshape(*lead, m)
+
+
+def conv1d_ternary_at(f, g, e, ks) -> np.ndarray:
+    """Sec. 4 ternary sum at the output indices ks (O(m^2) per index)."""
+    f, g, e = _c(f), _c(g), _c(e)
+    ks = _i64arr(ks)
+    out = np.empty(len(ks), np.complex128)
+    _load().orc_conv1d_ternary_at(f.shape[-1], _ptr(f), _ptr(g), _ptr(e), len(ks), _ptr(ks), _ptr(out))
+    return out
 
 
 def convnd_complex(f, g) -> np.ndarray:

@@ -196,6 +196,26 @@ void orc_conv1d_ternary(int64_t m, int64_t batch, const dc *f, const dc *g,
         }
 }
 
+/* Same ternary sum evaluated only at the output indices ks[0..npts-1]. */
+void orc_conv1d_ternary_at(int64_t m, const dc *f, const dc *g, const dc *e, int64_t npts,
+                           const int64_t *ks, dc *out)
+{
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = 0; j < npts; ++j) {
+        const int64_t k = ks[j];
+        dc s = 0;
+        for (int64_t p = -(m - 1); p <= m - 1; ++p) {
+            const dc fp = herm1(f, p);
+            for (int64_t q = -(m - 1); q <= m - 1; ++q) {
+                const int64_t r = k - p - q;
+                if (r < -(m - 1) || r > m - 1) continue;
+                s += fp * herm1(g, q) * herm1(e, r);
+            }
+        }
+        out[j] = s;
+    }
+}
+
 /* ---------------------------------------------------------------------------
  * Multidimensional helpers.  Arrays are C-ordered, last axis contiguous
  * (Sec. 3.1: y is the stride-one direction).  ndim is 1, 2 or 3.

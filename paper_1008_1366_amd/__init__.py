@@ -1,0 +1,350 @@
+"""libimpconv: implicitly dealiased convolutions on AMD MI355X (gfx950).
+
+Thin Python binding over the C ABI declared in ``include/impconv.h``: every
+function here only checks shapes, allocates the caller-side output and
+workspace with torch (device memory), and calls the library on torch's
+current HIP stream.  All arithmetic happens in the library's HIP kernels.
+There is no CPU fallback: if ``libimpconv.so`` is missing or a tensor is not
+on a GPU, the call raises.
+
+Operations (Bowman & Roberts, "Efficient dealiased convolutions without
+padding"):
+  conv1d_complex    Sec. 2.1   h_k = sum_{p<=k} f_p g_{k-p}, k < m
+  conv1d_hermitian  Sec. 2.3   centered Hermitian (2/3 rule), k = 0..m-1
+  conv1d_ternary    Sec. 4     centered Hermitian ternary, k = 0..m-1
+  conv2d / conv3d   Sec. 3     complex or centered Hermitian, multi-D
+  RaggedPlan        uneven-length batches of complex 1D convolutions
+  conv1d_complex_ad / ragged_conv_ad  differentiable wrappers (autograd)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+__all__ = [
+    "lib", "available", "ImpconvError", "conv1d_complex", "conv1d_hermitian", "conv1d_ternary",
+    "conv2d", "conv3d", "RaggedPlan", "conv1d_complex_ad", "ragged_conv_ad", "workspace_bytes",
+    "EXPLICIT_PADDED", "REV_F", "CONJ_G", "REV_OUT", "NO_SYMMETRIZE",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libimpconv.so")
+
+EXPLICIT_PADDED, REV_F, CONJ_G, REV_OUT, NO_SYMMETRIZE = 1, 2, 4, 8, 16
+COMPLEX, HERMITIAN, TERNARY = 0, 1, 2
+C64, C128 = 0, 1
+
+_lib = None
+_i64 = ctypes.c_int64
+_p = ctypes.c_void_p
+_u32 = ctypes.c_uint32
+_sz = ctypes.c_size_t
+
+
+class ImpconvError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = ""
+        if _lib is not None:
+            msg = _lib.impconv_last_error().decode()
+            kind = _lib.impconv_status_string(status).decode()
+        else:
+            kind = str(status)
+        super().__init__(f"{where}: {kind} ({status}): {msg}")
+        self.status = status
+
+
+def lib():
+    """The loaded C library (ctypes).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1008_1366_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        st = ctypes.c_int
+        sig = {
+            "impconv_version": ([], ctypes.c_int),
+            "impconv_status_string": ([ctypes.c_int], ctypes.c_char_p),
+            "impconv_last_error": ([], ctypes.c_char_p),
+            "impconv_init": ([], st),
+            "impconv_conv1d_workspace": ([ctypes.c_int, ctypes.c_int, _i64, _i64, _i64, _u32,
+                                          ctypes.POINTER(_sz)], st),
+            "impconv_conv1d_complex": ([ctypes.c_int, _i64, _i64, _i64, _p, _p, _p, _p, _sz, _u32, _p], st),
+            "impconv_conv1d_hermitian": ([ctypes.c_int, _i64, _i64, _i64, _p, _p, _p, _p, _sz, _u32, _p], st),
+            "impconv_conv1d_ternary": ([ctypes.c_int, _i64, _i64, _p, _p, _p, _p, _p, _sz, _u32, _p], st),
+            "impconv_convnd_workspace": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, _p, _p, _i64, _i64,
+                                          _u32, ctypes.POINTER(_sz)], st),
+            "impconv_conv2d": ([ctypes.c_int, ctypes.c_int, _i64, _i64, _p, _p, _p, _p, _p, _p, _sz,
+                                _u32, _p], st),
+            "impconv_conv3d": ([ctypes.c_int, ctypes.c_int, _i64, _i64, _p, _p, _p, _p, _p, _p, _sz,
+                                _u32, _p], st),
+            "impconv_ragged_plan_create": ([ctypes.c_int, _i64, _p, _p, ctypes.POINTER(_p)], st),
+            "impconv_ragged_workspace": ([_p, ctypes.POINTER(_sz)], st),
+            "impconv_ragged_execute": ([_p, _p, _p, _p, _p, _sz, _u32, _p], st),
+            "impconv_ragged_plan_destroy": ([_p], st),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def available() -> bool:
+    return os.path.exists(LIB_PATH) and torch.cuda.is_available()
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise ImpconvError(status, where)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.complex64:
+        return C64
+    if t.dtype == torch.complex128:
+        return C128
+    raise TypeError(f"expected complex64 or complex128, got {t.dtype}")
+
+
+def _dev(*ts: torch.Tensor):
+    d = ts[0].device
+    for t in ts:
+        if t.device.type != "cuda":
+            raise RuntimeError("libimpconv runs on the GPU only: move the tensors to a cuda device")
+        if t.device != d:
+            raise RuntimeError("all tensors must be on the same device")
+        if not t.is_contiguous():
+            raise RuntimeError("tensors must be contiguous")
+    return d
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _work(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 16), dtype=torch.uint8, device=device)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _as_bmm(f: torch.Tensor):
+    """(m,) -> (1,1,m); (B,m) -> (B,1,m); (B,M,m) stays."""
+    if f.dim() == 1:
+        return f.view(1, 1, -1)
+    if f.dim() == 2:
+        return f.view(f.shape[0], 1, f.shape[1])
+    if f.dim() == 3:
+        return f
+    raise ValueError("1D inputs must have shape (m,), (B, m) or (B, M, m)")
+
+
+def workspace_bytes(kind: int, dtype: int, batch: int, M: int, m: int, flags: int = 0) -> int:
+    out = _sz()
+    _check(lib().impconv_conv1d_workspace(kind, dtype, batch, M, m, flags, ctypes.byref(out)),
+           "impconv_conv1d_workspace")
+    return out.value
+
+
+def _conv1d(kind: int, f, g, method: str, flags: int):
+    if f.shape != g.shape or f.dtype != g.dtype:
+        raise ValueError("f and g must have the same shape and dtype")
+    dev = _dev(f, g)
+    F, G = _as_bmm(f), _as_bmm(g)
+    B, M, m = F.shape
+    dt = _dtype_code(f)
+    if method == "explicit":
+        flags |= EXPLICIT_PADDED
+    elif method != "implicit":
+        raise ValueError("method must be 'implicit' or 'explicit'")
+    h = torch.empty((B, m), dtype=f.dtype, device=dev)
+    wb = workspace_bytes(kind, dt, B, M, m, flags)
+    w = _work(wb, dev)
+    fn = lib().impconv_conv1d_complex if kind == COMPLEX else lib().impconv_conv1d_hermitian
+    _check(fn(dt, B, M, m, _ptr(F), _ptr(G), _ptr(h), _ptr(w), wb, flags, ctypes.c_void_p(_stream(dev))),
+           "conv1d")
+    if f.dim() == 1:
+        return h.view(m)
+    return h
+
+
+def conv1d_complex(f, g, method: str = "implicit", flags: int = 0):
+    """Complex 1D dealiased convolution (Sec. 2.1) of (m,), (B, m) or (B, M, m)
+    inputs (M = dot-product width); returns (m,) or (B, m)."""
+    return _conv1d(COMPLEX, f, g, method, flags)
+
+
+def conv1d_hermitian(f, g, method: str = "implicit"):
+    """Centered Hermitian 1D convolution (Sec. 2.3) of non-negative-wavenumber
+    halves; Im f[0] and Im g[0] are ignored."""
+    return _conv1d(HERMITIAN, f, g, method, 0)
+
+
+def conv1d_ternary(f, g, e):
+    """Centered Hermitian ternary convolution (Sec. 4) of (m,) or (B, m) halves."""
+    if not (f.shape == g.shape == e.shape) or not (f.dtype == g.dtype == e.dtype):
+        raise ValueError("f, g, e must share shape and dtype")
+    dev = _dev(f, g, e)
+    F, G, Ev = (x.view(1, -1) if x.dim() == 1 else x for x in (f, g, e))
+    B, m = F.shape
+    dt = _dtype_code(f)
+    h = torch.empty((B, m), dtype=f.dtype, device=dev)
+    wb = workspace_bytes(TERNARY, dt, B, 1, m, 0)
+    w = _work(wb, dev)
+    _check(lib().impconv_conv1d_ternary(dt, B, m, _ptr(F), _ptr(G), _ptr(Ev), _ptr(h), _ptr(w), wb, 0,
+                                        ctypes.c_void_p(_stream(dev))), "conv1d_ternary")
+    return h.view(m) if f.dim() == 1 else h
+
+
+def _convnd(nd: int, f, g, kind: str, m, flags: int):
+    if f.shape != g.shape or f.dtype != g.dtype:
+        raise ValueError("f and g must have the same shape and dtype")
+    dev = _dev(f, g)
+    k = {"complex": COMPLEX, "hermitian": HERMITIAN}[kind]
+    n = tuple(f.shape[-nd:])
+    lead = f.shape[:-nd]
+    if len(lead) == 0:
+        B, M = 1, 1
+    elif len(lead) == 1:
+        B, M = lead[0], 1
+    elif len(lead) == 2:
+        B, M = lead
+    else:
+        raise ValueError("inputs must be (*n), (B, *n) or (B, M, *n)")
+    if m is None:
+        if k == COMPLEX:
+            m = n
+        else:
+            raise ValueError("Hermitian nD convolutions need the logical sizes m")
+    m = tuple(int(x) for x in m)
+    dt = _dtype_code(f)
+    marr = (ctypes.c_int64 * nd)(*m)
+    narr = (ctypes.c_int64 * nd)(*n)
+    out = _sz()
+    _check(lib().impconv_convnd_workspace(k, dt, nd, marr, narr, B, M, flags, ctypes.byref(out)),
+           "impconv_convnd_workspace")
+    w = _work(out.value, dev)
+    h = torch.empty((B, *n), dtype=f.dtype, device=dev)
+    fn = lib().impconv_conv2d if nd == 2 else lib().impconv_conv3d
+    _check(fn(k, dt, B, M, marr, narr, _ptr(f), _ptr(g), _ptr(h), _ptr(w), out.value, flags,
+              ctypes.c_void_p(_stream(dev))), f"conv{nd}d")
+    return h.view(*n) if len(lead) == 0 else h
+
+
+def conv2d(f, g, kind: str = "complex", m=None, symmetrize: bool = True):
+    """2D convolution (Secs. 3.1 / 3.2); inputs (n0, n1), (B, n0, n1) or
+    (B, M, n0, n1); Hermitian needs m = (m0, m1)."""
+    return _convnd(2, f, g, kind, m, 0 if symmetrize else NO_SYMMETRIZE)
+
+
+def conv3d(f, g, kind: str = "complex", m=None, symmetrize: bool = True):
+    """3D convolution (Sec. 3.4); inputs (n0, n1, n2), (B, ...) or (B, M, ...)."""
+    return _convnd(3, f, g, kind, m, 0 if symmetrize else NO_SYMMETRIZE)
+
+
+class RaggedPlan:
+    """Uneven-length batch of complex 1D convolutions packed in one array:
+    pair j uses elements offsets[j] .. offsets[j] + ms[j] - 1."""
+
+    def __init__(self, ms, offsets, dtype=torch.complex64, device=None):
+        import numpy as np
+        self.ms = np.ascontiguousarray(np.asarray(ms, dtype=np.int64))
+        self.offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        self.dtype = dtype
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.extent = int((self.ms + self.offsets).max()) if len(self.ms) else 0
+        dt = C64 if dtype == torch.complex64 else C128
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().impconv_ragged_plan_create(dt, len(self.ms), self.ms.ctypes.data_as(_p),
+                                                    self.offsets.ctypes.data_as(_p), ctypes.byref(self._h)),
+                   "impconv_ragged_plan_create")
+        out = _sz()
+        _check(lib().impconv_ragged_workspace(self._h, ctypes.byref(out)), "impconv_ragged_workspace")
+        self.work_bytes = out.value
+        self._work = _work(self.work_bytes, self.device)
+
+    def execute(self, f, g, flags: int = 0, out=None, work=None):
+        _dev(f, g)
+        if f.dtype != self.dtype or g.dtype != self.dtype:
+            raise TypeError("dtype differs from the plan's")
+        if f.numel() < self.extent or g.numel() < self.extent:
+            raise ValueError("packed inputs shorter than the plan's extent")
+        h = torch.zeros_like(f) if out is None else out
+        w = self._work if work is None else work
+        _check(lib().impconv_ragged_execute(self._h, _ptr(f), _ptr(g), _ptr(h), _ptr(w), self.work_bytes,
+                                            flags, ctypes.c_void_p(_stream(f.device))), "ragged_execute")
+        return h
+
+    def __del__(self):
+        try:
+            if self._h and _lib is not None:
+                _lib.impconv_ragged_plan_destroy(self._h)
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- autograd
+# For h = f * g (complex 1D, Sec. 2.1 sum) and a real loss L with
+# gh = dL/dRe h + i dL/dIm h (torch's convention), the vector-Jacobian
+# products are correlations:
+#   grad_f[p] = sum_{k>=p} gh_k conj(g_{k-p}) = REV(conv(REV(gh), conj g))_p
+# and symmetrically for g; the library evaluates them with the REV_F,
+# CONJ_G and REV_OUT load/store flags.
+
+class _Conv1dComplexFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, f, g):
+        ctx.save_for_backward(f, g)
+        return conv1d_complex(f, g)
+
+    @staticmethod
+    def backward(ctx, gh):
+        f, g = ctx.saved_tensors
+        gh = gh.contiguous()
+        gf = gg = None
+        shape = f.shape
+        F, G = _as_bmm(f), _as_bmm(g)
+        GH = gh.reshape(F.shape[0], 1, F.shape[2]).expand(-1, F.shape[1], -1).contiguous()
+        fl = REV_F | CONJ_G | REV_OUT
+        if ctx.needs_input_grad[0]:
+            gf = torch.stack([conv1d_complex(GH[:, i].contiguous(), G[:, i].contiguous(), flags=fl)
+                              for i in range(F.shape[1])], 1).reshape(shape)
+        if ctx.needs_input_grad[1]:
+            gg = torch.stack([conv1d_complex(GH[:, i].contiguous(), F[:, i].contiguous(), flags=fl)
+                              for i in range(F.shape[1])], 1).reshape(shape)
+        return gf, gg
+
+
+def conv1d_complex_ad(f, g):
+    """Differentiable conv1d_complex (hand-written adjoint, no autograd tape
+    through the kernels)."""
+    return _Conv1dComplexFn.apply(f, g)
+
+
+class _RaggedFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, plan, f, g):
+        ctx.plan = plan
+        ctx.save_for_backward(f, g)
+        return plan.execute(f, g)
+
+    @staticmethod
+    def backward(ctx, gh):
+        plan = ctx.plan
+        f, g = ctx.saved_tensors
+        gh = gh.contiguous()
+        fl = REV_F | CONJ_G | REV_OUT
+        gf = plan.execute(gh, g, flags=fl) if ctx.needs_input_grad[1] else None
+        gg = plan.execute(gh, f, flags=fl) if ctx.needs_input_grad[2] else None
+        return None, gf, gg
+
+
+def ragged_conv_ad(plan: RaggedPlan, f, g):
+    """Differentiable ragged batch (forward and hand-written adjoint)."""
+    return _RaggedFn.apply(plan, f, g)

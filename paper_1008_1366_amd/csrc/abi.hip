@@ -1,0 +1,264 @@
+// abi.cpp -- the extern "C" entry points of libimpconv: argument checks on
+// the host, workspace sizing, and the launch sequence of each convolution.
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+#include "multid.hpp"
+#include "runtime.hpp"
+
+namespace impconv {
+
+namespace {
+thread_local std::string g_err;
+}
+
+impconv_status fail(impconv_status st, const std::string& msg)
+{
+    g_err = msg;
+    return st;
+}
+
+impconv_status hip_fail(hipError_t e, const char* what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return IMPCONV_E_HIP;
+}
+
+namespace {
+
+size_t csize(int dt) { return dt ? 16 : 8; }
+
+bool aligned(const void* p, int dt) { return (reinterpret_cast<uintptr_t>(p) % csize(dt)) == 0; }
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb)
+{
+    if (!a || !b || na == 0 || nb == 0) return false;
+    const char* x = static_cast<const char*>(a);
+    const char* y = static_cast<const char*>(b);
+    return x < y + nb && y < x + na;
+}
+
+impconv_status check_dtype(int dt)
+{
+    if (dt != IMPCONV_C64 && dt != IMPCONV_C128) return fail(IMPCONV_E_ARG, "dtype must be IMPCONV_C64 or IMPCONV_C128");
+    return IMPCONV_OK;
+}
+
+impconv_status check_ptrs(int dt, std::initializer_list<const void*> ps)
+{
+    for (const void* p : ps) {
+        if (!p) return fail(IMPCONV_E_ARG, "null data pointer");
+        if (!aligned(p, dt)) return fail(IMPCONV_E_ALIGN, "data pointer not aligned to its complex element size");
+    }
+    return IMPCONV_OK;
+}
+
+hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+// ------------------------------------------------------------------ 1D plans
+struct Plan1D {
+    int kind, dt;
+    int64_t batch, M, m;
+    uint32_t flags;
+    int64_t N;        // FFT size of the fused kernel (complex: N >= m; Hermitian: NC; ternary: NN)
+    bool explicit_;   // comparator path
+    int64_t Ne;       // explicit: padded transform size
+    size_t work;      // bytes
+};
+
+impconv_status plan1d(int kind, int dt, int64_t batch, int64_t M, int64_t m, uint32_t flags, Plan1D* p)
+{
+    impconv_status st = check_dtype(dt);
+    if (st) return st;
+    if (m < 1) return fail(IMPCONV_E_SIZE, "m must be >= 1");
+    if (batch < 0) return fail(IMPCONV_E_SIZE, "batch must be >= 0");
+    if (M < 1) return fail(IMPCONV_E_SIZE, "M must be >= 1");
+    const uint32_t known = IMPCONV_EXPLICIT_PADDED | IMPCONV_REV_F | IMPCONV_CONJ_G | IMPCONV_REV_OUT;
+    if (flags & ~known) return fail(IMPCONV_E_ARG, "unknown flag bits for a 1D convolution");
+    const bool adj = flags & (IMPCONV_REV_F | IMPCONV_CONJ_G | IMPCONV_REV_OUT);
+    if (adj && kind != IMPCONV_COMPLEX) return fail(IMPCONV_E_ARG, "REV/CONJ flags apply to complex convolutions only");
+    *p = Plan1D{kind, dt, batch, M, m, flags, 0, bool(flags & IMPCONV_EXPLICIT_PADDED), 0, 0};
+    if (p->explicit_ && adj) return fail(IMPCONV_E_ARG, "REV/CONJ flags are not accepted with EXPLICIT_PADDED");
+    const size_t cs = csize(dt);
+    if (kind == IMPCONV_COMPLEX) {
+        p->N = next_pow2(m);
+        if (!p->explicit_) {
+            if (p->N > kRowMax) return large1d_plan(p->dt, batch, M, m, &p->work) ;
+        } else {
+            p->Ne = 2 * p->N;
+            if (p->Ne > kRowMax) return fail(IMPCONV_E_UNSUPPORTED, "explicit complex comparator supports m <= 4096");
+            p->work = size_t(batch) * (2 * M + 1) * p->Ne * cs;
+        }
+    } else if (kind == IMPCONV_HERMITIAN) {
+        int64_t N = next_pow2(m);
+        if (N < 2) N = 2;
+        p->N = N / 2;
+        if (!p->explicit_) {
+            if (p->N > kRowMax) return fail(IMPCONV_E_UNSUPPORTED, "Hermitian convolution supports m <= 16384");
+        } else {
+            // conventional 2/3 rule: real transform length 2^ceil(log2(3m-2)), half spectrum + 1
+            int64_t Ne = next_pow2(std::max<int64_t>(3 * m - 2, 2));
+            p->Ne = Ne;
+            if (Ne / 2 > kRowMax) return fail(IMPCONV_E_UNSUPPORTED, "explicit Hermitian comparator supports m <= 5462");
+            p->work = size_t(batch) * (2 * M + 1) * (Ne / 2 + 1) * cs;
+        }
+    } else if (kind == IMPCONV_TERNARY) {
+        if (p->explicit_) return fail(IMPCONV_E_UNSUPPORTED, "no explicit ternary comparator");
+        p->N = next_pow2(m);
+        if (p->N > kRowMax) return fail(IMPCONV_E_UNSUPPORTED, "ternary convolution supports m <= 8192");
+    } else {
+        return fail(IMPCONV_E_ARG, "unknown kind");
+    }
+    return IMPCONV_OK;
+}
+
+RowArgs row_args(const DevTables* tb, int dt)
+{
+    RowArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.tw = tb->tw[dt];
+    a.tw3 = tb->tw3[dt];
+    return a;
+}
+
+}  // namespace
+}  // namespace impconv
+
+using namespace impconv;
+
+extern "C" {
+
+int impconv_version(void) { return 10000; }
+
+const char* impconv_status_string(int s)
+{
+    switch (s) {
+        case IMPCONV_OK: return "ok";
+        case IMPCONV_E_ARG: return "invalid argument";
+        case IMPCONV_E_SIZE: return "invalid size";
+        case IMPCONV_E_WORKSPACE: return "workspace too small";
+        case IMPCONV_E_ALIGN: return "misaligned pointer";
+        case IMPCONV_E_UNSUPPORTED: return "unsupported size or mode";
+        case IMPCONV_E_HIP: return "HIP error";
+        default: return "unknown status";
+    }
+}
+
+const char* impconv_last_error(void) { return g_err.c_str(); }
+
+impconv_status impconv_init(void)
+{
+    return tables() ? IMPCONV_OK : IMPCONV_E_HIP;
+}
+
+impconv_status impconv_conv1d_workspace(int kind, int dtype, int64_t batch, int64_t M, int64_t m,
+                                        uint32_t flags, size_t* bytes)
+{
+    if (!bytes) return fail(IMPCONV_E_ARG, "bytes is NULL");
+    Plan1D p;
+    impconv_status st = plan1d(kind, dtype, batch, M, m, flags, &p);
+    if (st) return st;
+    *bytes = p.work;
+    return IMPCONV_OK;
+}
+
+static impconv_status run1d(int kind, int dtype, int64_t batch, int64_t M, int64_t m, const void* f,
+                            const void* g, const void* e, void* h, void* work, size_t wb,
+                            uint32_t flags, void* stream)
+{
+    Plan1D p;
+    impconv_status st = plan1d(kind, dtype, batch, M, m, flags, &p);
+    if (st) return st;
+    if (batch == 0) return IMPCONV_OK;
+    const int dt = dtype;
+    st = kind == IMPCONV_TERNARY ? check_ptrs(dt, {f, g, e, h}) : check_ptrs(dt, {f, g, h});
+    if (st) return st;
+    const size_t cs = csize(dt);
+    const size_t nin = size_t(batch) * (kind == IMPCONV_TERNARY ? 1 : M) * m * cs, nout = size_t(batch) * m * cs;
+    if (overlap(h, nout, f, nin) || overlap(h, nout, g, nin) || (e && overlap(h, nout, e, nin)))
+        return fail(IMPCONV_E_ARG, "h overlaps an input");
+    if (wb < p.work) return fail(IMPCONV_E_WORKSPACE, "workspace too small: need " + std::to_string(p.work) + " bytes");
+    if (p.work && !work) return fail(IMPCONV_E_ARG, "work is NULL");
+    if (p.work && !aligned(work, dt)) return fail(IMPCONV_E_ALIGN, "work not aligned");
+    const DevTables* tb = tables();
+    if (!tb) return IMPCONV_E_HIP;
+    hipStream_t s = S(stream);
+    hipError_t err = hipSuccess;
+
+    if (kind == IMPCONV_COMPLEX && !p.explicit_ && p.N > kRowMax)
+        return large1d_run(*tb, dt, batch, M, m, f, g, h, work, flags, s);
+
+    RowArgs a = row_args(tb, dt);
+    a.nrows = batch;
+    a.m = m;
+    a.M = M;
+    a.flags = flags & (kRevF | kConjG | kRevOut);
+    if (!p.explicit_) {
+        a.f = f; a.g = g; a.e = e; a.h = h;
+        if (kind == IMPCONV_TERNARY) {
+            a.f_row = a.g_row = a.e_row = a.h_row = m;
+            err = launch_row_ternary(dt, int(p.N), a, s);
+        } else {
+            a.f_row = a.g_row = M * m;
+            a.f_i = a.g_i = m;
+            a.h_row = m;
+            err = kind == IMPCONV_COMPLEX ? launch_row_complex(dt, int(p.N), a, s)
+                                          : launch_row_hermitian(dt, int(p.N), a, s);
+        }
+        if (err != hipSuccess) return hip_fail(err, "row kernel launch");
+        return IMPCONV_OK;
+    }
+    // Explicit comparator: materialize zero-padded copies in the workspace,
+    // transform at the padded size, multiply, transform back, crop.
+    const int64_t L = kind == IMPCONV_COMPLEX ? p.Ne : p.Ne / 2 + 1;  // padded row length
+    char* w = static_cast<char*>(work);
+    void* fp = w;
+    void* gp = w + size_t(batch) * M * L * cs;
+    void* hp = w + size_t(batch) * 2 * M * L * cs;
+    if ((err = launch_pad_rows(dt, f, fp, batch * M, m, m, L, s)) != hipSuccess) return hip_fail(err, "pad");
+    if ((err = launch_pad_rows(dt, g, gp, batch * M, m, m, L, s)) != hipSuccess) return hip_fail(err, "pad");
+    a.f = fp; a.g = gp; a.h = hp;
+    a.f_row = a.g_row = M * L;
+    a.f_i = a.g_i = L;
+    a.h_row = L;
+    if (kind == IMPCONV_COMPLEX) {
+        a.m = L;
+        a.m_out = L;
+        a.scale = 1.0 / double(p.Ne);
+        err = launch_row_cyclic(dt, int(p.Ne), a, s);
+    } else {
+        a.m = L;
+        a.m_out = L;
+        a.scale = 1.0 / double(p.Ne);
+        err = launch_row_realcyclic(dt, int(p.Ne / 2), a, s);
+    }
+    if (err != hipSuccess) return hip_fail(err, "explicit transform");
+    if ((err = launch_pad_rows(dt, hp, h, batch, L, m, m, s)) != hipSuccess) return hip_fail(err, "crop");
+    return IMPCONV_OK;
+}
+
+impconv_status impconv_conv1d_complex(int dtype, int64_t batch, int64_t M, int64_t m, const void* f,
+                                      const void* g, void* h, void* work, size_t work_bytes,
+                                      uint32_t flags, void* stream)
+{
+    return run1d(IMPCONV_COMPLEX, dtype, batch, M, m, f, g, nullptr, h, work, work_bytes, flags, stream);
+}
+
+impconv_status impconv_conv1d_hermitian(int dtype, int64_t batch, int64_t M, int64_t m, const void* f,
+                                        const void* g, void* h, void* work, size_t work_bytes,
+                                        uint32_t flags, void* stream)
+{
+    return run1d(IMPCONV_HERMITIAN, dtype, batch, M, m, f, g, nullptr, h, work, work_bytes, flags, stream);
+}
+
+impconv_status impconv_conv1d_ternary(int dtype, int64_t batch, int64_t m, const void* f, const void* g,
+                                      const void* e, void* h, void* work, size_t work_bytes,
+                                      uint32_t flags, void* stream)
+{
+    return run1d(IMPCONV_TERNARY, dtype, batch, 1, m, f, g, e, h, work, work_bytes, flags, stream);
+}
+
+}  // extern "C"

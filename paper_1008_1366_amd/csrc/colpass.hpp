@@ -1,0 +1,332 @@
+// colpass.hpp -- implicitly padded transforms along a strided (outer) axis.
+//
+// A column is one line along the transformed axis: `rows` elements at
+// element stride `ld`; neighbouring columns are adjacent in memory.  One
+// workgroup transforms a tile of TC adjacent columns, so every row segment
+// it loads or stores is TC contiguous complex values (64-128 bytes).  This is
+// the GPU form of the paper's multivector outer transforms (Sec. 3.1: one
+// root of unity per row serves a whole row of columns).
+//
+// Modes (Sec. 2.1 fftpadBackward/Forward and Sec. 2.2 fft0padBackward/
+// Forward, with the padded size N >= m a power of two):
+//   kPadBwd : in[0] (m rows) -> out[r] = FFT+(zeta_{2N}^{rk} U_k), r = 0, 1
+//   kPadFwd : in[0], in[1] (N rows) -> out_k = s (F0_k + zeta_{2N}^{-k} F1_k), k < m
+//   kCenBwd : in[0] (centered, wavenumber k at row k + off_in) ->
+//             out[r+1] = FFT+(w_{.,r}), r = -1, 0, 1, with w_{0,r} = U_0 and
+//             w_{k,r} = zeta_{3N}^{rk} (U_k + zeta_3^{-r} U_{k-N})
+//   kCenFwd : in[r+1] (N rows each) -> out (wavenumber k at row k + off_out):
+//             3N U_k = sum_r zeta_{3N}^{-rk} F_r(k mod N), |k| < m; zero slots 0
+//   kFft    : plain FFT of direction DIR of in[0] (n_in rows, zero padded to
+//             N) into out[0] (n_out rows), scaled by s (explicit comparator)
+//   kFsBwd / kFsFwd : first and last pass of the four-step form of the 1D
+//             complex convolution of length NF = N1 * N (N1 = ncols): a 1D
+//             input f_k, k = k1 + N1 k2, is read as an N x N1 matrix; the
+//             backward pass applies the residue shift zeta_{2NF}^{rk}, an
+//             N-point FFT down each column and the twiddle zeta_{NF}^{j2 k1};
+//             the forward pass undoes the twiddle, transforms back and
+//             recombines (F0 + zeta_{2NF}^{-k} F1) / 2NF.
+#pragma once
+#include "fft_wg.hpp"
+
+namespace impconv {
+
+enum ColMode { kPadBwd = 0, kPadFwd = 1, kCenBwd = 2, kCenFwd = 3, kFft = 4, kFsBwd = 5, kFsFwd = 6 };
+
+struct ColArgs {
+    const void* in[3];
+    void* out[3];
+    int64_t nslab;                 // independent 2D slabs, slab = s1 * nsub + s2
+    int64_t nsub;                  // >= 1
+    int64_t in_bs, out_bs;         // element stride of s1
+    int64_t in_bs2, out_bs2;       // element stride of s2
+    int64_t ncols;                 // columns per slab
+    int64_t in_ld, out_ld;         // element stride between rows
+    int n_in, n_out;               // stored rows of input / output
+    int m;                         // logical modes along the axis
+    int off_in, off_out;           // row of wavenumber 0 (centered modes)
+    int sym;                       // k_last = 0 symmetrization: 0 off, 1 2D rule, 2 3D rule
+    int64_t sym_nz;                // 3D rule: storage length of the last axis
+    int sym_offy;                  // 3D rule: row of k_y = 0 in the y storage
+    int sym_ny;                    // 3D rule: storage length of the y axis
+    // valid columns c = iy * mask_nz + iz: ylo <= iy < yhi and iz < zhi; the
+    // others (zero slots of the transverse axes) read as zero
+    int64_t mask_nz;
+    int mask_ylo, mask_yhi, mask_zhi;
+    int64_t nf;                    // four-step: full 1D length N1 * N
+    const int64_t* slab_off;       // four-step, optional: element offset of each s1 slab's 1D data
+    const int64_t* slab_m;         // four-step, optional: logical length of each s1 slab
+    uint32_t fsflags;              // four-step: 1 = reverse (input of kFsBwd, output of kFsFwd), 2 = conj input
+    double scale;
+    const void* tw;
+    const void* tw3;
+};
+
+// Columns per tile: a 64-byte row segment (8 complex64 / 4 complex128), up to
+// 128 bytes for short transforms, limited by 1024 threads and ~140 KB of LDS.
+template <typename T>
+__host__ __device__ constexpr int col_TC(int N)
+{
+    int tc = (N <= 512 ? 128 : 64) / int(sizeof(C<T>));
+    const int G = N / fft_E<T>(N);
+    while (tc > 1 && (tc * G > 1024 || (N > fft_E<T>(N) && tc * lpad_size(N) * int(sizeof(C<T>)) > 143360)))
+        tc /= 2;
+    return tc;
+}
+template <typename T> __host__ __device__ constexpr int col_block(int N) { return col_TC<T>(N) * (N / fft_E<T>(N)); }
+
+// blockIdx -> logical tile so that consecutive tiles (which share cache lines
+// and run concurrently) are issued to the same XCD: the hardware deals
+// workgroups to the 8 XCDs round-robin.  Returns -1 for the padding blocks.
+__device__ __forceinline__ int64_t xcd_tile(int64_t nblocks)
+{
+    const int64_t bid = blockIdx.x;
+    const int64_t per = (nblocks + 7) / 8;
+    const int64_t lg = (bid % 8) * per + bid / 8;
+    return lg < nblocks ? lg : -1;
+}
+
+template <typename T, int N, int MODE, int DIR>
+__global__ void __launch_bounds__(col_block<T>(N))
+k_colpass(ColArgs a)
+{
+    constexpr int E = fft_E<T>(N), G = N / E, TC = col_TC<T>(N);
+    constexpr int LDSN = N > E ? lpad_size(N) * TC : 1;
+    __shared__ C<T> sh[LDSN];
+    const int col = threadIdx.x % TC, t = threadIdx.x / TC;
+    const int64_t ntile = (a.ncols + TC - 1) / TC;
+    const int64_t lg = xcd_tile(a.nslab * ntile);
+    if (lg < 0) return;  // whole padding block: no barrier is reached
+    const int64_t slab = lg / ntile, tile = lg - slab * ntile;
+    const int64_t s1 = slab / a.nsub, s2 = slab - s1 * a.nsub;
+    const int64_t c = tile * TC + col;
+    const bool cin = c < a.ncols;  // column exists: stores go through
+    const int64_t cc = cin ? c : 0;
+    bool cact = cin;               // column carries data: loads go through
+    if (a.mask_nz > 0) {
+        const int64_t iy = cc / a.mask_nz, iz = cc - iy * a.mask_nz;
+        cact = cin && iy >= a.mask_ylo && iy < a.mask_yhi && iz < a.mask_zhi;
+    }
+    C<T>* lds = sh + col;
+    const C<T>* twb = (const C<T>*)a.tw;
+    const C<T>* twN = twb + tw_off(N);
+    const C<T>* tw2N = twb + tw_off(2 * N);
+    const C<T>* tw3N = (const C<T>*)a.tw3 + tw_off(N);
+    const int64_t ib = s1 * a.in_bs + s2 * a.in_bs2 + cc, ob = s1 * a.out_bs + s2 * a.out_bs2 + cc;
+    auto ldrow = [&](int q, int row, int nrows) -> C<T> {  // in[q] at (row, c), zero outside
+        const C<T>* p = (const C<T>*)a.in[q] + ib;
+        const bool ok = cact && row >= 0 && row < nrows;
+        const C<T> v = p[(ok ? row : 0) * a.in_ld];
+        return ok ? v : zero<T>();
+    };
+    auto strow = [&](int q, int row, C<T> v) {
+        if (cin) ((C<T>*)a.out[q])[ob + int64_t(row) * a.out_ld] = v;
+    };
+
+    if constexpr (MODE == kPadBwd) {
+        C<T> x[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = ldrow(0, t + e * G, a.m);
+        C<T> y[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) y[e] = x[e];
+        fft<T, N, E, +1>(y, t, lds, TC, twN);
+#pragma unroll
+        for (int e = 0; e < E; ++e) strow(0, t + e * G, y[e]);
+        const int z = opaque_zero();
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = x[e] * tw2N[t + e * G + z];
+        fft<T, N, E, +1>(x, t, lds, TC, twN);
+#pragma unroll
+        for (int e = 0; e < E; ++e) strow(1, t + e * G, x[e]);
+    } else if constexpr (MODE == kPadFwd) {
+        C<T> x[E], y[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = ldrow(0, t + e * G, N);
+        fft<T, N, E, -1>(x, t, lds, TC, twN);
+        {
+            const int z = opaque_zero();
+#pragma unroll
+            for (int e = 0; e < E; ++e) y[e] = ldrow(1, t + e * G + z, N);
+        }
+        fft<T, N, E, -1>(y, t, lds, TC, twN);
+        const T s = T(a.scale);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + e * G;
+            if (k < a.m) strow(0, k, scale(x[e] + mulc(y[e], tw2N[k]), s));
+        }
+    } else if constexpr (MODE == kCenBwd) {
+        // U_k and U_{k-N} of this thread's frequencies, with the optional
+        // conjugate mirror of the k_last = 0 hyperplane.
+        C<T> up[E], un[E];
+        int64_t mcol = cc;
+        bool plane = false;
+        int ky = 0;
+        if (a.sym == 1) {
+            plane = c == 0;
+        } else if (a.sym == 2) {
+            const int64_t iy = cc / a.sym_nz, iz = cc - iy * a.sym_nz;
+            plane = iz == 0;
+            ky = int(iy) - a.sym_offy;
+            const int iym = -ky + a.sym_offy;
+            mcol = (iym >= 0 && iym < a.sym_ny) ? int64_t(iym) * a.sym_nz : cc;
+        }
+        const C<T>* base = (const C<T>*)a.in[0] + s1 * a.in_bs + s2 * a.in_bs2;
+        auto ldk = [&](int k) -> C<T> {  // wavenumber k of this column (|k| < m)
+            const bool in = cact && k > -a.m && k < a.m;
+            // mirror: k < 0, or k = 0 with ky < 0 (3D); DC real
+            const bool mir = plane && (k < 0 || (k == 0 && ky < 0));
+            const int kk = in ? (mir ? -k : k) : 0;
+            const int64_t colx = mir ? mcol : cc;
+            C<T> v = base[colx + int64_t(kk + a.off_in) * a.in_ld];
+            if (mir) v = conj(v);
+            if (plane && k == 0 && ky == 0) v.im = T(0);
+            return in ? v : zero<T>();
+        };
+        // The thread index goes through an empty asm so the per-element
+        // mirror selection below stays a run-time computation.  With one
+        // thread per column (G = 1) it is otherwise fully constant-folded,
+        // and that folded form was observed to load wrong mirrored values
+        // (caught by the G = 1 symmetrized parity cases).
+        int tl = t;
+        asm volatile("" : "+v"(tl));
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = tl + e * G;
+            up[e] = ldk(k);
+            un[e] = ldk(k - N);
+        }
+        const T h3 = T(0.86602540378443864676);
+        static_for<3>([&](auto ri) {
+            constexpr int R = int(decltype(ri)::value) - 1;
+            const C<T> z3 = R == 0 ? C<T>{T(1), T(0)} : (R > 0 ? C<T>{T(-0.5), -h3} : C<T>{T(-0.5), h3});
+            const int z = opaque_zero();
+            C<T> w[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int k = t + e * G;
+                C<T> v = up[e] + z3 * un[e];
+                if constexpr (R != 0) {
+                    const C<T> tw = tw3N[k + z];
+                    v = R > 0 ? v * tw : mulc(v, tw);
+                }
+                w[e] = k == 0 ? up[e] : v;
+            }
+            fft<T, N, E, +1>(w, t, lds, TC, twN);
+#pragma unroll
+            for (int e = 0; e < E; ++e) strow(R + 1, t + e * G, w[e]);
+        });
+    } else if constexpr (MODE == kCenFwd) {
+        C<T> ap[E], an[E];
+        const T h3 = T(0.86602540378443864676);
+        static_for<3>([&](auto ri) {
+            constexpr int R = int(decltype(ri)::value) - 1;
+            C<T> x[E];
+            const int z = opaque_zero();
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[e] = ldrow(R + 1, t + e * G + z, N);
+            fft<T, N, E, -1>(x, t, lds, TC, twN);
+            // zeta_3^{R} for the negative wavenumbers
+            const C<T> z3p = R == 0 ? C<T>{T(1), T(0)} : (R > 0 ? C<T>{T(-0.5), h3} : C<T>{T(-0.5), -h3});
+            const int z2 = opaque_zero();
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int k = t + e * G;
+                C<T> v = x[e];
+                if constexpr (R != 0) {
+                    const C<T> tw = tw3N[k + z2];
+                    v = R > 0 ? mulc(v, tw) : v * tw;  // zeta_{3N}^{-Rk}
+                }
+                ap[e] = R == -1 ? v : ap[e] + v;
+                an[e] = R == -1 ? z3p * v : an[e] + z3p * v;
+            }
+        });
+        const T s = T(a.scale);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + e * G;
+            if (k < a.m) strow(0, k + a.off_out, scale(ap[e], s));
+            if (k >= 1 && k - N > -a.m) strow(0, k - N + a.off_out, scale(an[e], s));
+        }
+        // zero slots: rows whose wavenumber lies outside |k| < m
+        for (int row = t; row < a.n_out; row += G) {
+            const int k = row - a.off_out;
+            if (k <= -a.m || k >= a.m) strow(0, row, zero<T>());
+        }
+    } else if constexpr (MODE == kFsBwd) {
+        const C<T>* twF = twb + tw_off(a.nf);
+        const C<T>* tw2F = twb + tw_off(2 * a.nf);
+        const int64_t m1 = a.slab_m ? a.slab_m[s1] : a.m;
+        const C<T>* src = (const C<T>*)a.in[0] + (a.slab_off ? a.slab_off[s1] + s2 * a.in_bs2 : ib - cc);
+        const bool rev = a.fsflags & 1, cj = a.fsflags & 2;
+        C<T> x[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {  // element k = c + N1 (t + e G) of the 1D input
+            const int64_t k = cc + a.ncols * int64_t(t + e * G);
+            const bool ok = cact && k < m1;
+            C<T> v = src[ok ? (rev ? m1 - 1 - k : k) : 0];
+            if (cj) v = conj(v);
+            x[e] = ok ? v : zero<T>();
+        }
+        static_for<2>([&](auto ri) {
+            constexpr int R = decltype(ri)::value;
+            C<T> y[E];
+            const int z = opaque_zero();
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int64_t k = cc + a.ncols * int64_t(t + e * G);
+                y[e] = R ? x[e] * tw2F[k + z] : x[e];
+            }
+            fft<T, N, E, +1>(y, t, lds, TC, twN);
+            const int z2 = opaque_zero();
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int j2 = t + e * G;
+                strow(R, j2, y[e] * twF[int64_t(j2) * cc + z2]);
+            }
+        });
+    } else if constexpr (MODE == kFsFwd) {
+        const C<T>* twF = twb + tw_off(a.nf);
+        const C<T>* tw2F = twb + tw_off(2 * a.nf);
+        C<T> acc[E];
+        static_for<2>([&](auto ri) {
+            constexpr int R = decltype(ri)::value;
+            C<T> x[E];
+            const int z = opaque_zero();
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int j2 = t + e * G;
+                x[e] = mulc(ldrow(R, j2, N), twF[int64_t(j2) * cc + z]);
+            }
+            fft<T, N, E, -1>(x, t, lds, TC, twN);
+            const int z2 = opaque_zero();
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int64_t k = cc + a.ncols * int64_t(t + e * G);
+                acc[e] = R ? acc[e] + mulc(x[e], tw2F[k + z2]) : x[e];
+            }
+        });
+        const T s = T(a.scale);
+        const int64_t m1 = a.slab_m ? a.slab_m[s1] : a.m;
+        C<T>* H = (C<T>*)a.out[0] + (a.slab_off ? a.slab_off[s1] : ob - cc);
+        const bool rev = a.fsflags & 1;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int64_t k = cc + a.ncols * int64_t(t + e * G);
+            if (cin && k < m1) H[rev ? m1 - 1 - k : k] = scale(acc[e], s);
+        }
+    } else {  // kFft
+        C<T> x[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = ldrow(0, t + e * G, a.n_in);
+        fft<T, N, E, DIR>(x, t, lds, TC, twN);
+        const T s = T(a.scale);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + e * G;
+            if (k < a.n_out) strow(0, k, scale(x[e], s));
+        }
+    }
+}
+
+}  // namespace impconv

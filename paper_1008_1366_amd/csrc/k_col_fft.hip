@@ -1,0 +1,27 @@
+// Instantiations of the plain strided FFT column pass (explicit comparator).
+#include "colpass.hpp"
+#include "launch.hpp"
+
+namespace impconv {
+
+template <typename T, int N, int DIR>
+static hipError_t go(const ColArgs& a, hipStream_t s)
+{
+    const int64_t nb = a.nslab * ((a.ncols + col_TC<T>(N) - 1) / col_TC<T>(N));
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_colpass<T, N, kFft, DIR>), dim3(((nb + 7) / 8) * 8), dim3(col_block<T>(N)), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_fft(int dt, int N, int dir, const ColArgs& a, hipStream_t s)
+{
+    switch (N) {
+#define X(n) case n: return dir > 0 ? (dt ? go<double, n, 1>(a, s) : go<float, n, 1>(a, s)) \
+                                    : (dt ? go<double, n, -1>(a, s) : go<float, n, -1>(a, s));
+        IMPCONV_COL_CASES(X)
+#undef X
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace impconv

@@ -1,0 +1,27 @@
+// Instantiations of the kPadBwd / kPadFwd column passes.
+#include "colpass.hpp"
+#include "launch.hpp"
+
+namespace impconv {
+
+template <typename T, int N, int MODE>
+static hipError_t go(const ColArgs& a, hipStream_t s)
+{
+    const int64_t nb = a.nslab * ((a.ncols + col_TC<T>(N) - 1) / col_TC<T>(N));
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_colpass<T, N, MODE, 1>), dim3(((nb + 7) / 8) * 8), dim3(col_block<T>(N)), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_pad(int dt, int N, int mode, const ColArgs& a, hipStream_t s)
+{
+    switch (N) {
+#define X(n) case n: return mode == kPadBwd ? (dt ? go<double, n, kPadBwd>(a, s) : go<float, n, kPadBwd>(a, s)) \
+                                        : (dt ? go<double, n, kPadFwd>(a, s) : go<float, n, kPadFwd>(a, s));
+        IMPCONV_COL_CASES(X)
+#undef X
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace impconv

@@ -1,0 +1,67 @@
+// Instantiations of the centered Hermitian (2/3 rule) and ternary row kernels.
+#include "launch.hpp"
+
+namespace impconv {
+
+template <typename T, int NC>
+static hipError_t go_herm(const RowArgs& a, hipStream_t s)
+{
+    constexpr int threads = row_block<T, 1>(NC);
+    constexpr bool accg = !regs_fit<T>(5, row_E<T, 1>(NC), threads);
+    const int64_t blocks = (a.nrows + row_GPB<T, 1>(NC) - 1) / row_GPB<T, 1>(NC);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_conv1d_hermitian<T, NC, accg>), dim3(blocks), dim3(threads), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int NN>
+static hipError_t go_tern(const RowArgs& a, hipStream_t s)
+{
+    constexpr int threads = row_block<T, 1>(NN);
+    constexpr bool accg = !regs_fit<T>(5, row_E<T, 1>(NN), threads);
+    const int64_t blocks = (a.nrows + row_GPB<T, 1>(NN) - 1) / row_GPB<T, 1>(NN);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_conv1d_ternary<T, NN, accg>), dim3(blocks), dim3(threads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_hermitian(int dt, int NC, const RowArgs& a, hipStream_t s)
+{
+    switch (NC) {
+#define X(n) case n: return dt ? go_herm<double, n>(a, s) : go_herm<float, n>(a, s);
+        IMPCONV_POW2_CASES(X)
+#undef X
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int NC>
+static hipError_t go_realcyclic(const RowArgs& a, hipStream_t s)
+{
+    const int64_t blocks = (a.nrows + row_GPB<T, 1>(NC) - 1) / row_GPB<T, 1>(NC);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_conv1d_realcyclic<T, NC>), dim3(blocks), dim3(row_block<T, 1>(NC)), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_realcyclic(int dt, int NC, const RowArgs& a, hipStream_t s)
+{
+    switch (NC) {
+#define X(n) case n: return dt ? go_realcyclic<double, n>(a, s) : go_realcyclic<float, n>(a, s);
+        IMPCONV_POW2_CASES(X)
+#undef X
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_row_ternary(int dt, int NN, const RowArgs& a, hipStream_t s)
+{
+    switch (NN) {
+#define X(n) case n: return dt ? go_tern<double, n>(a, s) : go_tern<float, n>(a, s);
+        IMPCONV_POW2_CASES(X)
+#undef X
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace impconv

@@ -1,0 +1,39 @@
+// launch.hpp -- host launchers of the kernel families (one translation unit
+// per family so the template instantiations compile in parallel).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "rowconv.hpp"
+
+namespace impconv {
+
+// Largest FFT size of the fused row kernels (LDS-resident, 8192 complex
+// values = 64 KB complex64 / 128 KB complex128 plus padding).
+constexpr int kRowMax = 8192;
+
+// dt: 0 = complex64, 1 = complex128.  N / NC / NN: FFT size (power of two).
+hipError_t launch_row_complex(int dt, int N, const RowArgs& a, hipStream_t s);
+hipError_t launch_row_cyclic(int dt, int N, const RowArgs& a, hipStream_t s);
+hipError_t launch_row_hermitian(int dt, int NC, const RowArgs& a, hipStream_t s);
+hipError_t launch_row_ternary(int dt, int NN, const RowArgs& a, hipStream_t s);
+hipError_t launch_row_realcyclic(int dt, int NC, const RowArgs& a, hipStream_t s);
+
+// dst[r][j] = j < copy ? src[r][j] : 0, j < dst_ld
+hipError_t launch_pad_rows(int dt, const void* src, void* dst, int64_t nrows, int64_t src_ld,
+                           int64_t copy, int64_t dst_ld, hipStream_t s);
+
+// Column passes (colpass.hpp); N <= kColMax.
+constexpr int kColMax = 4096;
+struct ColArgs;
+hipError_t launch_col(int dt, int N, int mode, int dir, const ColArgs& a, hipStream_t s);
+hipError_t launch_col_pad(int dt, int N, int mode, const ColArgs& a, hipStream_t s);
+hipError_t launch_col_cen(int dt, int N, int mode, const ColArgs& a, hipStream_t s);
+hipError_t launch_col_fft(int dt, int N, int dir, const ColArgs& a, hipStream_t s);
+hipError_t launch_col_fs(int dt, int N, int mode, const ColArgs& a, hipStream_t s);
+
+}  // namespace impconv
+
+#define IMPCONV_POW2_CASES(X) \
+    X(1) X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192)
+#define IMPCONV_COL_CASES(X) \
+    X(1) X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)

@@ -1,0 +1,472 @@
+// multid.hip -- host side of the multi-pass convolutions.
+//
+// 2D (Sec. 3.1 cconv2 / Sec. 3.2 conv2) and 3D (Sec. 3.4 cconv3 and the
+// centered Hermitian analogue): every outer axis is transformed with the
+// implicitly padded column pass into 2 (complex) or 3 (centered) residue
+// arrays held in the caller's workspace, separate from the data (Sec. 1);
+// the innermost axis is convolved row by row with the fused 1D kernels; the
+// outer axes are transformed back in reverse order.  Workspace layout puts
+// the dot-product index i next to the innermost axis ([.. x'][i][y]), so that
+// each row kernel sees uniform row and term strides.
+//
+// Long 1D complex convolutions use the four-step form: column pass with the
+// residue shift and twiddle, cyclic row convolution, column pass back.
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "colpass.hpp"
+#include "launch.hpp"
+#include "multid.hpp"
+
+namespace impconv {
+
+namespace {
+
+size_t csize(int dt) { return dt ? 16 : 8; }
+
+ColArgs col_args(const DevTables& tb, int dt)
+{
+    ColArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nsub = 1;
+    a.tw = tb.tw[dt];
+    a.tw3 = tb.tw3[dt];
+    a.scale = 1.0;
+    return a;
+}
+
+RowArgs row_args(const DevTables& tb, int dt)
+{
+    RowArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.tw = tb.tw[dt];
+    a.tw3 = tb.tw3[dt];
+    a.scale = 1.0;
+    return a;
+}
+
+#define HIPCHK(expr, what)                                   \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return hip_fail(e_, what);     \
+    } while (0)
+
+}  // namespace
+
+void fourstep_split(int64_t N, int64_t* N1, int64_t* N2)
+{
+    const int l = ilog2(N);
+    *N2 = int64_t(1) << (l / 2);
+    *N1 = N / *N2;
+}
+
+impconv_status large1d_plan(int dt, int64_t batch, int64_t M, int64_t m, size_t* work)
+{
+    const int64_t N = next_pow2(m);
+    int64_t N1, N2;
+    fourstep_split(N, &N1, &N2);
+    if (N1 > kRowMax || N2 > kColMax || 2 * N > (int64_t(1) << kTwLog))
+        return fail(IMPCONV_E_UNSUPPORTED, "complex 1D convolution supports m <= 131072");
+    *work = size_t(4) * batch * M * N * csize(dt);
+    return IMPCONV_OK;
+}
+
+// Four-step pass sequence shared by the uniform and the ragged batches.
+// f_off/m_dev: optional per-pair offsets and lengths (ragged); otherwise pair
+// b starts at b * M * m and has length m.
+static impconv_status fourstep(const DevTables& tb, int dt, int64_t batch, int64_t M, int64_t m,
+                               int64_t N, const void* f, const void* g, void* h, void* work,
+                               const int64_t* d_off, const int64_t* d_m, uint32_t flags,
+                               hipStream_t s)
+{
+    int64_t N1, N2;
+    fourstep_split(N, &N1, &N2);
+    const size_t cs = csize(dt);
+    char* w = static_cast<char*>(work);
+    const size_t arr = size_t(batch) * M * N * cs;
+    void* Wf[2] = {w, w + arr};
+    void* Wg[2] = {w + 2 * arr, w + 3 * arr};
+    // pass 1: residue shift, column FFT (size N2), twiddle -> W[b][j2][i][k1]
+    for (int q = 0; q < 2; ++q) {
+        ColArgs a = col_args(tb, dt);
+        a.in[0] = q ? g : f;
+        a.out[0] = q ? Wg[0] : Wf[0];
+        a.out[1] = q ? Wg[1] : Wf[1];
+        a.nslab = batch * M;
+        a.nsub = M;
+        a.in_bs = M * m;
+        a.in_bs2 = m;
+        a.out_bs = M * N;
+        a.out_bs2 = N1;
+        a.ncols = N1;
+        a.out_ld = M * N1;
+        a.m = int(m);
+        a.nf = N;
+        a.slab_off = d_off;
+        a.slab_m = d_m;
+        a.fsflags = q == 0 ? ((flags & IMPCONV_REV_F) ? 1u : 0u) : ((flags & IMPCONV_CONJ_G) ? 2u : 0u);
+        HIPCHK(launch_col(dt, int(N2), kFsBwd, 1, a, s), "four-step pass 1");
+    }
+    // pass 2: cyclic convolution of the rows (size N1), written in place
+    for (int r = 0; r < 2; ++r) {
+        RowArgs a = row_args(tb, dt);
+        a.f = Wf[r];
+        a.g = Wg[r];
+        a.h = Wf[r];
+        a.nrows = batch * N2;
+        a.m = N1;
+        a.m_out = N1;
+        a.M = M;
+        a.f_row = a.g_row = a.h_row = M * N1;
+        a.f_i = a.g_i = N1;
+        a.scale = 1.0;
+        HIPCHK(launch_row_cyclic(dt, int(N1), a, s), "four-step pass 2");
+    }
+    // pass 3: twiddle, column FFT back, residue recombination, / 2N
+    ColArgs a = col_args(tb, dt);
+    a.in[0] = Wf[0];
+    a.in[1] = Wf[1];
+    a.out[0] = h;
+    a.nslab = batch;
+    a.in_bs = M * N;
+    a.in_ld = M * N1;
+    a.out_bs = m;
+    a.ncols = N1;
+    a.m = int(m);
+    a.nf = N;
+    a.slab_off = d_off;
+    a.slab_m = d_m;
+    a.fsflags = (flags & IMPCONV_REV_OUT) ? 1u : 0u;
+    a.scale = 1.0 / double(2 * N);
+    HIPCHK(launch_col(dt, int(N2), kFsFwd, 1, a, s), "four-step pass 3");
+    return IMPCONV_OK;
+}
+
+impconv_status large1d_run(const DevTables& tb, int dt, int64_t batch, int64_t M, int64_t m,
+                           const void* f, const void* g, void* h, void* work, uint32_t flags,
+                           hipStream_t s)
+{
+    return fourstep(tb, dt, batch, M, m, next_pow2(m), f, g, h, work, nullptr, nullptr, flags, s);
+}
+
+impconv_status large1d_run_ragged(const DevTables& tb, int dt, int64_t count, int64_t N, int64_t maxm,
+                                  const void* f, const void* g, void* h, void* work,
+                                  const int64_t* d_off, const int64_t* d_m, uint32_t flags,
+                                  hipStream_t s)
+{
+    return fourstep(tb, dt, count, 1, maxm, N, f, g, h, work, d_off, d_m, flags, s);
+}
+
+// ------------------------------------------------------------------ nD
+namespace {
+
+struct PlanND {
+    int kind, dt, nd;
+    int64_t m[3], n[3], Np[3];  // logical modes, storage extents, padded transform sizes (outer axes)
+    int64_t batch, M;
+    uint32_t flags;
+    size_t work;
+};
+
+impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t* n, int64_t batch,
+                      int64_t M, uint32_t flags, PlanND* p)
+{
+    if (dt != IMPCONV_C64 && dt != IMPCONV_C128) return fail(IMPCONV_E_ARG, "bad dtype");
+    if (kind != IMPCONV_COMPLEX && kind != IMPCONV_HERMITIAN) return fail(IMPCONV_E_ARG, "nD kind must be COMPLEX or HERMITIAN");
+    if (!m || !n) return fail(IMPCONV_E_ARG, "m or n is NULL");
+    if (batch < 0 || M < 1) return fail(IMPCONV_E_SIZE, "batch must be >= 0 and M >= 1");
+    const uint32_t known = IMPCONV_NO_SYMMETRIZE;
+    if (flags & ~known) return fail(IMPCONV_E_ARG, "unsupported flag for an nD convolution");
+    std::memset(p, 0, sizeof(*p));
+    p->kind = kind; p->dt = dt; p->nd = nd; p->batch = batch; p->M = M; p->flags = flags;
+    for (int d = 0; d < nd; ++d) {
+        p->m[d] = m[d];
+        p->n[d] = n[d];
+        if (m[d] < 1) return fail(IMPCONV_E_SIZE, "m must be >= 1 on every axis");
+        const bool last = d == nd - 1;
+        if (kind == IMPCONV_COMPLEX) {
+            if (n[d] != m[d]) return fail(IMPCONV_E_SIZE, "complex nD storage requires n == m");
+        } else if (!last) {
+            if (n[d] != 2 * m[d] - 1 && n[d] != 2 * m[d]) return fail(IMPCONV_E_SIZE, "centered axis needs n = 2m-1 or 2m");
+        } else {
+            if (n[d] != m[d] && n[d] != m[d] + 1) return fail(IMPCONV_E_SIZE, "Hermitian axis needs n = m or m+1");
+        }
+        p->Np[d] = next_pow2(m[d]);
+        if (!last && p->Np[d] > kColMax) return fail(IMPCONV_E_UNSUPPORTED, "outer axis too long (m <= 4096)");
+        if (last) {
+            int64_t L = kind == IMPCONV_COMPLEX ? p->Np[d] : std::max<int64_t>(p->Np[d], 2) / 2;
+            if (L > kRowMax) return fail(IMPCONV_E_UNSUPPORTED, "innermost axis too long");
+        }
+    }
+    const size_t cs = csize(dt);
+    const int R = kind == IMPCONV_COMPLEX ? 2 : 3;
+    if (nd == 2) {
+        // residue arrays [b][x'][i][y] for f and g
+        p->work = size_t(2) * R * batch * M * p->Np[0] * n[1] * cs;
+    } else {
+        const size_t X = size_t(2) * R * batch * M * p->Np[0] * n[1] * n[2];
+        const size_t Y = size_t(2) * R * R * batch * M * p->Np[0] * p->Np[1] * n[2];
+        const size_t Q = size_t(R) * batch * p->Np[0] * n[1] * n[2];
+        p->work = (X + Y + Q) * cs;
+    }
+    return IMPCONV_OK;
+}
+
+// Outer-axis backward pass of one input array (f or g).
+// src: [B][M][n0][cols], dst[r]: [B][N0][M][cols] (r < R)
+impconv_status outer_bwd(const DevTables& tb, const PlanND& p, const void* src, void* const* dst,
+                         int64_t nslab1, int64_t in_bs1, int64_t n0, int64_t m0, int64_t N0,
+                         int64_t cols, int sym, int64_t sym_nz, int sym_offy, int sym_ny,
+                         int64_t mask_nz, int mask_ylo, int mask_yhi, int mask_zhi, hipStream_t s)
+{
+    ColArgs a = col_args(tb, p.dt);
+    a.in[0] = src;
+    for (int r = 0; r < 3; ++r) a.out[r] = dst[r];
+    a.nslab = nslab1 * p.M;
+    a.nsub = p.M;
+    a.in_bs = in_bs1;
+    a.in_bs2 = n0 * cols;
+    a.out_bs = N0 * p.M * cols;
+    a.out_bs2 = cols;
+    a.ncols = cols;
+    a.in_ld = cols;
+    a.out_ld = p.M * cols;
+    a.n_in = int(n0);
+    a.m = int(m0);
+    a.off_in = int(n0 - m0);
+    a.sym = sym;
+    a.sym_nz = sym_nz;
+    a.sym_offy = sym_offy;
+    a.sym_ny = sym_ny;
+    a.mask_nz = mask_nz;
+    a.mask_ylo = mask_ylo;
+    a.mask_yhi = mask_yhi;
+    a.mask_zhi = mask_zhi;
+    const int mode = p.kind == IMPCONV_COMPLEX ? kPadBwd : kCenBwd;
+    HIPCHK(launch_col(p.dt, int(N0), mode, 1, a, s), "outer backward pass");
+    return IMPCONV_OK;
+}
+
+// Outer-axis forward pass: src[r]: [B][N0][ld=ldin] -> dst [B][n0][cols]
+impconv_status outer_fwd(const DevTables& tb, const PlanND& p, void* const* src, void* dst,
+                         int64_t nslab, int64_t in_bs, int64_t in_ld, int64_t n0, int64_t m0,
+                         int64_t N0, int64_t cols, hipStream_t s)
+{
+    ColArgs a = col_args(tb, p.dt);
+    for (int r = 0; r < 3; ++r) a.in[r] = src[r];
+    a.out[0] = dst;
+    a.nslab = nslab;
+    a.in_bs = in_bs;
+    a.out_bs = n0 * cols;
+    a.ncols = cols;
+    a.in_ld = in_ld;
+    a.out_ld = cols;
+    a.n_out = int(n0);
+    a.m = int(m0);
+    a.off_out = int(n0 - m0);
+    const bool cx = p.kind == IMPCONV_COMPLEX;
+    a.scale = 1.0 / double((cx ? 2 : 3) * N0);
+    HIPCHK(launch_col(p.dt, int(N0), cx ? kPadFwd : kCenFwd, 1, a, s), "outer forward pass");
+    return IMPCONV_OK;
+}
+
+// Innermost-axis row convolutions over nrows rows, in place in f.
+impconv_status inner_rows(const DevTables& tb, const PlanND& p, void* f, const void* g,
+                          int64_t nrows, hipStream_t s)
+{
+    const int nd = p.nd;
+    const int64_t m = p.m[nd - 1], n = p.n[nd - 1];
+    RowArgs a = row_args(tb, p.dt);
+    a.f = f;
+    a.g = g;
+    a.h = f;
+    a.nrows = nrows;
+    a.m = m;
+    a.M = p.M;
+    a.f_row = a.g_row = a.h_row = p.M * n;
+    a.f_i = a.g_i = n;
+    a.h_pad = n;
+    hipError_t e;
+    if (p.kind == IMPCONV_COMPLEX) {
+        e = launch_row_complex(p.dt, int(p.Np[nd - 1]), a, s);
+    } else {
+        e = launch_row_hermitian(p.dt, int(std::max<int64_t>(p.Np[nd - 1], 2) / 2), a, s);
+    }
+    HIPCHK(e, "inner row convolution");
+    return IMPCONV_OK;
+}
+
+impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const int64_t* m,
+                     const int64_t* n, const void* f, const void* g, void* h, void* work, size_t wb,
+                     uint32_t flags, void* stream)
+{
+    PlanND p;
+    impconv_status st = plannd(kind, dt, nd, m, n, batch, M, flags, &p);
+    if (st) return st;
+    if (batch == 0) return IMPCONV_OK;
+    const size_t cs = csize(dt);
+    if (!f || !g || !h) return fail(IMPCONV_E_ARG, "null data pointer");
+    for (const void* q : {f, g, (const void*)h})
+        if (reinterpret_cast<uintptr_t>(q) % cs) return fail(IMPCONV_E_ALIGN, "data pointer misaligned");
+    size_t vol = 1;
+    for (int d = 0; d < nd; ++d) vol *= size_t(n[d]);
+    const size_t nin = batch * M * vol * cs, nout = batch * vol * cs;
+    auto ov = [](const void* a, size_t na, const void* b, size_t nb) {
+        const char* x = (const char*)a; const char* y = (const char*)b;
+        return x < y + nb && y < x + na;
+    };
+    if (ov(h, nout, f, nin) || ov(h, nout, g, nin)) return fail(IMPCONV_E_ARG, "h overlaps an input");
+    if (wb < p.work) return fail(IMPCONV_E_WORKSPACE, "workspace too small: need " + std::to_string(p.work) + " bytes");
+    if (!work) return fail(IMPCONV_E_ARG, "work is NULL");
+    if (reinterpret_cast<uintptr_t>(work) % cs) return fail(IMPCONV_E_ALIGN, "work misaligned");
+    const DevTables* tbp = tables();
+    if (!tbp) return IMPCONV_E_HIP;
+    const DevTables& tb = *tbp;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool herm = kind == IMPCONV_HERMITIAN;
+    const int R = herm ? 3 : 2;
+    const bool sym = herm && !(flags & IMPCONV_NO_SYMMETRIZE);
+    char* w = static_cast<char*>(work);
+
+    if (nd == 2) {
+        const int64_t N0 = p.Np[0], n0 = n[0], n1 = n[1], m0 = m[0], m1 = m[1];
+        const size_t arr = size_t(batch) * M * N0 * n1 * cs;
+        void* Wf[3] = {w, w + arr, w + 2 * arr};
+        void* Wg[3] = {w + R * arr, w + (R + 1) * arr, w + (R + 2) * arr};
+        if (!herm) { Wf[2] = Wf[1]; Wg[2] = Wg[1]; }
+        // Hermitian: columns y < m1 carry data (slot m1 is a zero slot); k_y = 0 is column 0
+        const int64_t mask_nz = herm ? n1 : 0;
+        if ((st = outer_bwd(tb, p, f, Wf, batch, M * n0 * n1, n0, m0, N0, n1, sym ? 1 : 0, 0, 0, 0,
+                            mask_nz, 0, 1, int(m1), s))) return st;
+        if ((st = outer_bwd(tb, p, g, Wg, batch, M * n0 * n1, n0, m0, N0, n1, sym ? 1 : 0, 0, 0, 0,
+                            mask_nz, 0, 1, int(m1), s))) return st;
+        for (int r = 0; r < R; ++r)
+            if ((st = inner_rows(tb, p, Wf[r], Wg[r], batch * N0, s))) return st;
+        if ((st = outer_fwd(tb, p, Wf, h, batch, N0 * M * n1, M * n1, n0, m0, N0, n1, s))) return st;
+        return IMPCONV_OK;
+    }
+    // 3D
+    const int64_t N0 = p.Np[0], N1 = p.Np[1];
+    const int64_t n0 = n[0], n1 = n[1], n2 = n[2], m0 = m[0], m1 = m[1], m2 = m[2];
+    const size_t xa = size_t(batch) * M * N0 * n1 * n2 * cs;      // one x-residue array
+    const size_t ya = size_t(batch) * M * N0 * N1 * n2 * cs;       // one (x, y)-residue array
+    const size_t qa = size_t(batch) * N0 * n1 * n2 * cs;           // one y-forward output
+    void* Xf[3]; void* Xg[3];
+    for (int r = 0; r < 3; ++r) {
+        Xf[r] = w + (r < R ? r : R - 1) * xa;
+        Xg[r] = w + (R + (r < R ? r : R - 1)) * xa;
+    }
+    char* yb = w + 2 * R * xa;
+    char* qb = yb + 2 * R * R * ya;
+    // x pass over columns (y, z): valid columns skip the zero slots of y and z
+    const int ylo = herm ? int(n1 - (2 * m1 - 1)) : 0;
+    const int64_t mask_nz = herm ? n2 : 0;
+    if ((st = outer_bwd(tb, p, f, Xf, batch, M * n0 * n1 * n2, n0, m0, N0, n1 * n2, sym ? 2 : 0, n2,
+                        int(n1 - m1), int(n1), mask_nz, ylo, int(n1), int(m2), s))) return st;
+    if ((st = outer_bwd(tb, p, g, Xg, batch, M * n0 * n1 * n2, n0, m0, N0, n1 * n2, sym ? 2 : 0, n2,
+                        int(n1 - m1), int(n1), mask_nz, ylo, int(n1), int(m2), s))) return st;
+    void* Q[3];
+    for (int rx = 0; rx < R; ++rx) {
+        void* Yf[3]; void* Yg[3];
+        for (int ry = 0; ry < 3; ++ry) {
+            const int rr = ry < R ? ry : R - 1;
+            Yf[ry] = yb + (size_t(rx) * R + rr) * ya;
+            Yg[ry] = yb + (size_t(R) * R + rx * R + rr) * ya;
+        }
+        // y pass: slabs (b, x') of [n1][M][n2] -> [b, x'][y'][M][n2]
+        ColArgs a = col_args(tb, dt);
+        a.in[0] = nullptr;
+        PlanND py = p;
+        py.Np[0] = N1;
+        const int64_t nplanes = batch * N0;
+        // input layout after the x pass: [b][x'][i][y][z] -> slab (plane, i), rows y (ld n2)
+        auto ypass = [&](const void* src, void* const* dst) -> impconv_status {
+            ColArgs c = col_args(tb, dt);
+            c.in[0] = src;
+            for (int r = 0; r < 3; ++r) c.out[r] = dst[r];
+            c.nslab = nplanes * M;
+            c.nsub = M;
+            c.in_bs = M * n1 * n2;
+            c.in_bs2 = n1 * n2;
+            c.out_bs = N1 * M * n2;
+            c.out_bs2 = n2;
+            c.ncols = n2;
+            c.in_ld = n2;
+            c.out_ld = M * n2;
+            c.n_in = int(n1);
+            c.m = int(m1);
+            c.off_in = int(n1 - m1);
+            if (herm) { c.mask_nz = n2; c.mask_ylo = 0; c.mask_yhi = 1; c.mask_zhi = int(m2); }
+            HIPCHK(launch_col(dt, int(N1), herm ? kCenBwd : kPadBwd, 1, c, s), "y backward pass");
+            return IMPCONV_OK;
+        };
+        if ((st = ypass(Xf[rx], Yf))) return st;
+        if ((st = ypass(Xg[rx], Yg))) return st;
+        for (int ry = 0; ry < R; ++ry)
+            if ((st = inner_rows(tb, p, Yf[ry], Yg[ry], nplanes * N1, s))) return st;
+        // y forward: [plane][y'][M][n2] (3 residues) -> Q[rx] [plane][n1][n2]
+        Q[rx] = qb + size_t(rx) * qa;
+        {
+            ColArgs c = col_args(tb, dt);
+            for (int r = 0; r < 3; ++r) c.in[r] = Yf[r];
+            c.out[0] = Q[rx];
+            c.nslab = nplanes;
+            c.in_bs = N1 * M * n2;
+            c.out_bs = n1 * n2;
+            c.ncols = n2;
+            c.in_ld = M * n2;
+            c.out_ld = n2;
+            c.n_out = int(n1);
+            c.m = int(m1);
+            c.off_out = int(n1 - m1);
+            c.scale = 1.0 / double((herm ? 3 : 2) * N1);
+            HIPCHK(launch_col(dt, int(N1), herm ? kCenFwd : kPadFwd, 1, c, s), "y forward pass");
+        }
+        (void)a;
+        (void)py;
+    }
+    if (!herm) Q[2] = Q[1];
+    // x forward: Q[rx] [b][x'][n1 n2] -> h [b][n0][n1 n2]
+    PlanND px = p;
+    px.M = 1;
+    if ((st = outer_fwd(tb, px, Q, h, batch, N0 * n1 * n2, n1 * n2, n0, m0, N0, n1 * n2, s))) return st;
+    return IMPCONV_OK;
+}
+
+}  // namespace
+}  // namespace impconv
+
+using namespace impconv;
+
+extern "C" {
+
+impconv_status impconv_convnd_workspace(int kind, int dtype, int ndim, const int64_t* m,
+                                        const int64_t* n, int64_t batch, int64_t M, uint32_t flags,
+                                        size_t* bytes)
+{
+    if (!bytes) return fail(IMPCONV_E_ARG, "bytes is NULL");
+    if (ndim != 2 && ndim != 3) return fail(IMPCONV_E_ARG, "ndim must be 2 or 3");
+    PlanND p;
+    impconv_status st = plannd(kind, dtype, ndim, m, n, batch, M, flags, &p);
+    if (st) return st;
+    *bytes = p.work;
+    return IMPCONV_OK;
+}
+
+impconv_status impconv_conv2d(int kind, int dtype, int64_t batch, int64_t M, const int64_t* m,
+                              const int64_t* n, const void* f, const void* g, void* h, void* work,
+                              size_t work_bytes, uint32_t flags, void* stream)
+{
+    return runnd(kind, dtype, 2, batch, M, m, n, f, g, h, work, work_bytes, flags, stream);
+}
+
+impconv_status impconv_conv3d(int kind, int dtype, int64_t batch, int64_t M, const int64_t* m,
+                              const int64_t* n, const void* f, const void* g, void* h, void* work,
+                              size_t work_bytes, uint32_t flags, void* stream)
+{
+    return runnd(kind, dtype, 3, batch, M, m, n, f, g, h, work, work_bytes, flags, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,31 @@
+// multid.hpp -- host orchestration of the multi-pass convolutions: 1D
+// complex convolutions longer than one workgroup's LDS (four-step form) and
+// the 2D / 3D complex and centered Hermitian convolutions (Secs. 3.1-3.4).
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/impconv.h"
+#include "runtime.hpp"
+
+namespace impconv {
+
+// Complex 1D convolution of length m > kRowMax (next_pow2(m) <= 2^17).
+impconv_status large1d_plan(int dt, int64_t batch, int64_t M, int64_t m, size_t* work);
+impconv_status large1d_run(const DevTables& tb, int dt, int64_t batch, int64_t M, int64_t m,
+                           const void* f, const void* g, void* h, void* work, uint32_t flags,
+                           hipStream_t s);
+
+// Four-step passes for a ragged size class: count pairs of FFT size N, pair j
+// at element d_off[j] with length d_m[j] (device arrays), M = 1.
+impconv_status large1d_run_ragged(const DevTables& tb, int dt, int64_t count, int64_t N, int64_t maxm,
+                                  const void* f, const void* g, void* h, void* work,
+                                  const int64_t* d_off, const int64_t* d_m, uint32_t flags,
+                                  hipStream_t s);
+
+// Split of a four-step length N into N1 (row, contiguous) x N2 (column).
+void fourstep_split(int64_t N, int64_t* N1, int64_t* N2);
+
+}  // namespace impconv

@@ -1,0 +1,646 @@
+// rowconv.hpp -- fused 1D implicitly dealiased convolutions, one FFT group per
+// row, everything between the HBM load of the inputs and the HBM store of the
+// result kept in registers and LDS.
+//
+// A "row" is one independent 1D convolution: the contiguous inputs f_i, g_i
+// (i < M, the dot-product width of Sec. 3.3) and the contiguous output h.
+// Rows are batch entries in 1D and the innermost-axis lines of the
+// multidimensional convolutions.  The logical length m of a row may be any
+// value up to the kernel's padded size; entries at and beyond m read as zero,
+// which leaves the dealiased sum for k < m unchanged (zero padding of the
+// inputs beyond m contributes no terms).
+#pragma once
+#include "fft_wg.hpp"
+
+namespace impconv {
+
+enum : uint32_t {
+    kRevF = 1u << 1,    // read f reversed within its logical length
+    kConjG = 1u << 2,   // read g conjugated
+    kRevOut = 1u << 3,  // write h reversed within its logical length
+};
+
+struct RowArgs {
+    const void* f;
+    const void* g;
+    const void* e;  // third input of the ternary convolution
+    void* h;
+    int64_t nrows;
+    int64_t m;      // logical input length (all rows, unless row_m is given)
+    int64_t m_out;  // logical output length (cyclic kernel only)
+    int64_t M;      // dot-product width
+    int64_t f_row, f_i, g_row, g_i, e_row, h_row;  // element strides
+    const int64_t* row_off;  // optional per-row element offset (f, g, h share it)
+    const int64_t* row_m;    // optional per-row logical length
+    uint32_t flags;
+    double scale;            // cyclic kernel output scale
+    const void* tw;          // concatenated zeta_N^j tables, N = 1, 2, 4, ...
+    const void* tw3;         // concatenated zeta_{3N}^j tables (j < N)
+    int64_t h_pad;           // Hermitian rows: stored output length; entries m..h_pad-1 are zeroed
+};
+
+// Elements per thread of the row kernels: family 0 (complex, cyclic) keeps
+// fft_E values per thread; family 1 (Hermitian, ternary), whose prologues
+// read four inputs per element and keep five arrays live, keeps half as many.
+template <typename T, int FAM>
+__host__ __device__ constexpr int row_E(int N)
+{
+    // at least 2 (a radix-1 stage would make no progress) unless N == 1, and
+    // large enough that one group fits a 1024-thread workgroup
+    const int e = FAM == 0 ? fft_E<T>(N) : (fft_E<T>(N) / 2 >= 2 ? fft_E<T>(N) / 2 : fft_E<T>(N));
+    return N / e > 1024 ? N / 1024 : e;
+}
+// Threads per group and groups per block for a row kernel of FFT size N.
+template <typename T, int FAM = 0> __host__ __device__ constexpr int row_G(int N) { return N / row_E<T, FAM>(N); }
+template <typename T, int FAM = 0> __host__ __device__ constexpr int row_GPB(int N)
+{
+    return row_G<T, FAM>(N) >= 128 ? 1 : 128 / row_G<T, FAM>(N);
+}
+template <typename T, int FAM = 0> __host__ __device__ constexpr int row_block(int N)
+{
+    return row_G<T, FAM>(N) * row_GPB<T, FAM>(N);
+}
+template <typename T, int FAM = 0> __host__ __device__ constexpr int row_lds(int N)
+{
+    return N > row_E<T, FAM>(N) ? lpad_size(N) : 1;
+}
+
+// Waves per SIMD the row kernels are compiled for: the register budget of
+// each wave is 512 / waves.  Small blocks would otherwise let the compiler
+// take all 512 registers and leave one wave per SIMD to hide HBM latency.
+template <typename T>
+__host__ __device__ constexpr int row_waves(int)
+{
+    return 2;
+}
+
+// Whether narr live arrays of E complex values fit the VGPR budget a block
+// of `threads` leaves each wave (512 per SIMD lane, shared by the waves a
+// SIMD holds).  If not, the kernel accumulates its result in HBM instead of
+// registers.
+template <typename T>
+__host__ __device__ constexpr bool regs_fit(int narr, int E, int threads)
+{
+    int waves = (threads + 63) / 64;
+    int per_simd = (waves + 3) / 4;
+    if (per_simd < row_waves<T>(0)) per_simd = row_waves<T>(0);
+    int budget = 512 / per_simd;
+    int need = narr * E * 2 * int(sizeof(T) / 4);
+    return need * 5 <= budget * 4;  // leave ~20% for addresses and temporaries
+}
+
+struct RowCtx {
+    int64_t row, of, og, oe, oh;
+    int m;  // logical length of this row (0 for the padding groups past nrows)
+    bool act;
+};
+
+// Rows past nrows (the idle groups of the last block) read row 0 with
+// length 0, so every load below stays in bounds and yields zero.
+__device__ __forceinline__ RowCtx row_ctx(const RowArgs& a, int64_t row)
+{
+    RowCtx c;
+    c.row = row;
+    c.act = row < a.nrows;
+    const int64_t r = c.act ? row : 0;
+    c.m = c.act ? (int)a.m : 0;
+    c.of = r * a.f_row;
+    c.og = r * a.g_row;
+    c.oe = r * a.e_row;
+    c.oh = r * a.h_row;
+    if (a.row_off) c.of = c.og = c.oe = c.oh = a.row_off[r];
+    if (c.act && a.row_m) c.m = (int)a.row_m[r];
+    return c;
+}
+
+// U[j] for j < m, else 0, without a branch: the load always executes at a
+// clamped in-bounds index and the value is selected afterwards.  (A guarded
+// load per element would put every element in its own basic block, which
+// defeats instruction scheduling and forces register spills.)
+template <typename T>
+__device__ __forceinline__ C<T> ldz(const C<T>* U, int j, int m)
+{
+    const bool ok = unsigned(j) < unsigned(m);  // 0 <= j < m
+    const C<T> v = U[ok ? j : 0];
+    return ok ? v : zero<T>();
+}
+
+// ======================================================================
+// Complex 1D convolution, 1/2 padding rule (Sec. 2.1, fftpadBackward /
+// fftpadForward / cconv): the 2N-padded backward transform splits into two
+// size-N transforms of zeta_{2N}^{rk} f_k (r = 0, 1); their products are
+// transformed forward and recombined as (F_0 + zeta_{2N}^{-k} F_1) / 2N.
+// ======================================================================
+template <typename T, int N, bool ACCG, bool MD>
+__global__ void __launch_bounds__(row_block<T>(N), row_waves<T>(N))
+k_conv1d_complex(RowArgs a)
+{
+    constexpr int E = fft_E<T>(N), G = N / E, GPB = row_GPB<T>(N), LDSN = row_lds<T>(N);
+    __shared__ C<T> sh[GPB * LDSN];
+    const int grp = threadIdx.x / G, t = threadIdx.x % G;
+    const RowCtx c = row_ctx(a, (int64_t)blockIdx.x * GPB + grp);
+    C<T>* lds = sh + grp * LDSN;
+    const C<T>* twb = (const C<T>*)a.tw;
+    const C<T>* twN = twb + tw_off(N);
+    const C<T>* tw2N = twb + tw_off(2 * N);
+    const C<T>* F = (const C<T>*)a.f + c.of;
+    const C<T>* Gp = (const C<T>*)a.g + c.og;
+    C<T>* H = (C<T>*)a.h + c.oh;
+    const bool revf = a.flags & kRevF, cjg = a.flags & kConjG, revo = a.flags & kRevOut;
+    const T s = T(1) / T(2 * N);
+    C<T> acc[ACCG ? 1 : E];
+
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        C<T> P[E];
+        const int64_t nM = MD ? a.M : 1;  // MD = false: single product, no accumulator
+        for (int64_t i = 0; i < nM; ++i) {
+            C<T> x[E], y[E];
+            const int z = opaque_zero();
+            const C<T>* Fz = F + z;
+            const C<T>* Gz = Gp + z;
+            const C<T>* Wz = tw2N + z;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int k = t + e * G;
+                C<T> fv = ldz(Fz + i * a.f_i, revf ? c.m - 1 - k : k, c.m);
+                C<T> gv = ldz(Gz + i * a.g_i, k, c.m);
+                if (cjg) gv = conj(gv);
+                if (r) {
+                    const C<T> w = Wz[k];
+                    fv = fv * w;
+                    gv = gv * w;
+                }
+                x[e] = fv;
+                y[e] = gv;
+            }
+            fft<T, N, E, +1>(x, t, lds, 1, twN);
+            fft<T, N, E, +1>(y, t, lds, 1, twN);
+#pragma unroll
+            for (int e = 0; e < E; ++e) P[e] = (MD && i > 0) ? P[e] + x[e] * y[e] : x[e] * y[e];
+        }
+        fft<T, N, E, -1>(P, t, lds, 1, twN);
+        const C<T>* Wo = tw2N + opaque_zero();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + e * G;
+            const C<T> v = r ? mulc(P[e], Wo[k]) : P[e];
+            if constexpr (ACCG) {
+                if (k < c.m) {
+                    C<T>* hp = H + (revo ? c.m - 1 - k : k);
+                    *hp = r ? *hp + scale(v, s) : scale(v, s);
+                }
+            } else {
+                acc[e] = r ? acc[e] + v : v;
+            }
+        }
+    }
+    if constexpr (!ACCG) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + e * G;
+            if (k < c.m) H[revo ? c.m - 1 - k : k] = scale(acc[e], s);
+        }
+    }
+}
+
+// ======================================================================
+// Plain cyclic convolution of size N (no dealiasing): the building block of
+// the explicitly padded comparator (inputs already zero padded in HBM) and
+// the middle pass of the multi-pass large-N convolutions.
+// h_k = scale * sum_i IFFT(FFT(f_i) FFT(g_i))_k, k < m_out.
+// ======================================================================
+template <typename T, int N>
+__global__ void __launch_bounds__(row_block<T>(N), row_waves<T>(N))
+k_conv1d_cyclic(RowArgs a)
+{
+    constexpr int E = fft_E<T>(N), G = N / E, GPB = row_GPB<T>(N), LDSN = row_lds<T>(N);
+    __shared__ C<T> sh[GPB * LDSN];
+    const int grp = threadIdx.x / G, t = threadIdx.x % G;
+    const RowCtx c = row_ctx(a, (int64_t)blockIdx.x * GPB + grp);
+    C<T>* lds = sh + grp * LDSN;
+    const C<T>* twN = (const C<T>*)a.tw + tw_off(N);
+    const C<T>* F = (const C<T>*)a.f + c.of;
+    const C<T>* Gp = (const C<T>*)a.g + c.og;
+    C<T>* H = (C<T>*)a.h + c.oh;
+    C<T> P[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) P[e] = zero<T>();
+    for (int64_t i = 0; i < a.M; ++i) {
+        C<T> x[E], y[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + e * G;
+            x[e] = ldz(F + i * a.f_i, k, c.m);
+            y[e] = ldz(Gp + i * a.g_i, k, c.m);
+        }
+        fft<T, N, E, +1>(x, t, lds, 1, twN);
+        fft<T, N, E, +1>(y, t, lds, 1, twN);
+#pragma unroll
+        for (int e = 0; e < E; ++e) P[e] = P[e] + x[e] * y[e];
+    }
+    fft<T, N, E, -1>(P, t, lds, 1, twN);
+    const T s = T(a.scale);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = t + e * G;
+        if (c.act && k < a.m_out) H[k] = scale(P[e], s);  // stores may branch
+    }
+}
+
+// Value P_{(n - k) mod n} of the sequence whose position t + e*G this thread
+// holds in P[e]; used by the real-to-complex post-processing, which pairs
+// frequency k with n - k.  Goes through LDS unless one thread holds it all.
+template <typename T, int NC, int E>
+__device__ __forceinline__ void mirror(const C<T> (&P)[E], C<T> (&Pm)[E], int t, C<T>* lds)
+{
+    constexpr int G = NC / E;
+    if constexpr (G == 1) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) Pm[e] = P[(NC - e) & (NC - 1)];
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) lds[lpad(t + e * G)] = P[e];
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) Pm[e] = lds[lpad((NC - (t + e * G)) & (NC - 1))];
+        __syncthreads();
+    }
+}
+
+// Spectrum V_k (k = 0..NC) of a real sequence v of length 2 NC from the
+// size-NC forward FFT P of its packing z_l = v_{2l} + i v_{2l+1}:
+// V_k = (P_k + conj P_{NC-k}) / 2 - i zeta_{2NC}^{-k} (P_k - conj P_{NC-k}) / 2.
+template <typename T>
+__device__ __forceinline__ C<T> r2c_post(C<T> p, C<T> pm, C<T> w2k)
+{
+    const C<T> ev = scale(p + conj(pm), T(0.5));
+    const C<T> od = scale(p - conj(pm), T(0.5));
+    return ev + muli<-1>(mulc(od, w2k));
+}
+
+// Packed input Z_k = (X_k + conj X_{NC-k}) + i zeta_{2NC}^k (X_k - conj X_{NC-k})
+// whose size-NC backward FFT is x_{2l} + i x_{2l+1}, x the length-2NC real
+// backward transform of the Hermitian half X_0..X_NC.
+template <typename T>
+__device__ __forceinline__ C<T> c2r_pre(C<T> xk, C<T> xmk, C<T> w2k)
+{
+    const C<T> cx = conj(xmk);
+    return (xk + cx) + muli<+1>((xk - cx) * w2k);
+}
+
+// ======================================================================
+// Centered Hermitian 1D convolution, 2/3 padding rule (Sec. 2.3).  The input
+// half U_0..U_{N-1} (N = 2 NC >= m, zero beyond m) is implicitly padded to
+// 3N.  For each residue r in {-1, 0, 1} the Hermitian sequence
+//   w_{0,r} = U_0,  w_{k,r} = zeta_{3N}^{rk} (U_k + zeta_3^{-r} conj U_{N-k}),
+// is transformed complex-to-real (packed into one size-NC complex FFT), the
+// real products of the two inputs are transformed real-to-complex, and
+//   3N H_k = sum_r zeta_{3N}^{-rk} V_r(k),  V_r(N-k) = conj V_r(k).
+// ======================================================================
+// zeta_3^{-R} and zeta_6^{-R} for R in {-1, 0, 1}
+template <typename T, int R>
+__device__ __forceinline__ C<T> z3m()
+{
+    const T h = T(0.86602540378443864676);
+    return R == 0 ? C<T>{T(1), T(0)} : (R > 0 ? C<T>{T(-0.5), -h} : C<T>{T(-0.5), h});
+}
+template <typename T, int R>
+__device__ __forceinline__ C<T> z6m()
+{
+    const T h = T(0.86602540378443864676);
+    return R == 0 ? C<T>{T(1), T(0)} : (R > 0 ? C<T>{T(0.5), -h} : C<T>{T(0.5), h});
+}
+
+// zeta_{3N}^{R k}, 0 <= k < N, from the zeta_{3N}^j table
+template <typename T, int R>
+__device__ __forceinline__ C<T> zeta3N(const C<T>* tw3N, int k)
+{
+    if constexpr (R == 0) return C<T>{T(1), T(0)};
+    const C<T> w = tw3N[k];
+    return R > 0 ? w : conj(w);
+}
+
+// Packed c2r input for residue R at frequency k (0 <= k < NC) built from the
+// Hermitian half U (length m, zero beyond).
+template <typename T, int NC, int R, bool MAYBE0>
+__device__ __forceinline__ C<T> herm_Z(const C<T>* U, int m, int k, const C<T>* tw3N,
+                                       const C<T>* tw2NC)
+{
+    constexpr int N = 2 * NC;
+    auto ld = [&](int j) -> C<T> { return ldz(U, j, m); };
+    const C<T> z3 = z3m<T, R>();
+    C<T> wk = zeta3N<T, R>(tw3N, k) * (ld(k) + z3 * conj(ld(N - k)));
+    C<T> wck = zeta3N<T, R>(tw3N, NC - k) * (ld(NC - k) + z3 * conj(ld(NC + k)));
+    if constexpr (MAYBE0) {
+        // k = 0 pairs w_0 = Re U_0 with the real w_NC (Re U_NC -/+ sqrt3 Im U_NC, or 2 Re U_NC)
+        const C<T> u0 = ld(0), uc = ld(NC);
+        const T sq3 = T(1.73205080756887729353);
+        const T vc = R == 0 ? T(2) * uc.re : (R > 0 ? uc.re - sq3 * uc.im : uc.re + sq3 * uc.im);
+        const bool z = k == 0;
+        wk = z ? C<T>{u0.re, T(0)} : wk;
+        wck = z ? C<T>{vc, T(0)} : wck;
+    }
+    return c2r_pre(wk, wck, tw2NC[k]);
+}
+
+// One residue of the Hermitian convolution: 2M c2r transforms, the real
+// products, one r2c transform and the accumulation of its contribution to
+// H_k, H_{N-k} and H_NC.
+template <typename T, int NC, int R, bool ACCG, bool FIRST>
+__device__ __forceinline__ void herm_residue(const RowArgs& a, const RowCtx& c, int m, int t,
+                                             C<T>* lds, C<T> (&alo)[ACCG ? 1 : row_E<T, 1>(NC)],
+                                             C<T> (&ahi)[ACCG ? 1 : row_E<T, 1>(NC)], C<T>& acen)
+{
+    constexpr int N = 2 * NC;
+    constexpr int E = row_E<T, 1>(NC), G = NC / E;
+    const C<T>* twb = (const C<T>*)a.tw;
+    const C<T>* twNC = twb + tw_off(NC);
+    const C<T>* twN = twb + tw_off(N);
+    const C<T>* tw3N = (const C<T>*)a.tw3 + tw_off(N);
+    C<T>* H = (C<T>*)a.h + c.oh;
+    const T s = T(1) / T(3 * N);
+    C<T> P[E];
+    for (int64_t i = 0; i < a.M; ++i) {
+        C<T> x[E], y[E];
+        {
+            const int z = opaque_zero();
+            const C<T>* F = (const C<T>*)a.f + c.of + i * a.f_i + z;
+            static_for<E>([&](auto ec) {
+                constexpr int e = decltype(ec)::value;
+                x[e] = herm_Z<T, NC, R, e == 0>(F, m, t + e * G, tw3N + z, twN + z);
+            });
+        }
+        fft<T, NC, E, +1>(x, t, lds, 1, twNC);
+        {
+            const int z = opaque_zero();
+            const C<T>* Gp = (const C<T>*)a.g + c.og + i * a.g_i + z;
+            static_for<E>([&](auto ec) {
+                constexpr int e = decltype(ec)::value;
+                y[e] = herm_Z<T, NC, R, e == 0>(Gp, m, t + e * G, tw3N + z, twN + z);
+            });
+        }
+        fft<T, NC, E, +1>(y, t, lds, 1, twNC);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const C<T> p{x[e].re * y[e].re, x[e].im * y[e].im};
+            P[e] = i ? P[e] + p : p;
+        }
+    }
+    fft<T, NC, E, -1>(P, t, lds, 1, twNC);
+    C<T> Pm[E];
+    mirror<T, NC, E>(P, Pm, t, lds);
+    const C<T> z3 = z3m<T, R>();
+    const int zo = opaque_zero();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = t + e * G;
+        const C<T> V = r2c_post(P[e], Pm[e], twN[k + zo]);
+        const C<T> wk = zeta3N<T, R>(tw3N + zo, k);
+        const C<T> lo = mulc(V, wk);              // zeta_{3N}^{-Rk} V_R(k)
+        const C<T> hi = z3 * (wk * conj(V));      // zeta_{3N}^{-R(N-k)} conj V_R(k)
+        if constexpr (ACCG) {
+            if (k < m) H[k] = FIRST ? scale(lo, s) : H[k] + scale(lo, s);
+            if (k > 0 && N - k < m) H[N - k] = FIRST ? scale(hi, s) : H[N - k] + scale(hi, s);
+        } else {
+            alo[e] = FIRST ? lo : alo[e] + lo;
+            ahi[e] = FIRST ? hi : ahi[e] + hi;
+        }
+        if (e == 0 && k == 0) {
+            // V_R(NC) = Re P_0 - Im P_0 enters H_NC with zeta_{3N}^{-R NC} = zeta_6^{-R}
+            const C<T> cen = z6m<T, R>() * C<T>{P[e].re - P[e].im, T(0)};
+            if constexpr (ACCG) {
+                if (NC < m) H[NC] = FIRST ? scale(cen, s) : H[NC] + scale(cen, s);
+            } else {
+                acen = FIRST ? cen : acen + cen;
+            }
+        }
+    }
+}
+
+// ======================================================================
+// Centered Hermitian 1D convolution, 2/3 padding rule (Sec. 2.3).  The input
+// half U_0..U_{N-1} (N = 2 NC >= m, zero beyond m) is implicitly padded to
+// 3N.  For each residue r in {-1, 0, 1} the Hermitian sequence
+//   w_{0,r} = U_0,  w_{k,r} = zeta_{3N}^{rk} (U_k + zeta_3^{-r} conj U_{N-k}),
+// is transformed complex-to-real (packed into one size-NC complex FFT), the
+// real products of the two inputs are transformed real-to-complex, and
+//   3N H_k = sum_r zeta_{3N}^{-rk} V_r(k),  V_r(N-k) = conj V_r(k).
+// ======================================================================
+template <typename T, int NC, bool ACCG>
+__global__ void __launch_bounds__((row_block<T, 1>(NC)), row_waves<T>(NC))
+k_conv1d_hermitian(RowArgs a)
+{
+    constexpr int N = 2 * NC;
+    constexpr int E = row_E<T, 1>(NC), G = NC / E, GPB = row_GPB<T, 1>(NC), LDSN = row_lds<T, 1>(NC);
+    __shared__ C<T> sh[GPB * LDSN];
+    const int grp = threadIdx.x / G, t = threadIdx.x % G;
+    const RowCtx c = row_ctx(a, (int64_t)blockIdx.x * GPB + grp);
+    C<T>* lds = sh + grp * LDSN;
+    const int m = c.m;
+    C<T> alo[ACCG ? 1 : E], ahi[ACCG ? 1 : E], acen = zero<T>();
+    herm_residue<T, NC, 0, ACCG, true>(a, c, m, t, lds, alo, ahi, acen);
+    herm_residue<T, NC, 1, ACCG, false>(a, c, m, t, lds, alo, ahi, acen);
+    herm_residue<T, NC, -1, ACCG, false>(a, c, m, t, lds, alo, ahi, acen);
+    if constexpr (!ACCG) {
+        C<T>* H = (C<T>*)a.h + c.oh;
+        const T s = T(1) / T(3 * N);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + e * G;
+            if (k < m) H[k] = scale(alo[e], s);
+            if (k > 0 && N - k < m) H[N - k] = scale(ahi[e], s);
+        }
+        if (t == 0 && NC < m) H[NC] = scale(acen, s);
+    }
+    if (c.act) {
+        C<T>* H = (C<T>*)a.h + c.oh;
+        for (int64_t j = m + t; j < a.h_pad; j += G) H[j] = zero<T>();
+    }
+}
+
+// ======================================================================
+// Centered Hermitian ternary convolution (Sec. 4.2, tconv).  With the input
+// half U_0..U_{N-1} (N >= m) padded to Fourier size 4N: for r in {0, 1} the
+// sequence {zeta_{4N}^{rk} U_k : k = 0..N}, U_N = 0, is transformed
+// complex-to-real at length 2N, the three real transforms are multiplied,
+// transformed back, and 4N H_k = sum_r zeta_{4N}^{-rk} V_r(k).
+// ======================================================================
+template <typename T, int NN, int R>
+__device__ __forceinline__ C<T> tern_Z(const C<T>* U, int m, int k, const C<T>* tw4N,
+                                       const C<T>* tw2N)
+{
+    auto X = [&](int j) -> C<T> {  // zeta_{4N}^{Rj} U_j for 0 <= j <= N (U_N = 0)
+        C<T> u = ldz(U, j, m < NN ? m : NN);
+        if (j == 0) u.im = T(0);
+        if constexpr (R != 0) u = u * tw4N[j & (NN - 1)];
+        return u;
+    };
+    return c2r_pre(X(k), X(NN - k), tw2N[k]);
+}
+
+template <typename T, int NN, int R>
+__device__ __forceinline__ void tern_load(const void* base, int64_t off, int m, int t,
+                                          const RowArgs& a, C<T> (&x)[row_E<T, 1>(NN)])
+{
+    constexpr int E = row_E<T, 1>(NN), G = NN / E;
+    const int q = opaque_zero();
+    const C<T>* twb = (const C<T>*)a.tw;
+    const C<T>* U = (const C<T>*)base + off + q;
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        x[e] = tern_Z<T, NN, R>(U, m, t + e * G, twb + tw_off(4 * NN) + q, twb + tw_off(2 * NN) + q);
+}
+
+template <typename T, int NN, int R, bool ACCG>
+__device__ __forceinline__ void tern_residue(const RowArgs& a, const RowCtx& c, int m, int t,
+                                             C<T>* lds, C<T> (&acc)[ACCG ? 1 : row_E<T, 1>(NN)])
+{
+    constexpr int E = row_E<T, 1>(NN), G = NN / E;
+    const C<T>* twb = (const C<T>*)a.tw;
+    const C<T>* twNN = twb + tw_off(NN);
+    C<T>* H = (C<T>*)a.h + c.oh;
+    const T s = T(1) / T(4 * NN);
+    C<T> x[E], y[E];
+    tern_load<T, NN, R>(a.f, c.of, m, t, a, x);
+    fft<T, NN, E, +1>(x, t, lds, 1, twNN);
+    tern_load<T, NN, R>(a.g, c.og, m, t, a, y);
+    fft<T, NN, E, +1>(y, t, lds, 1, twNN);
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[e] = C<T>{x[e].re * y[e].re, x[e].im * y[e].im};
+    tern_load<T, NN, R>(a.e, c.oe, m, t, a, y);
+    fft<T, NN, E, +1>(y, t, lds, 1, twNN);
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[e] = C<T>{x[e].re * y[e].re, x[e].im * y[e].im};
+    fft<T, NN, E, -1>(x, t, lds, 1, twNN);
+    mirror<T, NN, E>(x, y, t, lds);
+    const int qo = opaque_zero();
+    const C<T>* tw2N = twb + tw_off(2 * NN) + qo;
+    const C<T>* tw4N = twb + tw_off(4 * NN) + qo;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = t + e * G;
+        C<T> V = r2c_post(x[e], y[e], tw2N[k]);
+        if constexpr (R != 0) V = mulc(V, tw4N[k]);
+        if constexpr (ACCG) {
+            if (k < m) H[k] = R == 0 ? scale(V, s) : H[k] + scale(V, s);
+        } else {
+            acc[e] = R == 0 ? V : acc[e] + V;
+        }
+    }
+}
+
+// ======================================================================
+// Centered Hermitian ternary convolution (Sec. 4.2, tconv).  With the input
+// half U_0..U_{N-1} (N >= m) padded to Fourier size 4N: for r in {0, 1} the
+// sequence {zeta_{4N}^{rk} U_k : k = 0..N}, U_N = 0, is transformed
+// complex-to-real at length 2N, the three real transforms are multiplied,
+// transformed back, and 4N H_k = sum_r zeta_{4N}^{-rk} V_r(k).
+// ======================================================================
+template <typename T, int NN, bool ACCG>
+__global__ void __launch_bounds__((row_block<T, 1>(NN)), row_waves<T>(NN))
+k_conv1d_ternary(RowArgs a)
+{
+    constexpr int E = row_E<T, 1>(NN), G = NN / E, GPB = row_GPB<T, 1>(NN), LDSN = row_lds<T, 1>(NN);
+    __shared__ C<T> sh[GPB * LDSN];
+    const int grp = threadIdx.x / G, t = threadIdx.x % G;
+    const RowCtx c = row_ctx(a, (int64_t)blockIdx.x * GPB + grp);
+    C<T>* lds = sh + grp * LDSN;
+    const int m = c.m;
+    C<T> acc[ACCG ? 1 : E];
+    tern_residue<T, NN, 0, ACCG>(a, c, m, t, lds, acc);
+    tern_residue<T, NN, 1, ACCG>(a, c, m, t, lds, acc);
+    if constexpr (!ACCG) {
+        C<T>* H = (C<T>*)a.h + c.oh;
+        const T s = T(1) / T(4 * NN);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + e * G;
+            if (k < m) H[k] = scale(acc[e], s);
+        }
+    }
+}
+
+}  // namespace impconv
+
+namespace impconv {
+
+// ======================================================================
+// Plain cyclic convolution of two real sequences of length 2 NC given by
+// their half spectra X_0..X_NC (rows of length >= NC + 1): the explicitly
+// padded centered Hermitian comparator (2/3 rule with materialized padding).
+// h_k = scale * r2c(c2r(f) c2r(g))_k, k < m_out.
+// ======================================================================
+template <typename T, int NC>
+__global__ void __launch_bounds__((row_block<T, 1>(NC)), row_waves<T>(NC))
+k_conv1d_realcyclic(RowArgs a)
+{
+    constexpr int E = row_E<T, 1>(NC), G = NC / E, GPB = row_GPB<T, 1>(NC), LDSN = row_lds<T, 1>(NC);
+    __shared__ C<T> sh[GPB * LDSN];
+    const int grp = threadIdx.x / G, t = threadIdx.x % G;
+    const RowCtx c = row_ctx(a, (int64_t)blockIdx.x * GPB + grp);
+    C<T>* lds = sh + grp * LDSN;
+    const C<T>* twb = (const C<T>*)a.tw;
+    const C<T>* twNC = twb + tw_off(NC);
+    const C<T>* tw2 = twb + tw_off(2 * NC);
+    const int m = c.m;
+    C<T> P[E];
+    for (int64_t i = 0; i < a.M; ++i) {
+        C<T> x[E], y[E];
+        {
+            const int z = opaque_zero();
+            const C<T>* F = (const C<T>*)a.f + c.of + i * a.f_i + z;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int k = t + e * G;
+                C<T> xk = ldz(F, k, m), xm = ldz(F, NC - k, m);
+                if (k == 0) xk.im = T(0);
+                x[e] = c2r_pre(xk, xm, tw2[k + z]);
+            }
+        }
+        fft<T, NC, E, +1>(x, t, lds, 1, twNC);
+        {
+            const int z = opaque_zero();
+            const C<T>* Gp = (const C<T>*)a.g + c.og + i * a.g_i + z;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int k = t + e * G;
+                C<T> xk = ldz(Gp, k, m), xm = ldz(Gp, NC - k, m);
+                if (k == 0) xk.im = T(0);
+                y[e] = c2r_pre(xk, xm, tw2[k + z]);
+            }
+        }
+        fft<T, NC, E, +1>(y, t, lds, 1, twNC);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const C<T> p{x[e].re * y[e].re, x[e].im * y[e].im};
+            P[e] = i ? P[e] + p : p;
+        }
+    }
+    fft<T, NC, E, -1>(P, t, lds, 1, twNC);
+    C<T> Pm[E];
+    mirror<T, NC, E>(P, Pm, t, lds);
+    C<T>* H = (C<T>*)a.h + c.oh;
+    const T s = T(a.scale);
+    const int zo = opaque_zero();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = t + e * G;
+        if (c.act && k < a.m_out) H[k] = scale(r2c_post(P[e], Pm[e], tw2[k + zo]), s);
+    }
+}
+
+// dst[r][j] = j < copy ? src[r][j] : 0 for j < dst_ld (zero padding or crop).
+template <typename T>
+__global__ void k_pad_rows(const C<T>* __restrict__ src, C<T>* __restrict__ dst, int64_t nrows,
+                           int64_t src_ld, int64_t copy, int64_t dst_ld)
+{
+    const int64_t total = nrows * dst_ld;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / dst_ld, j = i - r * dst_ld;
+        dst[i] = j < copy ? src[r * src_ld + j] : zero<T>();
+    }
+}
+
+}  // namespace impconv

@@ -1,0 +1,45 @@
+// runtime.hpp -- host-side internals shared by the C ABI and the kernel
+// launch units: per-device twiddle tables, error reporting, launch helpers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "../../include/impconv.h"
+
+namespace impconv {
+
+// Largest power-of-two FFT table (zeta_N^j, N <= 2^kTwLog) and largest N of
+// the zeta_{3N}^j tables.
+constexpr int kTwLog = 18;
+constexpr int kTw3Log = 16;
+
+struct DevTables {
+    const void* tw[2];   // [0] complex64, [1] complex128: concatenated zeta_N^j, offset N - 1
+    const void* tw3[2];  // concatenated zeta_{3N}^j (j < N), offset N - 1
+};
+
+// Tables of the current device, created on first use (FP64 on the host,
+// rounded to FP32 for the complex64 copy).  Returns nullptr on HIP failure.
+const DevTables* tables();
+
+// FP64 host generation, exposed for the host-side unit test.
+void gen_roots(int64_t denom, int64_t count, double* out_re_im);
+
+impconv_status fail(impconv_status st, const std::string& msg);
+impconv_status hip_fail(hipError_t e, const char* what);
+
+inline int64_t next_pow2(int64_t x)
+{
+    int64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+inline int ilog2(int64_t x)
+{
+    int l = 0;
+    while ((int64_t(1) << l) < x) ++l;
+    return l;
+}
+
+}  // namespace impconv

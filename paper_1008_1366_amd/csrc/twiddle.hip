@@ -1,0 +1,109 @@
+// twiddle.cpp -- FP64 roots of unity for the FFT stages and the residue
+// shifts (Sec. 2.1 discussion of the zeta_N^k factors).  The paper builds
+// them from two short tables with one complex multiply; on the GPU the full
+// per-size tables cost only ~12 MB of HBM and one cached load per use, so
+// they are stored directly: tw_N[j] = zeta_N^j for every power-of-two N up to
+// 2^18 (concatenated, tw_N at offset N - 1) and zeta_{3N}^j, j < N, for the
+// 2/3-rule shifts.  Each value is computed in long double with the argument
+// reduced exactly (integer j mod denom, folded into the first octant) and
+// rounded once to double; the complex64 tables round those doubles to float.
+#include <cmath>
+#include <mutex>
+#include <vector>
+
+#include "cx.hpp"
+#include "runtime.hpp"
+
+namespace impconv {
+
+// zeta_denom^j = exp(2 pi i j / denom) for j = 0..count-1, FP64, interleaved.
+void gen_roots(int64_t denom, int64_t count, double* out)
+{
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    for (int64_t j = 0; j < count; ++j) {
+        // exact reduction in units of 1/(8 denom) of a turn: P = 8 (j mod denom),
+        // quadrant q = P / (2 denom), angle = q pi/2 + 2 pi b / (8 denom)
+        const int64_t D = 8 * denom;
+        const int64_t P = 8 * (j % denom);
+        const int64_t q = P / (2 * denom);
+        const int64_t b = P - q * 2 * denom;
+        long double c, s;
+        if (b <= denom) {  // within the first octant of the quadrant
+            long double th = two_pi * (long double)b / (long double)D;
+            c = cosl(th);
+            s = sinl(th);
+        } else {  // use complement: angle' = pi/2 - angle
+            long double th = two_pi * (long double)(2 * denom - b) / (long double)D;
+            c = sinl(th);
+            s = cosl(th);
+        }
+        long double re, im;
+        switch (q & 3) {
+            case 0: re = c; im = s; break;
+            case 1: re = -s; im = c; break;
+            case 2: re = -c; im = -s; break;
+            default: re = s; im = -c; break;
+        }
+        out[2 * j] = (double)re;
+        out[2 * j + 1] = (double)im;
+    }
+}
+
+namespace {
+
+std::mutex g_mu;
+DevTables g_tab[64];
+bool g_have[64];
+
+template <typename T>
+hipError_t upload(const std::vector<double>& src, const void** dst)
+{
+    const size_t n = src.size() / 2;
+    std::vector<C<T>> host(n);
+    for (size_t i = 0; i < n; ++i) host[i] = C<T>{(T)src[2 * i], (T)src[2 * i + 1]};
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, n * sizeof(C<T>));
+    if (e != hipSuccess) return e;
+    e = hipMemcpy(p, host.data(), n * sizeof(C<T>), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { (void)hipFree(p); return e; }
+    *dst = p;
+    return hipSuccess;
+}
+
+}  // namespace
+
+const DevTables* tables()
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= 64) {
+        hip_fail(e == hipSuccess ? hipErrorInvalidDevice : e, "hipGetDevice");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_have[dev]) return &g_tab[dev];
+    // zeta_N^j for N = 2^0 .. 2^kTwLog, concatenated at offset N - 1
+    std::vector<double> tw(2 * ((int64_t(1) << (kTwLog + 1)) - 1));
+    for (int l = 0; l <= kTwLog; ++l) {
+        const int64_t N = int64_t(1) << l;
+        gen_roots(N, N, tw.data() + 2 * (N - 1));
+    }
+    std::vector<double> tw3(2 * ((int64_t(1) << (kTw3Log + 1)) - 1));
+    for (int l = 0; l <= kTw3Log; ++l) {
+        const int64_t N = int64_t(1) << l;
+        gen_roots(3 * N, N, tw3.data() + 2 * (N - 1));
+    }
+    DevTables t{};
+    if ((e = upload<float>(tw, &t.tw[0])) != hipSuccess ||
+        (e = upload<double>(tw, &t.tw[1])) != hipSuccess ||
+        (e = upload<float>(tw3, &t.tw3[0])) != hipSuccess ||
+        (e = upload<double>(tw3, &t.tw3[1])) != hipSuccess) {
+        hip_fail(e, "twiddle table upload");
+        return nullptr;
+    }
+    g_tab[dev] = t;
+    g_have[dev] = true;
+    return &g_tab[dev];
+}
+
+}  // namespace impconv

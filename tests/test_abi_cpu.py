@@ -1,0 +1,109 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol include/impconv.h declares, and rejects bad arguments before
+touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "impconv.h")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(impconv_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_1008_1366_amd as ic
+    if not os.path.exists(ic.LIB_PATH):
+        pytest.skip("libimpconv.so not built")
+    return ic.lib()
+
+
+def test_header_declares_entry_points():
+    names = declared()
+    for n in ["impconv_conv1d_complex", "impconv_conv1d_hermitian", "impconv_conv1d_ternary",
+              "impconv_conv2d", "impconv_conv3d", "impconv_ragged_execute"]:
+        assert n in names
+
+
+def test_all_declared_symbols_exported(L):
+    lib = ctypes.CDLL(L._name)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings(L):
+    assert L.impconv_status_string(0) == b"ok"
+    assert L.impconv_status_string(3) == b"workspace too small"
+    assert L.impconv_version() >= 10000
+
+
+def ws(L, kind, dt, batch, M, m, flags=0):
+    out = ctypes.c_size_t(123)
+    st = L.impconv_conv1d_workspace(kind, dt, batch, M, m, flags, ctypes.byref(out))
+    return st, out.value
+
+
+def test_workspace_query_and_size_errors(L):
+    assert ws(L, 0, 0, 4, 1, 1024) == (0, 0)           # fused: no workspace
+    st, b = ws(L, 0, 0, 2, 1, 16384)                   # four-step: 4 residue arrays
+    assert st == 0 and b == 4 * 2 * 16384 * 8
+    st, b = ws(L, 0, 1, 3, 2, 100, 1)                  # explicit comparator: padded copies
+    assert st == 0 and b == 3 * (2 * 2 + 1) * 256 * 16
+    assert ws(L, 0, 0, 1, 1, 0)[0] == 2                # m < 1
+    assert ws(L, 0, 0, -1, 1, 8)[0] == 2               # batch < 0
+    assert ws(L, 0, 0, 1, 0, 8)[0] == 2                # M < 1
+    assert ws(L, 0, 7, 1, 1, 8)[0] == 1                # bad dtype
+    assert ws(L, 5, 0, 1, 1, 8)[0] == 1                # bad kind
+    assert ws(L, 1, 0, 1, 1, 8, 2)[0] == 1             # REV flag on Hermitian
+    assert ws(L, 0, 0, 1, 1, 1 << 20)[0] == 5          # beyond the four-step range
+    assert ws(L, 1, 0, 1, 1, 16384)[0] == 0
+    assert ws(L, 1, 0, 1, 1, 16385)[0] == 5
+
+
+def test_call_errors_before_launch(L):
+    c = ctypes.c_void_p
+    # null pointers are rejected before any device work
+    assert L.impconv_conv1d_complex(0, 1, 1, 8, None, None, None, None, 0, 0, None) == 1
+    # misaligned pointer
+    assert L.impconv_conv1d_complex(0, 1, 1, 8, c(8), c(4099), c(1 << 20), None, 0, 0, None) == 4
+    # h overlapping f
+    assert L.impconv_conv1d_complex(0, 1, 1, 8, c(1 << 20), c(1 << 24), c((1 << 20) + 16), None, 0, 0, None) == 1
+    # undersized workspace (explicit comparator needs one)
+    assert L.impconv_conv1d_complex(0, 1, 1, 8, c(1 << 20), c(1 << 24), c(1 << 26), c(1 << 28), 8, 1, None) == 3
+    assert b"workspace" in L.impconv_last_error()
+
+
+def test_nd_workspace_and_errors(L):
+    m = (ctypes.c_int64 * 2)(2048, 2048)
+    out = ctypes.c_size_t()
+    assert L.impconv_convnd_workspace(0, 0, 2, m, m, 8, 1, 0, ctypes.byref(out)) == 0
+    assert out.value == 2 * 2 * 8 * 2048 * 2048 * 8      # f and g residue arrays
+    n = (ctypes.c_int64 * 2)(2048, 2047)
+    assert L.impconv_convnd_workspace(0, 0, 2, m, n, 8, 1, 0, ctypes.byref(out)) == 2
+    mh = (ctypes.c_int64 * 3)(256, 256, 256)
+    nh = (ctypes.c_int64 * 3)(512, 512, 257)
+    assert L.impconv_convnd_workspace(1, 0, 3, mh, nh, 1, 3, 0, ctypes.byref(out)) == 0
+    nb = (ctypes.c_int64 * 3)(512, 511, 258)
+    assert L.impconv_convnd_workspace(1, 0, 3, mh, nb, 1, 3, 0, ctypes.byref(out)) == 2
+    assert L.impconv_convnd_workspace(1, 0, 4, mh, nh, 1, 3, 0, ctypes.byref(out)) == 1
+
+
+def test_ragged_plan_validation(L):
+    import numpy as np
+    p = ctypes.c_void_p()
+    ms = np.array([4, 8], np.int64)
+    offs = np.array([0, 2], np.int64)  # overlapping spans
+    st = L.impconv_ragged_plan_create(0, 2, ms.ctypes.data_as(ctypes.c_void_p),
+                                      offs.ctypes.data_as(ctypes.c_void_p), ctypes.byref(p))
+    assert st == 1
+    ms0 = np.array([0], np.int64)
+    st = L.impconv_ragged_plan_create(0, 1, ms0.ctypes.data_as(ctypes.c_void_p),
+                                      offs.ctypes.data_as(ctypes.c_void_p), ctypes.byref(p))
+    assert st == 2

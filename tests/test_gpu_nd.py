@@ -1,0 +1,134 @@
+"""GPU parity of the 2D / 3D entry points against the FP64 oracle: full fields
+on small grids spanning several tiles and ragged sizes, the 2048^2 complex
+batch-of-8 workload (sampled outputs plus an exact full-field separability
+check) and the 512x512x257 centered Hermitian M=3 workload (sampled)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import TOL, need_gpu, rel, rounded, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+DT = [np.complex128, np.complex64]
+
+
+@pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("shape", [(1, 1), (3, 5), (16, 16), (33, 20), (64, 130), (200, 9)])
+def test_complex_2d(dt, shape):
+    ic = need_gpu()
+    say(f"complex2d {shape} {dt.__name__}")
+    B, M = 2, 2
+    f = synth.unit_disk((B, M, *shape), 61)
+    g = synth.unit_disk((B, M, *shape), 62)
+    h = ic.conv2d(to_dev(f, dt), to_dev(g, dt)).cpu().numpy()
+    for b in range(B):
+        ref = oracle.convnd_complex_M(rounded(f[b], dt), rounded(g[b], dt))
+        assert rel(h[b], ref) < TOL[dt]
+
+
+@pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("shape", [(2, 3, 4), (8, 8, 8), (5, 17, 9)])
+def test_complex_3d(dt, shape):
+    ic = need_gpu()
+    say(f"complex3d {shape} {dt.__name__}")
+    M = 2
+    f = synth.unit_disk((1, M, *shape), 63)
+    g = synth.unit_disk((1, M, *shape), 64)
+    h = ic.conv3d(to_dev(f, dt), to_dev(g, dt)).cpu().numpy()
+    ref = oracle.convnd_complex_M(rounded(f[0], dt), rounded(g[0], dt))
+    assert rel(h[0], ref) < TOL[dt]
+
+
+def herm_input(m, n, seed, M=None):
+    shape = n if M is None else (M, *n)
+    u = synth.unit_disk(shape, seed)
+    return u
+
+
+@pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("m,n", [((1, 1), (1, 1)), ((2, 2), (4, 3)), ((5, 6), (9, 6)),
+                                 ((16, 16), (32, 17)), ((17, 40), (33, 41)), ((40, 7), (80, 7))])
+def test_hermitian_2d(dt, m, n):
+    ic = need_gpu()
+    say(f"hermitian2d m={m} n={n} {dt.__name__}")
+    M = 2
+    f, g = herm_input(m, n, 65, M), herm_input(m, n, 66, M)
+    h = ic.conv2d(to_dev(f[None], dt), to_dev(g[None], dt), kind="hermitian", m=m).cpu().numpy()[0]
+    ref = oracle.convnd_hermitian(rounded(f, dt), rounded(g, dt), m)
+    assert rel(h, ref) < TOL[dt]
+    # zero slots are written as exact zeros
+    if n[0] == 2 * m[0]:
+        assert np.all(h[0] == 0)
+    if n[1] == m[1] + 1:
+        assert np.all(h[:, m[1]] == 0)
+
+
+def test_hermitian_2d_no_symmetrize_projection():
+    ic = need_gpu()
+    m, n = (9, 8), (17, 9)
+    f, g = herm_input(m, n, 67), herm_input(m, n, 68)
+    h = ic.conv2d(to_dev(f, np.complex128), to_dev(g, np.complex128), kind="hermitian", m=m,
+                  symmetrize=False).cpu().numpy()
+    ref = oracle.convnd_hermitian(f, g, m, symmetrize=False)
+    assert rel(h, ref) < 1e-12
+
+
+@pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("m,n", [((2, 2, 2), (4, 4, 3)), ((4, 3, 5), (7, 6, 5)), ((8, 8, 8), (16, 16, 9)),
+                                 ((5, 9, 6), (10, 17, 7))])
+def test_hermitian_3d(dt, m, n):
+    ic = need_gpu()
+    say(f"hermitian3d m={m} n={n} {dt.__name__}")
+    M = 3
+    f, g = herm_input(m, n, 69, M), herm_input(m, n, 70, M)
+    h = ic.conv3d(to_dev(f[None], dt), to_dev(g[None], dt), kind="hermitian", m=m).cpu().numpy()[0]
+    ref = oracle.convnd_hermitian(rounded(f, dt), rounded(g, dt), m)
+    assert rel(h, ref) < TOL[dt]
+
+
+@pytest.mark.parametrize("dt", DT)
+def test_complex_2d_c3_workload(dt):
+    """2048^2, batch of 8 independent pairs in one call; (1+|k|^2)^-1 Gaussian
+    spectra; sampled outputs vs the oracle, plus one rank-1 pair checked on
+    the full field against outer products of 1D oracle results."""
+    ic = need_gpu()
+    say(f"complex2d C3 {dt.__name__}")
+    mx = my = 2048
+    B = 8
+    f = np.stack([synth.gaussian_2d(mx, my, 100 + 2 * b) for b in range(B)])
+    g = np.stack([synth.gaussian_2d(mx, my, 101 + 2 * b) for b in range(B)])
+    a, bb, c, d = (synth.unit_disk(2048, s) for s in (90, 91, 92, 93))
+    f[B - 1] = np.outer(a, bb)
+    g[B - 1] = np.outer(c, d)
+    h = ic.conv2d(to_dev(f, dt), to_dev(g, dt)).cpu().numpy()
+    rng = synth.rng(5)
+    pts = np.concatenate([[[0, 0], [mx - 1, my - 1], [1, 2047], [2047, 0]], rng.integers(0, mx, (12, 2))])
+    for b in range(0, B - 1, 3):
+        ref = oracle.convnd_complex_at(rounded(f[b], dt), rounded(g[b], dt), pts)
+        assert rel(h[b][pts[:, 0], pts[:, 1]], ref) < TOL[dt], b
+    full = np.outer(oracle.conv1d_complex(rounded(a, dt) if dt == np.complex128 else a, c),
+                    oracle.conv1d_complex(bb, d))
+    if dt == np.complex128:
+        assert rel(h[B - 1], full) < TOL[dt]
+    else:
+        ref = oracle.convnd_complex_at(rounded(f[B - 1], dt), rounded(g[B - 1], dt), pts)
+        assert rel(h[B - 1][pts[:, 0], pts[:, 1]], ref) < TOL[dt]
+
+
+@pytest.mark.parametrize("dt", DT)
+def test_hermitian_3d_c4_workload(dt):
+    """512 x 512 x 257 storage (m = 256 per axis, zero slots), M = 3 pairs,
+    |k|^-11/6 random-phase spectra; sampled outputs vs the oracle."""
+    ic = need_gpu()
+    say(f"hermitian3d C4 {dt.__name__}")
+    m, n = (256, 256, 256), (512, 512, 257)
+    f = np.stack([synth.power_spectrum_centered(m, n, 11 / 6, 200 + i) for i in range(3)])
+    g = np.stack([synth.power_spectrum_centered(m, n, 11 / 6, 203 + i) for i in range(3)])
+    h = ic.conv3d(to_dev(f[None], dt), to_dev(g[None], dt), kind="hermitian", m=m).cpu().numpy()[0]
+    pts = np.array([[0, 0, 0], [255, 255, 255], [-255, 0, 3], [5, -7, 0], [-3, -250, 128], [100, 100, 200]])
+    ref = oracle.convnd_hermitian_at(rounded(f, dt), rounded(g, dt), m, pts)
+    got = h[pts[:, 0] + 256, pts[:, 1] + 256, pts[:, 2]]
+    assert rel(got, ref) < TOL[dt]
+    assert np.all(h[0] == 0) and np.all(h[:, 0] == 0) and np.all(h[:, :, 256] == 0)

@@ -393,3 +393,22 @@ def test_hermitian_nd_sampled(orc):
     assert rel(got, ref) < TOL
     h0 = orc.convnd_hermitian(f[0], g[0], m) + orc.convnd_hermitian(f[1], g[1], m)
     assert rel(h, h0) < TOL
+
+
+def test_ternary_sampled_matches_full(orc):
+    m = 19
+    f, g, e = rnd(m, 71), rnd(m, 72), rnd(m, 73)
+    h = orc.conv1d_ternary(f, g, e)
+    ks = [0, 5, 18]
+    assert rel(orc.conv1d_ternary_at(f, g, e, ks), h[ks]) < TOL
+
+
+def test_nd_sampled_1d_forms(orc):
+    """The sampled nD routines restricted to one axis agree with numpy."""
+    m = 40
+    f, g = rnd(m, 74), rnd(m, 75)
+    ks = np.array([[0], [17], [39]])
+    assert rel(orc.convnd_complex_at(f, g, ks), np.convolve(f, g)[ks[:, 0]]) < TOL
+    full = np.convolve(herm_full_np(f), herm_full_np(g))
+    ref = full[2 * (m - 1) + ks[:, 0]]
+    assert rel(orc.convnd_hermitian_at(f, g, (m,), ks), ref) < TOL
