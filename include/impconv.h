@@ -126,6 +126,15 @@ impconv_status impconv_conv1d_ternary(int dtype, int64_t batch, int64_t m, const
                                       const void* g, const void* e, void* h, void* work,
                                       size_t work_bytes, uint32_t flags, void* stream);
 
+/* Profiling mode (off by default; not for use under stream capture): when
+ * enabled, every kernel launch of the library is bracketed by two hipEvents
+ * on its stream.  impconv_timing_report waits for them, writes a JSON array
+ * of per-kernel aggregates {"name","count","total_ms","min_ms","max_ms"} to
+ * buf (NUL-terminated, truncated to cap bytes), clears the records and
+ * returns the length of the full report. */
+void impconv_timing_enable(int on);
+size_t impconv_timing_report(char* buf, size_t cap);
+
 /* ----------------------------------------------------------------------
  * 2D / 3D convolutions (Secs. 3.1-3.4).  m[d] = logical modes per axis,
  * n[d] = storage extent per axis.  f, g are [batch][M][n0][n1](...[n2]),
@@ -148,8 +157,11 @@ impconv_status impconv_conv1d_ternary(int dtype, int64_t batch, int64_t m, const
  *                      Hermitian projection (U_k + conj U_{-k}) / 2 instead
  *                      (identical for already-symmetric input).  Zero slots
  *                      of h are written as 0.
- * Multidimensional Hermitian convolutions require m[d] <= 4096 per axis in
- * this build; complex ones m[d] <= 8192.
+ * IMPCONV_EXPLICIT_PADDED (2D complex only): the conventional comparator --
+ * inputs copied into zero-padded 2N0 x 2N1 work arrays, full-size FFTs along
+ * both axes, product, inverse, crop (m[d] <= 2048).
+ * Outer axes support m[d] <= 4096 in this build; the innermost axis
+ * m <= 8192 (complex) or m <= 16384 (Hermitian).
  * ---------------------------------------------------------------------- */
 impconv_status impconv_convnd_workspace(int kind, int dtype, int ndim, const int64_t* m,
                                         const int64_t* n, int64_t batch, int64_t M,

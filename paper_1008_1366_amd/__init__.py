@@ -26,6 +26,7 @@ import torch
 __all__ = [
     "lib", "available", "ImpconvError", "conv1d_complex", "conv1d_hermitian", "conv1d_ternary",
     "conv2d", "conv3d", "RaggedPlan", "conv1d_complex_ad", "ragged_conv_ad", "workspace_bytes",
+    "timing_enable", "timing_report",
     "EXPLICIT_PADDED", "REV_F", "CONJ_G", "REV_OUT", "NO_SYMMETRIZE",
 ]
 
@@ -83,6 +84,8 @@ def lib():
             "impconv_ragged_workspace": ([_p, ctypes.POINTER(_sz)], st),
             "impconv_ragged_execute": ([_p, _p, _p, _p, _p, _sz, _u32, _p], st),
             "impconv_ragged_plan_destroy": ([_p], st),
+            "impconv_timing_enable": ([ctypes.c_int], None),
+            "impconv_timing_report": ([ctypes.c_char_p, _sz], _sz),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -236,15 +239,37 @@ def _convnd(nd: int, f, g, kind: str, m, flags: int):
     return h.view(*n) if len(lead) == 0 else h
 
 
-def conv2d(f, g, kind: str = "complex", m=None, symmetrize: bool = True):
+def conv2d(f, g, kind: str = "complex", m=None, symmetrize: bool = True, method: str = "implicit"):
     """2D convolution (Secs. 3.1 / 3.2); inputs (n0, n1), (B, n0, n1) or
-    (B, M, n0, n1); Hermitian needs m = (m0, m1)."""
-    return _convnd(2, f, g, kind, m, 0 if symmetrize else NO_SYMMETRIZE)
+    (B, M, n0, n1); Hermitian needs m = (m0, m1).  method="explicit" runs the
+    explicitly zero-padded comparator (complex only)."""
+    flags = 0 if symmetrize else NO_SYMMETRIZE
+    if method == "explicit":
+        flags |= EXPLICIT_PADDED
+    elif method != "implicit":
+        raise ValueError("method must be 'implicit' or 'explicit'")
+    return _convnd(2, f, g, kind, m, flags)
 
 
 def conv3d(f, g, kind: str = "complex", m=None, symmetrize: bool = True):
     """3D convolution (Sec. 3.4); inputs (n0, n1, n2), (B, ...) or (B, M, ...)."""
     return _convnd(3, f, g, kind, m, 0 if symmetrize else NO_SYMMETRIZE)
+
+
+def timing_enable(on: bool = True) -> None:
+    """Bracket every library kernel launch with hipEvents (profiling mode)."""
+    lib().impconv_timing_enable(1 if on else 0)
+
+
+def timing_report() -> list:
+    """Per-kernel aggregates since the last report (waits for the events)."""
+    import json
+    cap = 1 << 20
+    buf = ctypes.create_string_buffer(cap)
+    n = lib().impconv_timing_report(buf, cap)
+    if n >= cap:
+        raise RuntimeError("timing report truncated")
+    return json.loads(buf.value.decode() or "[]")
 
 
 class RaggedPlan:

@@ -32,6 +32,14 @@ namespace impconv {
 
 enum ColMode { kPadBwd = 0, kPadFwd = 1, kCenBwd = 2, kCenFwd = 3, kFft = 4, kFsBwd = 5, kFsFwd = 6 };
 
+__host__ __device__ constexpr const char* col_mode_name(int mode)
+{
+    return mode == kPadBwd ? "colpass_pad_bwd" : mode == kPadFwd ? "colpass_pad_fwd"
+         : mode == kCenBwd ? "colpass_cen_bwd" : mode == kCenFwd ? "colpass_cen_fwd"
+         : mode == kFft ? "colpass_fft" : mode == kFsBwd ? "colpass_fourstep_bwd" : "colpass_fourstep_fwd";
+}
+#define MODE_NAME(x) col_mode_name(x)
+
 struct ColArgs {
     const void* in[3];
     void* out[3];
@@ -63,10 +71,13 @@ struct ColArgs {
 
 // Columns per tile: a 64-byte row segment (8 complex64 / 4 complex128), up to
 // 128 bytes for short transforms, limited by 1024 threads and ~140 KB of LDS.
+#ifndef IMPCONV_COL_SEG_BYTES
+#define IMPCONV_COL_SEG_BYTES 64
+#endif
 template <typename T>
 __host__ __device__ constexpr int col_TC(int N)
 {
-    int tc = (N <= 512 ? 128 : 64) / int(sizeof(C<T>));
+    int tc = (N <= 512 ? 128 : IMPCONV_COL_SEG_BYTES) / int(sizeof(C<T>));
     const int G = N / fft_E<T>(N);
     while (tc > 1 && (tc * G > 1024 || (N > fft_E<T>(N) && tc * lpad_size(N) * int(sizeof(C<T>)) > 143360)))
         tc /= 2;

@@ -205,10 +205,17 @@ __device__ __forceinline__ int opaque_zero()
 // Elements per thread for an FFT of size N: 16 complex64 or 8 complex128
 // values (32 VGPRs), so that three such arrays plus butterfly temporaries fit
 // the 256-VGPR budget of two waves per SIMD.
+#ifndef IMPCONV_EMAX_F32
+#define IMPCONV_EMAX_F32 16
+#endif
+#ifndef IMPCONV_EMAX_F64
+#define IMPCONV_EMAX_F64 8
+#endif
 template <typename T>
 __host__ __device__ constexpr int fft_E(int N)
 {
-    return N < (sizeof(T) == 4 ? 16 : 8) ? N : (sizeof(T) == 4 ? 16 : 8);
+    constexpr int emax = sizeof(T) == 4 ? IMPCONV_EMAX_F32 : IMPCONV_EMAX_F64;
+    return N < emax ? N : emax;
 }
 
 // Offset of tw_N inside the concatenated table of all power-of-two sizes.

@@ -1,6 +1,7 @@
 // Instantiations of the kPadBwd / kPadFwd column passes.
 #include "colpass.hpp"
 #include "launch.hpp"
+#include "runtime.hpp"
 
 namespace impconv {
 
@@ -9,7 +10,9 @@ static hipError_t go(const ColArgs& a, hipStream_t s)
 {
     const int64_t nb = a.nslab * ((a.ncols + col_TC<T>(N) - 1) / col_TC<T>(N));
     if (nb == 0) return hipSuccess;
+    timing_begin(s);
     hipLaunchKernelGGL((k_colpass<T, N, MODE, 1>), dim3(((nb + 7) / 8) * 8), dim3(col_block<T>(N)), 0, s, a);
+    timing_end(MODE_NAME(MODE), s);
     return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
 // Instantiations of the complex implicit and plain cyclic row kernels.
 #include "launch.hpp"
+#include "runtime.hpp"
 
 namespace impconv {
 
@@ -11,10 +12,14 @@ static hipError_t go_complex(const RowArgs& a, hipStream_t s)
     if (blocks == 0) return hipSuccess;
     if (a.M == 1) {
         constexpr bool accg = !regs_fit<T>(3, fft_E<T>(N), threads);
+        timing_begin(s);
         hipLaunchKernelGGL((k_conv1d_complex<T, N, accg, false>), dim3(blocks), dim3(threads), 0, s, a);
+        timing_end("k_conv1d_complex", s);
     } else {
         constexpr bool accg = !regs_fit<T>(4, fft_E<T>(N), threads);
+        timing_begin(s);
         hipLaunchKernelGGL((k_conv1d_complex<T, N, accg, true>), dim3(blocks), dim3(threads), 0, s, a);
+        timing_end("k_conv1d_complex", s);
     }
     return hipGetLastError();
 }
@@ -24,7 +29,9 @@ static hipError_t go_cyclic(const RowArgs& a, hipStream_t s)
 {
     const int64_t blocks = (a.nrows + row_GPB<T>(N) - 1) / row_GPB<T>(N);
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_conv1d_cyclic<T, N>), dim3(blocks), dim3(row_block<T>(N)), 0, s, a);
+    timing_begin(s);
+        hipLaunchKernelGGL((k_conv1d_cyclic<T, N>), dim3(blocks), dim3(row_block<T>(N)), 0, s, a);
+        timing_end("k_conv1d_cyclic", s);
     return hipGetLastError();
 }
 

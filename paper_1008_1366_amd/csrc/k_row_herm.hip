@@ -1,5 +1,6 @@
 // Instantiations of the centered Hermitian (2/3 rule) and ternary row kernels.
 #include "launch.hpp"
+#include "runtime.hpp"
 
 namespace impconv {
 
@@ -10,7 +11,9 @@ static hipError_t go_herm(const RowArgs& a, hipStream_t s)
     constexpr bool accg = !regs_fit<T>(5, row_E<T, 1>(NC), threads);
     const int64_t blocks = (a.nrows + row_GPB<T, 1>(NC) - 1) / row_GPB<T, 1>(NC);
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_conv1d_hermitian<T, NC, accg>), dim3(blocks), dim3(threads), 0, s, a);
+    timing_begin(s);
+        hipLaunchKernelGGL((k_conv1d_hermitian<T, NC, accg>), dim3(blocks), dim3(threads), 0, s, a);
+        timing_end("k_conv1d_hermitian", s);
     return hipGetLastError();
 }
 
@@ -21,7 +24,9 @@ static hipError_t go_tern(const RowArgs& a, hipStream_t s)
     constexpr bool accg = !regs_fit<T>(5, row_E<T, 1>(NN), threads);
     const int64_t blocks = (a.nrows + row_GPB<T, 1>(NN) - 1) / row_GPB<T, 1>(NN);
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_conv1d_ternary<T, NN, accg>), dim3(blocks), dim3(threads), 0, s, a);
+    timing_begin(s);
+        hipLaunchKernelGGL((k_conv1d_ternary<T, NN, accg>), dim3(blocks), dim3(threads), 0, s, a);
+        timing_end("k_conv1d_ternary", s);
     return hipGetLastError();
 }
 
@@ -40,7 +45,9 @@ static hipError_t go_realcyclic(const RowArgs& a, hipStream_t s)
 {
     const int64_t blocks = (a.nrows + row_GPB<T, 1>(NC) - 1) / row_GPB<T, 1>(NC);
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_conv1d_realcyclic<T, NC>), dim3(blocks), dim3(row_block<T, 1>(NC)), 0, s, a);
+    timing_begin(s);
+        hipLaunchKernelGGL((k_conv1d_realcyclic<T, NC>), dim3(blocks), dim3(row_block<T, 1>(NC)), 0, s, a);
+        timing_end("k_conv1d_realcyclic", s);
     return hipGetLastError();
 }
 

@@ -22,6 +22,11 @@ hipError_t launch_row_realcyclic(int dt, int NC, const RowArgs& a, hipStream_t s
 hipError_t launch_pad_rows(int dt, const void* src, void* dst, int64_t nrows, int64_t src_ld,
                            int64_t copy, int64_t dst_ld, hipStream_t s);
 
+// 2D copy with zero fill (see k_copy2d)
+hipError_t launch_copy2d(int dt, const void* src, void* dst, int64_t nb, int64_t nsub, int64_t sbs,
+                         int64_t sbs2, int64_t sld, int64_t dbs, int64_t dbs2, int64_t dld, int64_t cx,
+                         int64_t cy, int64_t dx, int64_t dy, hipStream_t s);
+
 // Column passes (colpass.hpp); N <= kColMax.
 constexpr int kColMax = 4096;
 struct ColArgs;

@@ -177,8 +177,10 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
     if (kind != IMPCONV_COMPLEX && kind != IMPCONV_HERMITIAN) return fail(IMPCONV_E_ARG, "nD kind must be COMPLEX or HERMITIAN");
     if (!m || !n) return fail(IMPCONV_E_ARG, "m or n is NULL");
     if (batch < 0 || M < 1) return fail(IMPCONV_E_SIZE, "batch must be >= 0 and M >= 1");
-    const uint32_t known = IMPCONV_NO_SYMMETRIZE;
+    const uint32_t known = IMPCONV_NO_SYMMETRIZE | IMPCONV_EXPLICIT_PADDED;
     if (flags & ~known) return fail(IMPCONV_E_ARG, "unsupported flag for an nD convolution");
+    if ((flags & IMPCONV_EXPLICIT_PADDED) && (kind != IMPCONV_COMPLEX || nd != 2))
+        return fail(IMPCONV_E_UNSUPPORTED, "the explicitly padded comparator covers 2D complex convolutions");
     std::memset(p, 0, sizeof(*p));
     p->kind = kind; p->dt = dt; p->nd = nd; p->batch = batch; p->M = M; p->flags = flags;
     for (int d = 0; d < nd; ++d) {
@@ -202,6 +204,13 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
     }
     const size_t cs = csize(dt);
     const int R = kind == IMPCONV_COMPLEX ? 2 : 3;
+    if (flags & IMPCONV_EXPLICIT_PADDED) {
+        // padded f and g, [b][2N0][M][2N1]
+        const int64_t P0 = 2 * p->Np[0], P1 = 2 * p->Np[1];
+        if (P0 > kColMax || P1 > kRowMax) return fail(IMPCONV_E_UNSUPPORTED, "explicit 2D comparator supports m <= 2048 per axis");
+        p->work = size_t(2) * batch * M * P0 * P1 * cs;
+        return IMPCONV_OK;
+    }
     if (nd == 2) {
         // residue arrays [b][x'][i][y] for f and g
         p->work = size_t(2) * R * batch * M * p->Np[0] * n[1] * cs;
@@ -329,6 +338,57 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
     const int R = herm ? 3 : 2;
     const bool sym = herm && !(flags & IMPCONV_NO_SYMMETRIZE);
     char* w = static_cast<char*>(work);
+
+    if (flags & IMPCONV_EXPLICIT_PADDED) {
+        // Conventional method (Sec. 1): copy the inputs into zero-padded
+        // 2N0 x 2N1 arrays, transform both axes at the padded size, multiply,
+        // transform back, crop.  Same FFT kernels as the implicit path.
+        const int64_t P0 = 2 * p.Np[0], P1 = 2 * p.Np[1], m0 = m[0], m1 = m[1];
+        const size_t arr = size_t(batch) * M * P0 * P1 * cs;
+        void* Fp = w;
+        void* Gp = w + arr;
+        const int64_t slab = P0 * M * P1;
+        for (int q = 0; q < 2; ++q)
+            HIPCHK(launch_copy2d(dt, q ? g : f, q ? Gp : Fp, batch * M, M, M * m0 * m1, m0 * m1, m1, slab, P1,
+                                 M * P1, m0, m1, P0, P1, s), "explicit pad");
+        for (int q = 0; q < 2; ++q) {
+            ColArgs a = col_args(tb, dt);
+            a.in[0] = q ? Gp : Fp;
+            a.out[0] = q ? Gp : Fp;
+            a.nslab = batch * M;
+            a.nsub = M;
+            a.in_bs = a.out_bs = slab;
+            a.in_bs2 = a.out_bs2 = P1;
+            a.ncols = P1;
+            a.in_ld = a.out_ld = M * P1;
+            a.n_in = int(P0);
+            a.n_out = int(P0);
+            HIPCHK(launch_col(dt, int(P0), kFft, 1, a, s), "explicit column FFT");
+        }
+        RowArgs ra = row_args(tb, dt);
+        ra.f = Fp; ra.g = Gp; ra.h = Fp;
+        ra.nrows = batch * P0;
+        ra.m = P1;
+        ra.m_out = P1;
+        ra.M = M;
+        ra.f_row = ra.g_row = ra.h_row = M * P1;
+        ra.f_i = ra.g_i = P1;
+        ra.scale = 1.0 / double(P0 * P1);
+        HIPCHK(launch_row_cyclic(dt, int(P1), ra, s), "explicit row convolution");
+        ColArgs a = col_args(tb, dt);
+        a.in[0] = Fp;
+        a.out[0] = Fp;
+        a.nslab = batch;
+        a.in_bs = a.out_bs = slab;
+        a.ncols = P1;
+        a.in_ld = a.out_ld = M * P1;
+        a.n_in = int(P0);
+        a.n_out = int(m0);
+        HIPCHK(launch_col(dt, int(P0), kFft, -1, a, s), "explicit inverse column FFT");
+        HIPCHK(launch_copy2d(dt, Fp, h, batch, 1, slab, 0, M * P1, m0 * m1, 0, m1, m0, m1, m0, m1, s),
+               "explicit crop");
+        return IMPCONV_OK;
+    }
 
     if (nd == 2) {
         const int64_t N0 = p.Np[0], n0 = n[0], n1 = n[1], m0 = m[0], m1 = m[1];

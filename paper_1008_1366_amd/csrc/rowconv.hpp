@@ -643,4 +643,23 @@ __global__ void k_pad_rows(const C<T>* __restrict__ src, C<T>* __restrict__ dst,
     }
 }
 
+// 2D copy with zero fill: for slab b = b1 * nsub + b2 (b < nb),
+// dst[b1 dbs + b2 dbs2 + x dld + y] = (x < cx && y < cy) ? src[b1 sbs + b2 sbs2 + x sld + y] : 0
+// for x < dx, y < dy.  Materializes the explicitly padded arrays of the
+// comparator and crops its result.
+template <typename T>
+__global__ void k_copy2d(const C<T>* __restrict__ src, C<T>* __restrict__ dst, int64_t nb, int64_t nsub,
+                         int64_t sbs, int64_t sbs2, int64_t sld, int64_t dbs, int64_t dbs2, int64_t dld,
+                         int64_t cx, int64_t cy, int64_t dx, int64_t dy)
+{
+    const int64_t per = dx * dy, total = nb * per;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = i / per, r = i - b * per, x = r / dy, y = r - x * dy;
+        const int64_t b1 = b / nsub, b2 = b - b1 * nsub;
+        const bool in = x < cx && y < cy;
+        dst[b1 * dbs + b2 * dbs2 + x * dld + y] = in ? src[b1 * sbs + b2 * sbs2 + x * sld + y] : zero<T>();
+    }
+}
+
 }  // namespace impconv

@@ -29,6 +29,13 @@ void gen_roots(int64_t denom, int64_t count, double* out_re_im);
 impconv_status fail(impconv_status st, const std::string& msg);
 impconv_status hip_fail(hipError_t e, const char* what);
 
+// Optional per-launch timing (profiling mode, off by default): when enabled,
+// every kernel launch of the library is bracketed by two hipEvents recorded
+// on its stream; impconv_timing_report aggregates them per kernel name.
+bool timing_on();
+void timing_begin(hipStream_t s);
+void timing_end(const char* name, hipStream_t s);
+
 inline int64_t next_pow2(int64_t x)
 {
     int64_t p = 1;

@@ -7,8 +7,12 @@
 // 2/3-rule shifts.  Each value is computed in long double with the argument
 // reduced exactly (integer j mod denom, folded into the first octant) and
 // rounded once to double; the complex64 tables round those doubles to float.
+#include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "cx.hpp"
@@ -106,4 +110,101 @@ const DevTables* tables()
     return &g_tab[dev];
 }
 
+// ------------------------------------------------------------------ timing
+namespace {
+struct Rec {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::mutex t_mu;
+bool t_on = false;
+std::vector<Rec> t_recs;
+thread_local hipEvent_t t_pending = nullptr;
+
+hipEvent_t new_event()
+{
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+}  // namespace
+
+bool timing_on() { return t_on; }
+
+void timing_begin(hipStream_t s)
+{
+    if (!t_on) return;
+    t_pending = new_event();
+    if (t_pending) (void)hipEventRecord(t_pending, s);
+}
+
+void timing_end(const char* name, hipStream_t s)
+{
+    if (!t_on || !t_pending) return;
+    hipEvent_t b = new_event();
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lk(t_mu);
+    t_recs.push_back({name, t_pending, b});
+    t_pending = nullptr;
+}
+
 }  // namespace impconv
+
+extern "C" {
+
+void impconv_timing_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(impconv::t_mu);
+    impconv::t_on = on != 0;
+}
+
+// Waits for the recorded events, writes a JSON array of per-kernel aggregates
+// {"name", "count", "total_ms", "min_ms", "max_ms"} into buf (NUL-terminated,
+// truncated to cap), releases the events and returns the full length.
+size_t impconv_timing_report(char* buf, size_t cap)
+{
+    using namespace impconv;
+    std::vector<Rec> recs;
+    {
+        std::lock_guard<std::mutex> lk(t_mu);
+        recs.swap(t_recs);
+    }
+    struct Agg { int64_t n = 0; double tot = 0, mn = 1e300, mx = 0; };
+    std::vector<std::pair<std::string, Agg>> aggs;
+    for (auto& r : recs) {
+        float ms = 0;
+        (void)hipEventSynchronize(r.b);
+        (void)hipEventElapsedTime(&ms, r.a, r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+        Agg* g = nullptr;
+        for (auto& p : aggs)
+            if (p.first == r.name) g = &p.second;
+        if (!g) {
+            aggs.push_back({r.name, Agg{}});
+            g = &aggs.back().second;
+        }
+        g->n++;
+        g->tot += ms;
+        g->mn = std::min(g->mn, double(ms));
+        g->mx = std::max(g->mx, double(ms));
+    }
+    std::string s = "[";
+    char tmp[512];
+    for (size_t i = 0; i < aggs.size(); ++i) {
+        const auto& a = aggs[i].second;
+        snprintf(tmp, sizeof(tmp), "%s{\"name\": \"%s\", \"count\": %lld, \"total_ms\": %.6f, \"min_ms\": %.6f, \"max_ms\": %.6f}",
+                 i ? ", " : "", aggs[i].first.c_str(), (long long)a.n, a.tot, a.mn, a.mx);
+        s += tmp;
+    }
+    s += "]";
+    if (buf && cap) {
+        const size_t n = std::min(cap - 1, s.size());
+        std::memcpy(buf, s.data(), n);
+        buf[n] = 0;
+    }
+    return s.size();
+}
+
+}  // extern "C"

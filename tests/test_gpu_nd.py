@@ -132,3 +132,15 @@ def test_hermitian_3d_c4_workload(dt):
     got = h[pts[:, 0] + 256, pts[:, 1] + 256, pts[:, 2]]
     assert rel(got, ref) < TOL[dt]
     assert np.all(h[0] == 0) and np.all(h[:, 0] == 0) and np.all(h[:, :, 256] == 0)
+
+
+@pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("shape", [(1, 1), (5, 7), (33, 64), (100, 3)])
+def test_explicit_complex_2d_matches_oracle(dt, shape):
+    ic = need_gpu()
+    B, M = 2, 2
+    f = synth.unit_disk((B, M, *shape), 81)
+    g = synth.unit_disk((B, M, *shape), 82)
+    h = ic.conv2d(to_dev(f, dt), to_dev(g, dt), method="explicit").cpu().numpy()
+    for b in range(B):
+        assert rel(h[b], oracle.convnd_complex_M(rounded(f[b], dt), rounded(g[b], dt))) < TOL[dt]
