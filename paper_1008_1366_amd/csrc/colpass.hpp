@@ -103,6 +103,7 @@ k_colpass(ColArgs a)
     constexpr int E = fft_E<T>(N), G = N / E, TC = col_TC<T>(N);
     constexpr int LDSN = N > E ? lpad_size(N) * TC : 1;
     __shared__ C<T> sh[LDSN];
+    static_assert(sizeof(sh) <= 160 * 1024, "LDS footprint exceeds 160 KB");
     const int col = threadIdx.x % TC, t = threadIdx.x / TC;
     const int64_t ntile = (a.ncols + TC - 1) / TC;
     const int64_t lg = xcd_tile(a.nslab * ntile);

@@ -123,6 +123,12 @@ template <int DIR, typename T> struct DFT<16, DIR, T> {
 // ------------------------------------------------------------------ Stockham stages
 // Group-local LDS view: element p of this group's sequence lives at
 // lds[lpad(p) * LS], LS = element stride (1 for rows, tile width for columns).
+// Addressing: lpad(x + c) = lpad(x) + c + (c >> 4) whenever
+// (x mod 16) + (c mod 16) < 16.  Both access patterns below satisfy it for
+// every power-of-two stage shape -- reads at t + i G (t < G, G a power of
+// two) and writes at base + r NS (base mod 16 < 16 - (R-1) NS mod 16) -- so
+// each butterfly computes one padded base and every element adds a
+// compile-time offset (an immediate in the LDS instruction).
 template <typename T, int N, int E, int DIR, int NS>
 __device__ __forceinline__ void fft_stage(C<T> (&v)[E], int t, C<T>* lds, int LS, const C<T>* __restrict__ tw)
 {
@@ -149,26 +155,100 @@ __device__ __forceinline__ void fft_stage(C<T> (&v)[E], int t, C<T>* lds, int LS
 #pragma unroll
         for (int r = 0; r < R; ++r) u[r] = v[q + r * Q];
         if constexpr (NS > 1) {
+            const int ks = k * (N / (NS * R));  // twiddle r of this butterfly: zeta_N^{r ks}
 #pragma unroll
-            for (int r = 1; r < R; ++r) u[r] = mulw<DIR>(u[r], tws[r * k * (N / (NS * R))]);
+            for (int r = 1; r < R; ++r) u[r] = mulw<DIR>(u[r], tws[r * ks]);
         }
         DFT<R, DIR, T>::run(u);
         if constexpr (LAST) {
 #pragma unroll
             for (int r = 0; r < R; ++r) v[q + r * Q] = u[r];
         } else {
-            const int base = (b - k) * R + k;
+            C<T>* wp = lds + lpad((b - k) * R + k) * LS;
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[lpad(base + r * NS) * LS] = u[r];
+            for (int r = 0; r < R; ++r) wp[(r * NS + ((r * NS) >> 4)) * LS] = u[r];
         }
     }
     if constexpr (!LAST) {
         __syncthreads();
+        const C<T>* rp = lds + lpad(t) * LS;
 #pragma unroll
-        for (int i = 0; i < E; ++i) v[i] = lds[lpad(t + i * G) * LS];
+        for (int i = 0; i < E; ++i) v[i] = rp[(i * G + ((i * G) >> 4)) * LS];
         __syncthreads();
         fft_stage<T, N, E, DIR, NS * R>(v, t, lds, LS, tw);
     }
+}
+
+// Two independent FFTs of the same size and direction advanced stage by
+// stage together: one set of twiddle loads and one pair of barriers per
+// stage serves both, and the two butterfly streams interleave to hide LDS
+// latency.  lds0 / lds1 are two disjoint exchange buffers.
+template <typename T, int N, int E, int DIR, int NS>
+__device__ __forceinline__ void fft2_stage(C<T> (&v0)[E], C<T> (&v1)[E], int t, C<T>* lds0, C<T>* lds1,
+                                           int LS, const C<T>* __restrict__ tw)
+{
+    constexpr int R = (N / NS < E) ? (N / NS) : E;
+    constexpr bool LAST = (NS * R == N);
+    constexpr int G = N / E;
+    constexpr int Q = E / R;
+    int zoff = 0;
+    asm volatile("" : "+s"(zoff));
+    asm volatile("" : "+v"(t));
+    const C<T>* tws = tw + zoff;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int b = t + q * G;
+        const int k = b & (NS - 1);
+        C<T> u0[R], u1[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            u0[r] = v0[q + r * Q];
+            u1[r] = v1[q + r * Q];
+        }
+        if constexpr (NS > 1) {
+            const int ks = k * (N / (NS * R));
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const C<T> w = tws[r * ks];
+                u0[r] = mulw<DIR>(u0[r], w);
+                u1[r] = mulw<DIR>(u1[r], w);
+            }
+        }
+        DFT<R, DIR, T>::run(u0);
+        DFT<R, DIR, T>::run(u1);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                v0[q + r * Q] = u0[r];
+                v1[q + r * Q] = u1[r];
+            }
+        } else {
+            const int wb = lpad((b - k) * R + k) * LS;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                lds0[wb + (r * NS + ((r * NS) >> 4)) * LS] = u0[r];
+                lds1[wb + (r * NS + ((r * NS) >> 4)) * LS] = u1[r];
+            }
+        }
+    }
+    if constexpr (!LAST) {
+        __syncthreads();
+        const int rb = lpad(t) * LS;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            v0[i] = lds0[rb + (i * G + ((i * G) >> 4)) * LS];
+            v1[i] = lds1[rb + (i * G + ((i * G) >> 4)) * LS];
+        }
+        __syncthreads();
+        fft2_stage<T, N, E, DIR, NS * R>(v0, v1, t, lds0, lds1, LS, tw);
+    }
+}
+
+template <typename T, int N, int E, int DIR>
+__device__ __forceinline__ void fft2(C<T> (&v0)[E], C<T> (&v1)[E], int t, C<T>* lds0, C<T>* lds1, int LS,
+                                     const C<T>* __restrict__ tw)
+{
+    if constexpr (N > 1) fft2_stage<T, N, E, DIR, 1>(v0, v1, t, lds0, lds1, LS, tw);
 }
 
 // Full FFT.  All threads of the workgroup must call this together (it

@@ -136,7 +136,10 @@ __global__ void __launch_bounds__(row_block<T>(N), row_waves<T>(N))
 k_conv1d_complex(RowArgs a)
 {
     constexpr int E = fft_E<T>(N), G = N / E, GPB = row_GPB<T>(N), LDSN = row_lds<T>(N);
-    __shared__ C<T> sh[GPB * LDSN];
+    // second exchange buffer for the paired transforms when both fit in LDS
+    constexpr bool DUAL = !MD && 2 * GPB * LDSN * int(sizeof(C<T>)) <= 160 * 1024;
+    __shared__ C<T> sh[(DUAL ? 2 : 1) * GPB * LDSN];
+    static_assert(sizeof(sh) <= 160 * 1024, "LDS footprint exceeds 160 KB");
     const int grp = threadIdx.x / G, t = threadIdx.x % G;
     const RowCtx c = row_ctx(a, (int64_t)blockIdx.x * GPB + grp);
     C<T>* lds = sh + grp * LDSN;
@@ -148,13 +151,65 @@ k_conv1d_complex(RowArgs a)
     C<T>* H = (C<T>*)a.h + c.oh;
     const bool revf = a.flags & kRevF, cjg = a.flags & kConjG, revo = a.flags & kRevOut;
     const T s = T(1) / T(2 * N);
-    C<T> acc[ACCG ? 1 : E];
 
+    if constexpr (!MD) {
+        // M = 1: f and g are read once; both residues r = 0, 1 are formed
+        // from the same registers (x0 = f, x1 = zeta_{2N}^k f, likewise g)
+        // and transformed together (fft2) through two exchange buffers.
+        C<T>* lds1 = DUAL ? sh + (GPB + grp) * LDSN : lds;
+        auto pair = [&](auto& a0, auto& a1, auto dir) {
+            constexpr int D = decltype(dir)::value;
+            if constexpr (DUAL) {
+                fft2<T, N, E, D>(a0, a1, t, lds, lds1, 1, twN);
+            } else {
+                fft<T, N, E, D>(a0, t, lds, 1, twN);
+                fft<T, N, E, D>(a1, t, lds, 1, twN);
+            }
+        };
+        C<T> x0[E], x1[E];
+        {
+            const int z = opaque_zero();
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int k = t + e * G;
+                x0[e] = ldz(F + z, revf ? c.m - 1 - k : k, c.m);
+                x1[e] = x0[e] * tw2N[k + z];
+            }
+        }
+        pair(x0, x1, std::integral_constant<int, +1>{});
+        {
+            C<T> y[E];
+            const int z = opaque_zero();
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                C<T> gv = ldz(Gp + z, t + e * G, c.m);
+                y[e] = cjg ? conj(gv) : gv;
+            }
+            C<T> y1[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) y1[e] = y[e] * tw2N[t + e * G + z];
+            pair(y, y1, std::integral_constant<int, +1>{});
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                x0[e] = x0[e] * y[e];
+                x1[e] = x1[e] * y1[e];
+            }
+        }
+        pair(x0, x1, std::integral_constant<int, -1>{});
+        const int z = opaque_zero();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + e * G;
+            if (k < c.m) H[revo ? c.m - 1 - k : k] = scale(x0[e] + mulc(x1[e], tw2N[k + z]), s);
+        }
+        return;
+    }
+
+    C<T> acc[ACCG ? 1 : E];
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
         C<T> P[E];
-        const int64_t nM = MD ? a.M : 1;  // MD = false: single product, no accumulator
-        for (int64_t i = 0; i < nM; ++i) {
+        for (int64_t i = 0; i < a.M; ++i) {
             C<T> x[E], y[E];
             const int z = opaque_zero();
             const C<T>* Fz = F + z;
@@ -177,7 +232,7 @@ k_conv1d_complex(RowArgs a)
             fft<T, N, E, +1>(x, t, lds, 1, twN);
             fft<T, N, E, +1>(y, t, lds, 1, twN);
 #pragma unroll
-            for (int e = 0; e < E; ++e) P[e] = (MD && i > 0) ? P[e] + x[e] * y[e] : x[e] * y[e];
+            for (int e = 0; e < E; ++e) P[e] = i > 0 ? P[e] + x[e] * y[e] : x[e] * y[e];
         }
         fft<T, N, E, -1>(P, t, lds, 1, twN);
         const C<T>* Wo = tw2N + opaque_zero();
@@ -216,6 +271,7 @@ k_conv1d_cyclic(RowArgs a)
 {
     constexpr int E = fft_E<T>(N), G = N / E, GPB = row_GPB<T>(N), LDSN = row_lds<T>(N);
     __shared__ C<T> sh[GPB * LDSN];
+    static_assert(sizeof(sh) <= 160 * 1024, "LDS footprint exceeds 160 KB");
     const int grp = threadIdx.x / G, t = threadIdx.x % G;
     const RowCtx c = row_ctx(a, (int64_t)blockIdx.x * GPB + grp);
     C<T>* lds = sh + grp * LDSN;
@@ -434,6 +490,7 @@ k_conv1d_hermitian(RowArgs a)
     constexpr int N = 2 * NC;
     constexpr int E = row_E<T, 1>(NC), G = NC / E, GPB = row_GPB<T, 1>(NC), LDSN = row_lds<T, 1>(NC);
     __shared__ C<T> sh[GPB * LDSN];
+    static_assert(sizeof(sh) <= 160 * 1024, "LDS footprint exceeds 160 KB");
     const int grp = threadIdx.x / G, t = threadIdx.x % G;
     const RowCtx c = row_ctx(a, (int64_t)blockIdx.x * GPB + grp);
     C<T>* lds = sh + grp * LDSN;
@@ -543,6 +600,7 @@ k_conv1d_ternary(RowArgs a)
 {
     constexpr int E = row_E<T, 1>(NN), G = NN / E, GPB = row_GPB<T, 1>(NN), LDSN = row_lds<T, 1>(NN);
     __shared__ C<T> sh[GPB * LDSN];
+    static_assert(sizeof(sh) <= 160 * 1024, "LDS footprint exceeds 160 KB");
     const int grp = threadIdx.x / G, t = threadIdx.x % G;
     const RowCtx c = row_ctx(a, (int64_t)blockIdx.x * GPB + grp);
     C<T>* lds = sh + grp * LDSN;
@@ -577,6 +635,7 @@ k_conv1d_realcyclic(RowArgs a)
 {
     constexpr int E = row_E<T, 1>(NC), G = NC / E, GPB = row_GPB<T, 1>(NC), LDSN = row_lds<T, 1>(NC);
     __shared__ C<T> sh[GPB * LDSN];
+    static_assert(sizeof(sh) <= 160 * 1024, "LDS footprint exceeds 160 KB");
     const int grp = threadIdx.x / G, t = threadIdx.x % G;
     const RowCtx c = row_ctx(a, (int64_t)blockIdx.x * GPB + grp);
     C<T>* lds = sh + grp * LDSN;
