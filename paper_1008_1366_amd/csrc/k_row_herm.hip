@@ -8,12 +8,14 @@ template <typename T, int NC>
 static hipError_t go_herm(const RowArgs& a, hipStream_t s)
 {
     constexpr int threads = row_block<T, 1>(NC);
-    constexpr bool accg = !regs_fit<T>(5, row_E<T, 1>(NC), threads);
     const int64_t blocks = (a.nrows + row_GPB<T, 1>(NC) - 1) / row_GPB<T, 1>(NC);
     if (blocks == 0) return hipSuccess;
     timing_begin(s);
-        hipLaunchKernelGGL((k_conv1d_hermitian<T, NC, accg>), dim3(blocks), dim3(threads), 0, s, a);
-        timing_end("k_conv1d_hermitian", s);
+    if (a.M == 1)
+        hipLaunchKernelGGL((k_conv1d_hermitian<T, NC, false>), dim3(blocks), dim3(threads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_conv1d_hermitian<T, NC, true>), dim3(blocks), dim3(threads), 0, s, a);
+    timing_end("k_conv1d_hermitian", s);
     return hipGetLastError();
 }
 

@@ -377,100 +377,54 @@ __device__ __forceinline__ C<T> zeta3N(const C<T>* tw3N, int k)
     return R > 0 ? w : conj(w);
 }
 
-// Packed c2r input for residue R at frequency k (0 <= k < NC) built from the
-// Hermitian half U (length m, zero beyond).
-template <typename T, int NC, int R, bool MAYBE0>
-__device__ __forceinline__ C<T> herm_Z(const C<T>* U, int m, int k, const C<T>* tw3N,
-                                       const C<T>* tw2NC)
+// Packed c2r inputs of the three residues r = 0, +1, -1 at this thread's
+// frequencies k = t + e G (0 <= k < NC), from one read of the Hermitian half
+// U (length m, zero beyond).  Each thread loads U_k and U_{NC+k}; the mirrored
+// values U_{NC-k} and U_{N-k} come from the thread holding NC - k through the
+// exchange buffer.  With w_{k,r} = zeta_{3N}^{rk} (U_k + zeta_3^{-r} conj U_{N-k}),
+// w_{0,r} = Re U_0 and the real w_{NC,r}, Z_{k,r} = c2r_pre(w_{k,r}, w_{NC-k,r}).
+template <typename T, int NC, int E>
+__device__ __forceinline__ void herm_build3(const C<T>* U, int m, int t, C<T>* lds, const C<T>* tw3N,
+                                            const C<T>* twN, C<T> (&z0)[E], C<T> (&z1)[E], C<T> (&z2)[E])
 {
-    constexpr int N = 2 * NC;
-    auto ld = [&](int j) -> C<T> { return ldz(U, j, m); };
-    const C<T> z3 = z3m<T, R>();
-    C<T> wk = zeta3N<T, R>(tw3N, k) * (ld(k) + z3 * conj(ld(N - k)));
-    C<T> wck = zeta3N<T, R>(tw3N, NC - k) * (ld(NC - k) + z3 * conj(ld(NC + k)));
-    if constexpr (MAYBE0) {
-        // k = 0 pairs w_0 = Re U_0 with the real w_NC (Re U_NC -/+ sqrt3 Im U_NC, or 2 Re U_NC)
-        const C<T> u0 = ld(0), uc = ld(NC);
-        const T sq3 = T(1.73205080756887729353);
-        const T vc = R == 0 ? T(2) * uc.re : (R > 0 ? uc.re - sq3 * uc.im : uc.re + sq3 * uc.im);
-        const bool z = k == 0;
-        wk = z ? C<T>{u0.re, T(0)} : wk;
-        wck = z ? C<T>{vc, T(0)} : wck;
-    }
-    return c2r_pre(wk, wck, tw2NC[k]);
-}
-
-// One residue of the Hermitian convolution: 2M c2r transforms, the real
-// products, one r2c transform and the accumulation of its contribution to
-// H_k, H_{N-k} and H_NC.
-template <typename T, int NC, int R, bool ACCG, bool FIRST>
-__device__ __forceinline__ void herm_residue(const RowArgs& a, const RowCtx& c, int m, int t,
-                                             C<T>* lds, C<T> (&alo)[ACCG ? 1 : row_E<T, 1>(NC)],
-                                             C<T> (&ahi)[ACCG ? 1 : row_E<T, 1>(NC)], C<T>& acen)
-{
-    constexpr int N = 2 * NC;
-    constexpr int E = row_E<T, 1>(NC), G = NC / E;
-    const C<T>* twb = (const C<T>*)a.tw;
-    const C<T>* twNC = twb + tw_off(NC);
-    const C<T>* twN = twb + tw_off(N);
-    const C<T>* tw3N = (const C<T>*)a.tw3 + tw_off(N);
-    C<T>* H = (C<T>*)a.h + c.oh;
-    const T s = T(1) / T(3 * N);
-    C<T> P[E];
-    for (int64_t i = 0; i < a.M; ++i) {
-        C<T> x[E], y[E];
-        {
-            const int z = opaque_zero();
-            const C<T>* F = (const C<T>*)a.f + c.of + i * a.f_i + z;
-            static_for<E>([&](auto ec) {
-                constexpr int e = decltype(ec)::value;
-                x[e] = herm_Z<T, NC, R, e == 0>(F, m, t + e * G, tw3N + z, twN + z);
-            });
-        }
-        fft<T, NC, E, +1>(x, t, lds, 1, twNC);
-        {
-            const int z = opaque_zero();
-            const C<T>* Gp = (const C<T>*)a.g + c.og + i * a.g_i + z;
-            static_for<E>([&](auto ec) {
-                constexpr int e = decltype(ec)::value;
-                y[e] = herm_Z<T, NC, R, e == 0>(Gp, m, t + e * G, tw3N + z, twN + z);
-            });
-        }
-        fft<T, NC, E, +1>(y, t, lds, 1, twNC);
+    constexpr int N = 2 * NC, G = NC / E;
+    const T h3 = T(0.86602540378443864676), sq3 = T(1.73205080756887729353);
+    C<T> lo[E], hi[E], lom[E], him[E];
+    {
+        const int z = opaque_zero();
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const C<T> p{x[e].re * y[e].re, x[e].im * y[e].im};
-            P[e] = i ? P[e] + p : p;
+            lo[e] = ldz(U + z, t + e * G, m);
+            hi[e] = ldz(U + z, NC + t + e * G, m);
         }
     }
-    fft<T, NC, E, -1>(P, t, lds, 1, twNC);
-    C<T> Pm[E];
-    mirror<T, NC, E>(P, Pm, t, lds);
-    const C<T> z3 = z3m<T, R>();
-    const int zo = opaque_zero();
+    mirror<T, NC, E>(lo, lom, t, lds);  // lom[e] = U_{(NC - k) mod NC}
+    mirror<T, NC, E>(hi, him, t, lds);  // him[e] = U_{NC + (NC - k) mod NC}
+    const int z = opaque_zero();
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = t + e * G;
-        const C<T> V = r2c_post(P[e], Pm[e], twN[k + zo]);
-        const C<T> wk = zeta3N<T, R>(tw3N + zo, k);
-        const C<T> lo = mulc(V, wk);              // zeta_{3N}^{-Rk} V_R(k)
-        const C<T> hi = z3 * (wk * conj(V));      // zeta_{3N}^{-R(N-k)} conj V_R(k)
-        if constexpr (ACCG) {
-            if (k < m) H[k] = FIRST ? scale(lo, s) : H[k] + scale(lo, s);
-            if (k > 0 && N - k < m) H[N - k] = FIRST ? scale(hi, s) : H[N - k] + scale(hi, s);
-        } else {
-            alo[e] = FIRST ? lo : alo[e] + lo;
-            ahi[e] = FIRST ? hi : ahi[e] + hi;
-        }
-        if (e == 0 && k == 0) {
-            // V_R(NC) = Re P_0 - Im P_0 enters H_NC with zeta_{3N}^{-R NC} = zeta_6^{-R}
-            const C<T> cen = z6m<T, R>() * C<T>{P[e].re - P[e].im, T(0)};
-            if constexpr (ACCG) {
-                if (NC < m) H[NC] = FIRST ? scale(cen, s) : H[NC] + scale(cen, s);
-            } else {
-                acen = FIRST ? cen : acen + cen;
-            }
-        }
+        const bool k0 = e == 0 && k == 0;
+        const C<T> a = lo[e];                         // U_k
+        const C<T> b = k0 ? zero<T>() : him[e];       // U_{N-k}
+        const C<T> c = k0 ? hi[e] : lom[e];           // U_{NC-k}
+        const C<T> d = hi[e];                         // U_{NC+k}
+        const C<T> wk = tw3N[k + z], wc = tw3N[NC - k + z], w2 = twN[k + z];
+        // r = 0
+        C<T> p = a + conj(b), q = c + conj(d);
+        if (k0) { p = C<T>{a.re, T(0)}; q = C<T>{T(2) * c.re, T(0)}; }
+        z0[e] = c2r_pre(p, q, w2);
+        // r = +1: zeta_3^{-1} = (-1/2, -sqrt3/2)
+        const C<T> z3p{T(-0.5), -h3}, z3m{T(-0.5), h3};
+        p = wk * (a + z3p * conj(b));
+        q = wc * (c + z3p * conj(d));
+        if (k0) { p = C<T>{a.re, T(0)}; q = C<T>{c.re - sq3 * c.im, T(0)}; }
+        z1[e] = c2r_pre(p, q, w2);
+        // r = -1: zeta_3^{+1}, conjugate shifts
+        p = mulc(a + z3m * conj(b), wk);
+        q = mulc(c + z3m * conj(d), wc);
+        if (k0) { p = C<T>{a.re, T(0)}; q = C<T>{c.re + sq3 * c.im, T(0)}; }
+        z2[e] = c2r_pre(p, q, w2);
     }
 }
 
@@ -482,8 +436,9 @@ __device__ __forceinline__ void herm_residue(const RowArgs& a, const RowCtx& c, 
 // is transformed complex-to-real (packed into one size-NC complex FFT), the
 // real products of the two inputs are transformed real-to-complex, and
 //   3N H_k = sum_r zeta_{3N}^{-rk} V_r(k),  V_r(N-k) = conj V_r(k).
+// Each input row is read once; the three residues are built from registers.
 // ======================================================================
-template <typename T, int NC, bool ACCG>
+template <typename T, int NC, bool MD>
 __global__ void __launch_bounds__((row_block<T, 1>(NC)), row_waves<T>(NC))
 k_conv1d_hermitian(RowArgs a)
 {
@@ -494,24 +449,77 @@ k_conv1d_hermitian(RowArgs a)
     const int grp = threadIdx.x / G, t = threadIdx.x % G;
     const RowCtx c = row_ctx(a, (int64_t)blockIdx.x * GPB + grp);
     C<T>* lds = sh + grp * LDSN;
+    const C<T>* twb = (const C<T>*)a.tw;
+    const C<T>* twNC = twb + tw_off(NC);
+    const C<T>* twN = twb + tw_off(N);
+    const C<T>* tw3N = (const C<T>*)a.tw3 + tw_off(N);
     const int m = c.m;
-    C<T> alo[ACCG ? 1 : E], ahi[ACCG ? 1 : E], acen = zero<T>();
-    herm_residue<T, NC, 0, ACCG, true>(a, c, m, t, lds, alo, ahi, acen);
-    herm_residue<T, NC, 1, ACCG, false>(a, c, m, t, lds, alo, ahi, acen);
-    herm_residue<T, NC, -1, ACCG, false>(a, c, m, t, lds, alo, ahi, acen);
-    if constexpr (!ACCG) {
-        C<T>* H = (C<T>*)a.h + c.oh;
-        const T s = T(1) / T(3 * N);
+    C<T> P0[E], P1[E], P2[E];
+    const int64_t nM = MD ? a.M : 1;
+    for (int64_t i = 0; i < nM; ++i) {
+        C<T> x0[E], x1[E], x2[E];
+        herm_build3<T, NC, E>((const C<T>*)a.f + c.of + i * a.f_i, m, t, lds, tw3N, twN, x0, x1, x2);
+        fft<T, NC, E, +1>(x0, t, lds, 1, twNC);
+        fft<T, NC, E, +1>(x1, t, lds, 1, twNC);
+        fft<T, NC, E, +1>(x2, t, lds, 1, twNC);
+        C<T> y0[E], y1[E], y2[E];
+        herm_build3<T, NC, E>((const C<T>*)a.g + c.og + i * a.g_i, m, t, lds, tw3N, twN, y0, y1, y2);
+        fft<T, NC, E, +1>(y0, t, lds, 1, twNC);
+        fft<T, NC, E, +1>(y1, t, lds, 1, twNC);
+        fft<T, NC, E, +1>(y2, t, lds, 1, twNC);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const C<T> p0{x0[e].re * y0[e].re, x0[e].im * y0[e].im};
+            const C<T> p1{x1[e].re * y1[e].re, x1[e].im * y1[e].im};
+            const C<T> p2{x2[e].re * y2[e].re, x2[e].im * y2[e].im};
+            P0[e] = (MD && i > 0) ? P0[e] + p0 : p0;
+            P1[e] = (MD && i > 0) ? P1[e] + p1 : p1;
+            P2[e] = (MD && i > 0) ? P2[e] + p2 : p2;
+        }
+    }
+    fft<T, NC, E, -1>(P0, t, lds, 1, twNC);
+    fft<T, NC, E, -1>(P1, t, lds, 1, twNC);
+    fft<T, NC, E, -1>(P2, t, lds, 1, twNC);
+    // recombination: V_r(k) from P_r(k), P_r(NC-k); H_k, H_{N-k}, H_NC
+    C<T> olo[E], ohi[E], ocen = zero<T>();
+    const T h3 = T(0.86602540378443864676);
+    static_for<3>([&](auto ri) {
+        constexpr int R = decltype(ri)::value == 0 ? 0 : (decltype(ri)::value == 1 ? 1 : -1);
+        C<T>(&P)[E] = R == 0 ? P0 : (R > 0 ? P1 : P2);
+        C<T> Pm[E];
+        mirror<T, NC, E>(P, Pm, t, lds);
+        const C<T> z3 = R == 0 ? C<T>{T(1), T(0)} : (R > 0 ? C<T>{T(-0.5), -h3} : C<T>{T(-0.5), h3});
+        const int zo = opaque_zero();
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = t + e * G;
-            if (k < m) H[k] = scale(alo[e], s);
-            if (k > 0 && N - k < m) H[N - k] = scale(ahi[e], s);
+            const C<T> V = r2c_post(P[e], Pm[e], twN[k + zo]);
+            C<T> lo = V, hi = conj(V);
+            if constexpr (R != 0) {
+                const C<T> w = tw3N[k + zo];
+                lo = R > 0 ? mulc(V, w) : V * w;                     // zeta_{3N}^{-Rk} V
+                hi = z3 * (R > 0 ? w * conj(V) : mulc(conj(V), w));  // zeta_3^{-R} zeta_{3N}^{Rk} conj V
+            }
+            olo[e] = R == 0 ? lo : olo[e] + lo;
+            ohi[e] = R == 0 ? hi : ohi[e] + hi;
+            if (e == 0 && k == 0) {
+                // V_R(NC) = Re P_0 - Im P_0 enters H_NC with zeta_6^{-R}
+                const C<T> z6 = R == 0 ? C<T>{T(1), T(0)} : (R > 0 ? C<T>{T(0.5), -h3} : C<T>{T(0.5), h3});
+                const C<T> cen = z6 * C<T>{P[e].re - P[e].im, T(0)};
+                ocen = R == 0 ? cen : ocen + cen;
+            }
         }
-        if (t == 0 && NC < m) H[NC] = scale(acen, s);
+    });
+    C<T>* H = (C<T>*)a.h + c.oh;
+    const T s = T(1) / T(3 * N);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = t + e * G;
+        if (k < m) H[k] = scale(olo[e], s);
+        if (k > 0 && N - k < m) H[N - k] = scale(ohi[e], s);
     }
+    if (t == 0 && NC < m) H[NC] = scale(ocen, s);
     if (c.act) {
-        C<T>* H = (C<T>*)a.h + c.oh;
         for (int64_t j = m + t; j < a.h_pad; j += G) H[j] = zero<T>();
     }
 }
