@@ -12,10 +12,12 @@ Other workloads (--workload): c1 (1D complex m=1024 complex128, batch 16384),
 c2 (1D centered Hermitian m=16384, batch 256), c4 (3D centered Hermitian
 512x512x257, M=3), c5 (4096 uneven 1D complex pairs, forward + backward).
 
-Output: one JSON line (rank 0) with the metric, per-step time, the roofline
-of the dominant kernel (HIP-event durations recorded by the library around
-each launch, on the launch stream) and the FP64 oracle timed on the host on
-a bounded sample (the only place bench.py touches the oracle).
+Output: one JSON line (rank 0) with the metric, per-step time (mean and the
+one-sided deviations below and above it), per-kernel algorithmic bytes and
+flops, the roofline of the dominant kernel (HIP-event durations recorded by
+the library around each launch, on the launch stream), the bandwidth of a
+plain device copy for reference, and the FP64 oracle timed on the host on a
+bounded sample (the only place bench.py touches the oracle).
 """
 from __future__ import annotations
 
@@ -33,6 +35,29 @@ sys.path.insert(0, ROOT)
 
 METRIC = "dealiased convs/sec + HBM GB/s, implicit vs explicit-padded, FP32/FP64 at rel err"
 HBM_PEAK_GBS = 8000.0
+# Vector FMA rate of 256 CUs x 4 SIMDs x 16 lanes x 2 flops at 2.4 GHz.  The
+# chip's 157.3 TFLOP/s FP32 figure needs packed FP32 instructions, which this
+# library is built without; FP64 runs at the same 78.6 TFLOP/s.
+VALU_PEAK_TFLOPS = 78.6
+VALU_PEAK_PACKED_FP32_TFLOPS = 157.3
+
+
+def flops_row_complex(N: int) -> float:
+    """Algorithmic flops of one fused complex row convolution of FFT size N
+    (Sec. 2.1): six N-point FFTs at 5 N log2 N, the residue shifts of f and g
+    (2N complex products), the residue products (2N) and the recombination
+    (N products, N additions, N scalings)."""
+    return 6 * 5.0 * N * np.log2(max(N, 2)) + 34.0 * N
+
+
+def flops_row_hermitian(NC: int, M: int = 1) -> float:
+    """Algorithmic flops of one fused Hermitian row convolution with NC
+    complex modes (m = 2 NC reals per transform, Sec. 2.3): for each of the
+    three residues, 2M real-to-complex-sized backward transforms and one
+    forward one at 2.5 m log2 m, the residue shifts (2M products of NC), the
+    M-dot of real products (2 m M) and the recombination (3 NC products)."""
+    m = 2 * NC
+    return 3 * (2 * M + 1) * 2.5 * m * np.log2(max(m, 2)) + 3 * (6.0 * 2 * M * NC + 2.0 * m * M) + 3 * 8.0 * NC
 
 
 def kernel_source_hash() -> str:
@@ -66,6 +91,37 @@ def timed(fn, steps, warmup, backlog=False):
     return e0.elapsed_time(e1) / steps
 
 
+def step_stats(fn, n):
+    """Per-step times (events around each step): mean and the root-mean-square
+    deviations of the steps below and above the mean (sigma_L, sigma_H)."""
+    import torch
+    s = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(s)
+    for i in range(n):
+        fn()
+        ev[i + 1].record(s)
+    torch.cuda.synchronize()
+    t = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(n)])
+    mu = t.mean()
+    lo, hi = t[t < mu], t[t >= mu]
+    rms = lambda d: float(np.sqrt(np.mean(d ** 2))) if len(d) else 0.0
+    return {"n": n, "mean_ms": round(float(mu), 5), "sigma_lo_ms": round(rms(mu - lo), 5),
+            "sigma_hi_ms": round(rms(hi - mu), 5)}
+
+
+def copy_bandwidth(mib=1024):
+    """Bandwidth of a plain device-to-device copy (read + write bytes / time)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    ms = timed(lambda: y.copy_(x), 10, 2)
+    del x, y
+    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
+
+
 # --------------------------------------------------------------------------- workloads
 
 def wl_c3(args):
@@ -86,23 +142,27 @@ def wl_c3(args):
     expl = lambda: ic.conv2d(F, G, method="explicit")
     # algorithmic bytes per launch: every pass moves 3 S (Sec. 3.1 schedule)
     kbytes = {"colpass_pad_bwd": 3 * S, "k_conv1d_complex": 3 * S, "colpass_pad_fwd": 3 * S}
+    # the row kernel convolves 2 m_x rows per pair (one launch per x residue)
+    kflops = {"k_conv1d_complex": B * mx * flops_row_complex(my)}
     step_bytes = 15 * S
 
-    def cpu_baseline(h_gpu):
+    def cpu_baseline(h_gpu, h_expl=None):
         """Oracle at stratified sample points of every pair: the whole
         low-wavenumber block [0,L)^2 (where the energy of the (1+|k|^2)^-1
         spectra concentrates) plus uniform random points elsewhere.  The
-        strata weights give an estimate of the full-field relative L2 error;
-        the time gives the oracle's rate, extrapolated by multiply-add count."""
+        strata weights give an estimate of each pair's full-field relative
+        L2 error (reported as max and median over the pairs, for the implicit
+        result and the explicitly padded one); the time gives the oracle's
+        rate, extrapolated by multiply-add count."""
         import oracle
         rng = synth.rng(7)
         L = 16
         blk = np.array([(i, j) for i in range(L) for j in range(L)])
         nrand = max(1, args.cpu_points // B)
         dt_np = np.complex64 if cdt == torch.complex64 else np.complex128
-        num = den = pnum = pden = 0.0
         macs = 0.0
         t_oracle = 0.0
+        res = {"implicit": [], "explicit": [], "uniform_random_points": []}
         for b in range(B):
             rp = rng.integers(0, mx, (4 * nrand, 2))
             rp = rp[(rp[:, 0] >= L) | (rp[:, 1] >= L)][:nrand]
@@ -113,18 +173,21 @@ def wl_c3(args):
             ref = oracle.convnd_complex_at(fr, gr, pts)
             t_oracle += time.perf_counter() - t0
             macs += float(np.sum((pts[:, 0] + 1.0) * (pts[:, 1] + 1.0)))
-            got = h_gpu[b][pts[:, 0], pts[:, 1]]
-            e2 = np.abs(got - ref) ** 2
             r2 = np.abs(ref) ** 2
             wb = (mx * my - L * L) / len(rp)
-            num += e2[:len(blk)].sum() + wb * e2[len(blk):].sum()
-            den += r2[:len(blk)].sum() + wb * r2[len(blk):].sum()
-            pnum += e2[len(blk):].sum()
-            pden += r2[len(blk):].sum()
+            for key, h in (("implicit", h_gpu), ("explicit", h_expl)):
+                if h is None:
+                    continue
+                e2 = np.abs(h[b][pts[:, 0], pts[:, 1]] - ref) ** 2
+                num = e2[:len(blk)].sum() + wb * e2[len(blk):].sum()
+                den = r2[:len(blk)].sum() + wb * r2[len(blk):].sum()
+                res[key].append(float(np.sqrt(num / den)))
+                if key == "implicit":
+                    res["uniform_random_points"].append(float(np.sqrt(e2[len(blk):].sum() / r2[len(blk):].sum())))
         full = (mx * (mx + 1) / 2.0) * (my * (my + 1) / 2.0)
         convs_per_s = 1.0 / (t_oracle / macs * full)
-        errs = {"full_field_estimate": float(np.sqrt(num / den)),
-                "uniform_random_points": float(np.sqrt(pnum / pden))}
+        errs = {k: {"max": max(v), "median": float(np.median(v)), "pairs": len(v)} for k, v in res.items() if v}
+        errs["estimate"] = "full-field relative L2 per pair, from the stratified sample"
         return {"value": convs_per_s, "unit": "convs/s", "cores": oracle.num_threads(), "kind": "oracle",
                 "sample": f"per pair the {L}x{L} low-wavenumber block plus {nrand} uniform random "
                           f"output points, direct FP64 sums ({t_oracle:.2f} s), extrapolated to whole "
@@ -133,7 +196,7 @@ def wl_c3(args):
     cfg = {"workload": f"2D complex implicit dealiased convolution {mx}x{my}, batch {B} pairs per step, "
                        f"{'complex64' if cdt == torch.complex64 else 'complex128'}",
            "m": [mx, my], "batch": B, "M": 1, "dtype": args.dtype}
-    return dict(run=run, explicit=expl, convs=B, step_bytes=step_bytes, kbytes=kbytes, cfg=cfg,
+    return dict(run=run, explicit=expl, convs=B, step_bytes=step_bytes, kbytes=kbytes, kflops=kflops, cfg=cfg,
                 cpu=cpu_baseline, out=lambda: run().cpu().numpy())
 
 
@@ -151,10 +214,11 @@ def wl_c2(args):
     cs = 8 if cdt == torch.complex64 else 16
     run = lambda: ic.conv1d_hermitian(F, G)
     kbytes = {"k_conv1d_hermitian": 3 * B * m * cs}
+    kflops = {"k_conv1d_hermitian": B * flops_row_hermitian(m // 2)}
 
     def cpu_baseline(h_gpu):
         import oracle
-        nb = max(1, args.cpu_rows)
+        nb = min(B, args.cpu_rows or 256)
         fr = np.asarray(f[:nb].astype(np.complex64 if cdt == torch.complex64 else np.complex128), np.complex128)
         gr = np.asarray(g[:nb].astype(np.complex64 if cdt == torch.complex64 else np.complex128), np.complex128)
         t0 = time.perf_counter()
@@ -168,8 +232,8 @@ def wl_c2(args):
                        f"{'complex64' if cdt == torch.complex64 else 'complex128'}",
            "m": m, "batch": B, "dtype": args.dtype}
     expl = None
-    return dict(run=run, explicit=expl, convs=B, step_bytes=3 * B * m * cs, kbytes=kbytes, cfg=cfg,
-                cpu=cpu_baseline, out=lambda: run().cpu().numpy())
+    return dict(run=run, explicit=expl, convs=B, step_bytes=3 * B * m * cs, kbytes=kbytes, kflops=kflops,
+                cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy())
 
 
 def wl_c1(args):
@@ -187,23 +251,28 @@ def wl_c1(args):
     run = lambda: ic.conv1d_complex(F, G)
     expl = lambda: ic.conv1d_complex(F, G, method="explicit")
     kbytes = {"k_conv1d_complex": 3 * B * m * cs}
+    kflops = {"k_conv1d_complex": B * flops_row_complex(m)}
 
-    def cpu_baseline(h_gpu):
+    def cpu_baseline(h_gpu, h_expl=None):
         import oracle
-        nb = max(1, args.cpu_rows)
+        nb = min(B, args.cpu_rows or 8192)
         t0 = time.perf_counter()
         ref = oracle.conv1d_complex(np.asarray(f[:nb].astype(np.complex64 if cdt == torch.complex64 else np.complex128), np.complex128)[:, None],
                                     np.asarray(g[:nb].astype(np.complex64 if cdt == torch.complex64 else np.complex128), np.complex128)[:, None])
         dt = time.perf_counter() - t0
-        err = float(np.linalg.norm(h_gpu[:nb] - ref) / np.linalg.norm(ref))
+        err = {}
+        for key, h in (("implicit", h_gpu), ("explicit", h_expl)):
+            if h is not None:
+                e = [float(np.linalg.norm(h[i] - ref[i]) / np.linalg.norm(ref[i])) for i in range(nb)]
+                err[key] = {"max": max(e), "median": float(np.median(e)), "pairs": nb}
         return {"value": nb / dt, "unit": "convs/s", "cores": oracle.num_threads(), "kind": "oracle",
                 "sample": f"{nb} of the {B} pairs, direct FP64 sums ({dt:.2f} s)"}, err
 
     cfg = {"workload": f"1D complex implicit dealiased convolution m={m}, batch {B}, "
                        f"{'complex64' if cdt == torch.complex64 else 'complex128'}", "m": m, "batch": B,
            "dtype": args.dtype}
-    return dict(run=run, explicit=expl, convs=B, step_bytes=3 * B * m * cs, kbytes=kbytes, cfg=cfg,
-                cpu=cpu_baseline, out=lambda: run().cpu().numpy())
+    return dict(run=run, explicit=expl, convs=B, step_bytes=3 * B * m * cs, kbytes=kbytes, kflops=kflops,
+                cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy())
 
 
 def wl_c4(args):
@@ -220,8 +289,13 @@ def wl_c4(args):
     cs = 8 if cdt == torch.complex64 else 16
     S = int(np.prod(n)) * cs
     run = lambda: ic.conv3d(F, G, kind="hermitian", m=m)
-    # Sec. 3.4 five-pass schedule, algorithmic bytes per launch
-    kbytes = {"colpass_cen_bwd": None, "k_conv1d_hermitian": None, "colpass_cen_fwd": None}
+    # Sec. 3.4 five-pass schedule, algorithmic bytes per step (S = one stored
+    # array): x back 6S -> 9S and y back 9S -> 13.5S (colpass_cen_bwd), z
+    # convolutions 13.5S -> 2.25S (3 m_x x 3 m_y rows, M = 3 per row), y
+    # forward 2.25S -> 1.5S and x forward 1.5S -> S (colpass_cen_fwd)
+    kbytes_step = {"colpass_cen_bwd": int(37.5 * S), "k_conv1d_hermitian": int(15.75 * S),
+                   "colpass_cen_fwd": int(6.25 * S)}
+    kflops_step = {"k_conv1d_hermitian": 9 * m[0] * m[1] * flops_row_hermitian(m[2] // 2, 3)}
     step_bytes = int(59.5 * S)
 
     def cpu_baseline(h_gpu):
@@ -244,11 +318,100 @@ def wl_c4(args):
                        "(m=256 per axis), M=3 pairs summed, "
                        f"{'complex64' if cdt == torch.complex64 else 'complex128'}",
            "m": list(m), "n": list(n), "M": 3, "dtype": args.dtype}
-    return dict(run=run, explicit=None, convs=1, step_bytes=step_bytes, kbytes=kbytes, cfg=cfg,
-                cpu=cpu_baseline, out=lambda: run().cpu().numpy())
+    return dict(run=run, explicit=None, convs=1, step_bytes=step_bytes, kbytes_step=kbytes_step,
+                kflops_step=kflops_step, cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy())
 
 
-WORKLOADS = {"c1": wl_c1, "c2": wl_c2, "c3": wl_c3, "c4": wl_c4}
+def wl_c5(args):
+    """4096 uneven complex 1D pairs, m = 2^round(U(6,16)), packed end to end;
+    one step = forward and backward (both input gradients) through the
+    differentiable ragged wrapper for the loss L = Re sum conj(w) h, whose
+    upstream gradient dL/dh is w."""
+    import torch
+    import paper_1008_1366_amd as ic
+    import synth
+    cdt = torch.complex64 if args.dtype == "c64" else torch.complex128
+    dt_np = np.complex64 if cdt == torch.complex64 else np.complex128
+    ms = synth.ragged_lengths(4096, 6, 16, 5)
+    offs = np.concatenate([[0], np.cumsum(ms)[:-1]])
+    tot = int(ms.sum())
+    f = synth.unit_disk(tot, 9)
+    g = synth.unit_disk(tot, 10)
+    w = synth.unit_disk(tot, 11)
+    F = torch.from_numpy(f).to("cuda", cdt).requires_grad_(True)
+    G = torch.from_numpy(g).to("cuda", cdt).requires_grad_(True)
+    Wt = torch.from_numpy(w).to("cuda", cdt)
+    plan = ic.RaggedPlan(ms, offs, dtype=cdt)
+    cs = 8 if cdt == torch.complex64 else 16
+
+    def run():
+        F.grad = None
+        G.grad = None
+        h = ic.ragged_conv_ad(plan, F, G)
+        h.backward(Wt)
+        return h
+
+    # algorithmic bytes per step and kernel: pairs with N = 2^ceil(log2 m)
+    # <= 8192 run the fused row kernel (reads f, g, writes h); longer ones the
+    # four-step form (pass 1 reads m and writes two N-point residues per
+    # input, pass 2 reads four and writes two residues, pass 3 reads two and
+    # writes m).  Three executions per step: forward, grad f, grad g.
+    Ns = 2 ** np.ceil(np.log2(ms)).astype(np.int64)
+    small = Ns <= 8192
+    kb = {"k_conv1d_complex": 3 * int(ms[small].sum()) * cs,
+          "colpass_fourstep_bwd": 2 * int((ms[~small] + 2 * Ns[~small]).sum()) * cs,
+          "k_conv1d_cyclic": 6 * int(Ns[~small].sum()) * cs,
+          "colpass_fourstep_fwd": int((2 * Ns[~small] + ms[~small]).sum()) * cs}
+    kbytes_step = {k: 3 * v for k, v in kb.items()}
+    kflops_step = {"k_conv1d_complex": 3 * float(sum(flops_row_complex(int(n)) for n in Ns[small]))}
+    step_bytes = 9 * tot * cs  # compulsory: f, g, h of each execution
+
+    def cpu_baseline(h_gpu):
+        """Oracle forward and both gradients of the pairs with m <= 8192, in
+        pair order up to a multiply-add budget, extrapolated to the whole
+        step by multiply-add count; errors of the GPU forward and gradients
+        on those pairs and at sampled outputs of the longest pairs."""
+        import oracle
+        gf = F.grad.detach().cpu().numpy()
+        gg = G.grad.detach().cpu().numpy()
+        fr, gr, wr = (np.asarray(a.astype(dt_np), np.complex128) for a in (f, g, w))
+        cand = np.where(ms <= 8192)[0]
+        budget = args.cpu_macs  # multiply-adds of the oracle sample
+        cum = np.cumsum(3 * ms[cand] * (ms[cand] + 1) / 2.0)
+        sel = cand[cum <= budget] if cum[0] <= budget else cand[:1]
+        t_or = 0.0
+        macs = 0.0
+        errs = {"h": [], "grad_f": [], "grad_g": []}
+        for j in sel:
+            o, m = offs[j], ms[j]
+            t0 = time.perf_counter()
+            ref = oracle.conv1d_complex(fr[o:o + m], gr[o:o + m])
+            rf, rg = oracle.grad_conv1d_complex(fr[o:o + m], gr[o:o + m], wr[o:o + m])
+            t_or += time.perf_counter() - t0
+            macs += 3 * m * (m + 1) / 2.0
+            for key, got, r in (("h", h_gpu[o:o + m], ref), ("grad_f", gf[o:o + m], rf), ("grad_g", gg[o:o + m], rg)):
+                errs[key].append(float(np.linalg.norm(got - r) / np.linalg.norm(r)))
+        big = np.argsort(ms)[-4:]
+        for j in big:
+            o, m = offs[j], ms[j]
+            ks = np.array([0, 1, m // 2, m - 1])
+            r = oracle.convnd_complex_at(fr[o:o + m], gr[o:o + m], ks[:, None])
+            errs["h"].append(float(np.linalg.norm(h_gpu[o + ks] - r) / np.linalg.norm(r)))
+        full = float(np.sum(3 * ms * (ms + 1) / 2.0))
+        err = {k: {"max": max(v), "median": float(np.median(v)), "pairs": len(v)} for k, v in errs.items()}
+        return {"value": len(ms) / (t_or / macs * full), "unit": "convs/s", "cores": oracle.num_threads(),
+                "kind": "oracle",
+                "sample": f"forward + both gradients of {len(sel)} pairs with m <= 8192, direct FP64 sums "
+                          f"({t_or:.2f} s), extrapolated to the whole step by multiply-add count"}, err
+
+    cfg = {"workload": f"{len(ms)} uneven complex 1D pairs, m = 2^round(U(6,16)), packed, forward + backward "
+                       f"(both gradients) per step, {'complex64' if cdt == torch.complex64 else 'complex128'}",
+           "pairs": int(len(ms)), "sum_m": tot, "dtype": args.dtype}
+    return dict(run=run, explicit=None, convs=len(ms), step_bytes=step_bytes, kbytes_step=kbytes_step,
+                kflops_step=kflops_step, cfg=cfg, cpu=cpu_baseline, out=lambda: run().detach().cpu().numpy())
+
+
+WORKLOADS = {"c1": wl_c1, "c2": wl_c2, "c3": wl_c3, "c4": wl_c4, "c5": wl_c5}
 
 
 def main():
@@ -261,14 +424,16 @@ def main():
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-explicit", action="store_true")
-    ap.add_argument("--cpu-points", type=int, default=2048)
-    ap.add_argument("--cpu-rows", type=int, default=8)
+    # oracle sample sizes (about 10 s of host work each)
+    ap.add_argument("--cpu-points", type=int, default=65536, help="c3: sampled output points over the batch")
+    ap.add_argument("--cpu-rows", type=int, default=0, help="c1/c2: convolutions (0: workload default)")
+    ap.add_argument("--cpu-macs", type=float, default=4e10, help="c5: multiply-add budget")
     ap.add_argument("--profile-copy", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
-              "(the path shards by batch with no exchange; see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the workloads "
+              "shard by batch with no exchange between GPUs, so they are measured on one", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -279,39 +444,71 @@ def main():
 
     # implicit path, with per-launch event timing inside the library
     ms_clean = timed(W["run"], args.steps, args.warmup)  # the timed region of the metric
+    stats = step_stats(W["run"], max(args.steps, 10))
     ic.timing_enable(True)  # second pass: per-launch kernel durations
-    timed(W["run"], args.steps, 1, backlog=True)
+    timed(W["run"], args.steps, 0, backlog=True)
     rep = ic.timing_report()
     ic.timing_enable(False)
     convs_s = W["convs"] * 1000.0 / ms_clean
+    copy_gbs = copy_bandwidth()
 
+    # per-kernel algorithmic bytes and flops: per launch (kbytes / kflops) or
+    # per step (kbytes_step / kflops_step, spread over the step's launches)
     kernels = []
     for r in rep:
-        avg = r["total_ms"] / max(1, r["count"])
-        kernels.append({"name": r["name"], "launches": r["count"], "avg_ms": avg, "total_ms": r["total_ms"]})
-    dom = max(kernels, key=lambda k: k["total_ms"]) if kernels else None
+        cnt = max(1, r["count"])
+        per_step = cnt / args.steps
+        kb = W.get("kbytes", {}).get(r["name"])
+        kf = W.get("kflops", {}).get(r["name"])
+        if kb is None and r["name"] in W.get("kbytes_step", {}):
+            kb = W["kbytes_step"][r["name"]] / per_step
+        if kf is None and r["name"] in W.get("kflops_step", {}):
+            kf = W["kflops_step"][r["name"]] / per_step
+        avg = r["total_ms"] / cnt
+        k = {"name": r["name"], "launches_per_step": round(per_step, 3), "avg_ms": round(avg, 5),
+             "ms_per_step": round(r["total_ms"] / args.steps, 5)}
+        if kb:
+            k["bytes_per_launch"] = int(kb)
+            k["gbs"] = round(kb / (avg * 1e-3) / 1e9, 1)
+        if kf:
+            k["flops_per_launch"] = float(kf)
+            k["tflops"] = round(kf / (avg * 1e-3) / 1e12, 2)
+        kernels.append(k)
+    dom = max(kernels, key=lambda k: k["ms_per_step"]) if kernels else None
     roof = None
     if dom is not None:
-        per_launch = W["kbytes"].get(dom["name"])
         traffic = None
         tf = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{args.dtype}.json")
         if os.path.exists(tf):
             t = json.load(open(tf))
             if t.get("source_hash") == kernel_source_hash() and dom["name"] in t.get("kernels", {}):
                 traffic = t["kernels"][dom["name"]]
-        if per_launch:
-            achieved = per_launch / (dom["avg_ms"] * 1e-3) / 1e9
-            roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom["name"],
-                    "kernel_avg_ms": round(dom["avg_ms"], 5), "algorithmic_bytes_per_launch": per_launch}
+        hbm_frac = dom["gbs"] / HBM_PEAK_GBS if "gbs" in dom else None
+        alu_frac = dom["tflops"] / VALU_PEAK_TFLOPS if "tflops" in dom else None
+        if alu_frac is not None and (hbm_frac is None or alu_frac > hbm_frac):
+            # arithmetic intensity above the ridge point: bound by the vector ALUs
+            roof = {"bound": "alu", "achieved": dom["tflops"], "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(alu_frac, 4), "traffic": traffic, "kernel": dom["name"],
+                    "kernel_avg_ms": dom["avg_ms"], "algorithmic_flops_per_launch": dom["flops_per_launch"],
+                    "frac_of_packed_fp32_peak": (round(dom["tflops"] / VALU_PEAK_PACKED_FP32_TFLOPS, 4)
+                                                 if args.dtype == "c64" else None),
+                    "hbm_view": {"achieved_gbs": dom.get("gbs"), "frac": round(hbm_frac, 4) if hbm_frac else None}}
+        elif hbm_frac is not None:
+            roof = {"bound": "hbm", "achieved": dom["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(hbm_frac, 4), "traffic": traffic, "kernel": dom["name"],
+                    "kernel_avg_ms": dom["avg_ms"], "algorithmic_bytes_per_launch": dom["bytes_per_launch"]}
 
+    alg_gbs = W["step_bytes"] / (ms_clean * 1e-3) / 1e9
     out = {"metric": METRIC, "value": round(convs_s, 2), "unit": "convs/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_clean, 5),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "fp32" if args.dtype == "c64" else "fp64", "data": "synthetic",
-           "config": W["cfg"],
-           "hbm_gbps_algorithmic": round(W["step_bytes"] / (ms_clean * 1e-3) / 1e9, 1),
-           "kernels": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in kk.items()} for kk in kernels],
+           "config": W["cfg"], "step_stats": stats,
+           "hbm_gbps_algorithmic": round(alg_gbs, 1),
+           "hbm_frac_of_peak": round(alg_gbs / HBM_PEAK_GBS, 4),
+           "copy_kernel_gbs": round(copy_gbs, 1),
+           "hbm_frac_of_copy": round(alg_gbs / copy_gbs, 4),
+           "kernels": kernels,
            "roofline": roof}
 
     if W.get("explicit") is not None and not args.no_explicit:
@@ -331,7 +528,10 @@ def main():
 
     if not args.no_cpu:
         h = W["out"]()
-        cpu, err = W["cpu"](h)
+        if W.get("explicit") is not None and not args.no_explicit:
+            cpu, err = W["cpu"](h, W["explicit"]().cpu().numpy())
+        else:
+            cpu, err = W["cpu"](h)
         out["cpu_baseline"] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in cpu.items()}
         out["rel_err_vs_oracle"] = err
     print(json.dumps(out), flush=True)

@@ -283,6 +283,10 @@ class RaggedPlan:
         self.dtype = dtype
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.extent = int((self.ms + self.offsets).max()) if len(self.ms) else 0
+        # pairs tile [0, extent) exactly: every output element is written
+        order = np.argsort(self.offsets, kind="stable")
+        ends = (self.offsets + self.ms)[order]
+        self.dense = bool(len(self.ms) and self.offsets[order][0] == 0 and np.all(self.offsets[order][1:] == ends[:-1]))
         dt = C64 if dtype == torch.complex64 else C128
         self._h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
@@ -300,7 +304,14 @@ class RaggedPlan:
             raise TypeError("dtype differs from the plan's")
         if f.numel() < self.extent or g.numel() < self.extent:
             raise ValueError("packed inputs shorter than the plan's extent")
-        h = torch.zeros_like(f) if out is None else out
+        if out is not None:
+            h = out
+        elif self.dense:
+            h = torch.empty_like(f)
+            if f.numel() > self.extent:
+                h.view(-1)[self.extent:].zero_()
+        else:
+            h = torch.zeros_like(f)
         w = self._work if work is None else work
         _check(lib().impconv_ragged_execute(self._h, _ptr(f), _ptr(g), _ptr(h), _ptr(w), self.work_bytes,
                                             flags, ctypes.c_void_p(_stream(f.device))), "ragged_execute")

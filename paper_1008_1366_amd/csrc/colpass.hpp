@@ -67,6 +67,7 @@ struct ColArgs {
     double scale;
     const void* tw;
     const void* tw3;
+    int ncu;                       // compute units of the device (persistent grids)
 };
 
 // Columns per tile: a 64-byte row segment (8 complex64 / 4 complex128), up to
@@ -337,6 +338,254 @@ k_colpass(ColArgs a)
         for (int e = 0; e < E; ++e) {
             const int k = t + e * G;
             if (k < a.n_out) strow(0, k, scale(x[e], s));
+        }
+    }
+}
+
+// ------------------------------------------------------------------ buffer loads
+// Raw buffer loads through a buffer resource (base address, num_records in
+// bytes, in scalar registers): a byte offset past num_records reads zero
+// without touching memory, which gives zero padding and masked columns with
+// neither a branch nor a select, so all of a thread's loads stay in one
+// basic block and the waitcnt pass can count them exactly.
+typedef int i32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+__device__ f32x2_t raw_buffer_load_f32x2(i32x4_t rsrc, int voff, int soff, int aux)
+    __asm("llvm.amdgcn.raw.buffer.load.v2f32");
+__device__ f64x2_t raw_buffer_load_f64x2(i32x4_t rsrc, int voff, int soff, int aux)
+    __asm("llvm.amdgcn.raw.buffer.load.v2f64");
+__device__ void raw_buffer_store_f32x2(f32x2_t v, i32x4_t rsrc, int voff, int soff, int aux)
+    __asm("llvm.amdgcn.raw.buffer.store.v2f32");
+__device__ void raw_buffer_store_f64x2(f64x2_t v, i32x4_t rsrc, int voff, int soff, int aux)
+    __asm("llvm.amdgcn.raw.buffer.store.v2f64");
+
+constexpr uint32_t kBufRecords = 0x7fffffffu;  // bytes addressable through a resource
+constexpr uint32_t kBufOff = 0x80000000u;      // an offset that reads zero / drops a write
+
+// Resource for the wave-uniform base p.  Word 3 selects a valid 32-bit data
+// format with identity swizzle, as raw loads on gfx9-family parts require.
+__device__ __forceinline__ i32x4_t buf_rsrc(const void* p)
+{
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    i32x4_t r;
+    r.x = __builtin_amdgcn_readfirstlane(int(uint32_t(a)));
+    r.y = __builtin_amdgcn_readfirstlane(int(uint32_t(a >> 32) & 0xffffu));  // stride 0
+    r.z = int(kBufRecords);
+    r.w = 0x00020000;
+    return r;
+}
+template <typename T>
+__device__ __forceinline__ C<T> buf_load(i32x4_t r, uint32_t off)
+{
+    if constexpr (sizeof(T) == 4) {
+        const f32x2_t v = raw_buffer_load_f32x2(r, int(off), 0, 0);
+        return C<T>{v.x, v.y};
+    } else {
+        const f64x2_t v = raw_buffer_load_f64x2(r, int(off), 0, 0);
+        return C<T>{v.x, v.y};
+    }
+}
+template <typename T>
+__device__ __forceinline__ void buf_store(i32x4_t r, uint32_t off, C<T> v)
+{
+    if constexpr (sizeof(T) == 4) {
+        f32x2_t w;
+        w.x = v.re;
+        w.y = v.im;
+        raw_buffer_store_f32x2(w, r, int(off), 0, 0);
+    } else {
+        f64x2_t w;
+        w.x = v.re;
+        w.y = v.im;
+        raw_buffer_store_f64x2(w, r, int(off), 0, 0);
+    }
+}
+
+// ------------------------------------------------------------------ persistent form
+// For long columns one tile fills the LDS of a compute unit, so a one-tile
+// workgroup leaves the CU idle while it waits for its loads.  k_colpipe is
+// the persistent form of kPadBwd / kPadFwd for that case: one workgroup per
+// CU walks a sequence of tiles.  The backward pass issues the next tile's
+// loads before the current tile's second transform; the forward pass loads
+// both of its inputs up front, so the second one arrives during the first
+// transform (a cross-tile prefetch there would need a third tile-sized
+// register array).  Prefetched loads must not be followed by global twiddle
+// loads (vector-memory loads return in order, so waiting for a twiddle would
+// wait for the prefetch too), hence the stage twiddles come from a copy of
+// zeta_N in LDS, and the residue shift zeta_{2N}^{t + eG} is formed as
+// zeta_{2N}^t zeta_N^{eG/2}.
+
+// zeta_N^j (j < N) from an LDS table that holds the first Q / 4 of it:
+// Q = 4 the whole table, Q = 2 the first half (zeta_N^{j + N/2} = -zeta_N^j).
+template <typename T, int N, int Q>
+struct LdsTw {
+    const C<T>* p;
+    __device__ __forceinline__ LdsTw operator+(int z) const { return LdsTw{p + z}; }
+    __device__ __forceinline__ C<T> operator[](int j) const
+    {
+        static_assert(Q == 4 || Q == 2, "LDS twiddle table: whole or half");
+        if constexpr (Q == 4) {
+            return p[j];
+        } else {
+            const C<T> v = p[j & (N / 2 - 1)];
+            return (j & (N / 2)) ? C<T>{-v.re, -v.im} : v;
+        }
+    }
+};
+
+// Quarters of zeta_N that fit in LDS beside the exchange tile (0: none).
+template <typename T>
+__host__ __device__ constexpr int pipe_twq(int N)
+{
+    const int cs = int(sizeof(C<T>));
+    const int ex = N > fft_E<T>(N) ? lpad_size(N) * col_TC<T>(N) * cs : 0;
+    return ex + N * cs <= 160 * 1024 ? 4 : ex + (N / 2) * cs <= 160 * 1024 ? 2 : 0;
+}
+// The pipelined form pays off where the exchange tile leaves room for only
+// one workgroup per CU.
+template <typename T>
+__host__ __device__ constexpr bool pipe_ok(int N)
+{
+    return N > fft_E<T>(N) && lpad_size(N) * col_TC<T>(N) * int(sizeof(C<T>)) > 80 * 1024 && pipe_twq<T>(N) > 0;
+}
+
+template <typename T, int N, int MODE>
+__global__ void __launch_bounds__(col_block<T>(N))
+k_colpipe(ColArgs a)
+{
+    static_assert(MODE == kPadBwd || MODE == kPadFwd, "pipelined pass: padded modes only");
+    constexpr int E = fft_E<T>(N), G = N / E, TC = col_TC<T>(N);
+    constexpr int LDSN = lpad_size(N) * TC;
+    constexpr int TWQ = pipe_twq<T>(N);
+    constexpr int TWN = TWQ * N / 4;
+    static_assert(TWQ > 0 && G % 2 == 0, "pipelined pass needs room for the twiddle table");
+    __shared__ C<T> sh[LDSN + TWN];
+    static_assert(sizeof(sh) <= 160 * 1024, "LDS footprint exceeds 160 KB");
+
+    // This workgroup's tiles: the tiles are split into 8 contiguous ranges,
+    // one per XCD (workgroups are dealt to the XCDs round-robin), and the
+    // workgroups of an XCD walk its range in lockstep so that neighbouring
+    // tiles, which share cache lines, are in flight together.
+    const int64_t ntile = (a.ncols + TC - 1) / TC;
+    const int64_t total = a.nslab * ntile;
+    const int64_t per = (total + 7) / 8;
+    const int64_t xcd = blockIdx.x % 8, nw = gridDim.x / 8;
+    const int64_t end = total < (xcd + 1) * per ? total : (xcd + 1) * per;
+    const int64_t first = xcd * per + blockIdx.x / 8;
+    if (first >= end) return;  // whole workgroup: no barrier is reached
+    const int niter = int((end - first + nw - 1) / nw);
+
+    const int col = threadIdx.x % TC, t = threadIdx.x / TC;
+    const C<T>* twg = (const C<T>*)a.tw;
+    for (int j = threadIdx.x; j < TWN; j += blockDim.x) sh[LDSN + j] = twg[tw_off(N) + j];
+    const C<T> zt = twg[tw_off(2 * N) + t];  // zeta_{2N}^t
+    __syncthreads();
+    const LdsTw<T, N, TWQ> tw{sh + LDSN};
+    C<T>* lds = sh + col;
+    const int64_t in_ld = a.in_ld, out_ld = a.out_ld;
+
+    // Tile it of the sequence: element offsets of its first column (wave
+    // uniform) in the input and output arrays, and the rows this thread
+    // loads and stores (0 for a column past the end, for loads also a
+    // masked column or it past the sequence).  This thread's byte offsets
+    // within a tile, (col + t ld) * sizeof(C<T>), are the same for every tile.
+    struct Tile {
+        int64_t ib, ob;
+        int nr, nw;
+    };
+    auto tile_at = [&](int it, int nrows) {
+        const int64_t q = first + int64_t(it < niter ? it : niter - 1) * nw;
+        const int64_t slab = q / ntile, tile = q - slab * ntile;
+        const int64_t s1 = slab / a.nsub, s2 = slab - s1 * a.nsub;
+        const int64_t c = tile * TC + col;
+        const bool cin = c < a.ncols;
+        bool cact = cin && it < niter;
+        if (a.mask_nz > 0) {
+            const int64_t cc = cin ? c : 0;
+            const int64_t iy = cc / a.mask_nz, iz = cc - iy * a.mask_nz;
+            cact = cact && iy >= a.mask_ylo && iy < a.mask_yhi && iz < a.mask_zhi;
+        }
+        Tile r;
+        r.nr = cact ? nrows : 0;
+        r.nw = cin ? N : 0;
+        r.ib = s1 * a.in_bs + s2 * a.in_bs2 + tile * TC;
+        r.ob = s1 * a.out_bs + s2 * a.out_bs2 + tile * TC;
+        return r;
+    };
+    const uint32_t ioff = uint32_t((col + int64_t(t) * in_ld) * int64_t(sizeof(C<T>)));
+    const uint32_t ooff = uint32_t((col + int64_t(t) * out_ld) * int64_t(sizeof(C<T>)));
+    const uint32_t istep = uint32_t(int64_t(G) * in_ld * int64_t(sizeof(C<T>)));
+    const uint32_t ostep = uint32_t(int64_t(G) * out_ld * int64_t(sizeof(C<T>)));
+    // rows t + eG of in[q] for this thread's column, zero at rows >= nr.
+    // (The thread offset goes through an empty asm so the compiler forms the
+    // E offsets at each use instead of hoisting all of them out of the tile
+    // loop, where they would hold E registers for the whole kernel.)
+    auto load = [&](C<T> (&v)[E], int q, const Tile& tl, int nr) {
+        const i32x4_t rs = buf_rsrc((const C<T>*)a.in[q] + tl.ib);
+        uint32_t off = ioff;
+        asm volatile("" : "+v"(off));
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = buf_load<T>(rs, t + e * G < nr ? off + uint32_t(e) * istep : kBufOff);
+    };
+    // rows t + eG of out[q] where keep(e) holds
+    auto store = [&](const C<T> (&v)[E], int q, const Tile& tl, auto keep) {
+        const i32x4_t rs = buf_rsrc((C<T>*)a.out[q] + tl.ob);
+        uint32_t off = ooff;
+        asm volatile("" : "+v"(off));
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            buf_store<T>(rs, t + e * G < tl.nw && keep(e) ? off + uint32_t(e) * ostep : kBufOff, v[e]);
+    };
+    // zeta_{2N}^{t + eG}
+    auto shift = [&](int e) { return e == 0 ? zt : zt * tw[e * (G / 2)]; };
+
+    // The backward loop is rotated so that the wait for a prefetched tile
+    // sits inside the loop body, after a fixed number of later memory
+    // operations: at a loop header the waitcnt pass would have to merge the
+    // prologue's state with the back edge's and wait for everything.
+    auto all = [](int) { return true; };
+    Tile cur = tile_at(0, MODE == kPadBwd ? a.m : N);
+    C<T> x[E];
+    if constexpr (MODE == kPadBwd) {
+        C<T> xn[E];
+        // residue 0: FFT+(U); residue 1: FFT+(zeta_{2N}^k U_k)
+        auto residue0 = [&]() {
+            C<T> y[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) y[e] = x[e];
+            fft<T, N, E, +1>(y, t, lds, TC, tw);
+            store(y, 0, cur, all);
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[e] = x[e] * shift(e);
+        };
+        load(x, 0, cur, cur.nr);
+        residue0();
+        for (int it = 0;; ++it) {
+            const Tile nxt = tile_at(it + 1, a.m);
+            load(xn, 0, nxt, nxt.nr);
+            fft<T, N, E, +1>(x, t, lds, TC, tw);
+            store(x, 1, cur, all);
+            if (it + 1 >= niter) break;
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[e] = xn[e];
+            cur = nxt;
+            residue0();
+        }
+    } else {
+        // out_k = s (F0_k + zeta_{2N}^{-k} F1_k), k < m
+        const T s = T(a.scale);
+        const int m = a.m;
+        C<T> y[E];
+        for (int it = 0; it < niter; ++it) {
+            load(x, 0, cur, cur.nr);
+            load(y, 1, cur, cur.nr);
+            fft<T, N, E, -1>(x, t, lds, TC, tw);
+            fft<T, N, E, -1>(y, t, lds, TC, tw);
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[e] = scale(x[e] + mulc(y[e], shift(e)), s);
+            store(x, 0, cur, [&](int e) { return t + e * G < m; });
+            cur = tile_at(it + 1, N);
         }
     }
 }

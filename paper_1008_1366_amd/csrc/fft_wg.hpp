@@ -129,8 +129,8 @@ template <int DIR, typename T> struct DFT<16, DIR, T> {
 // two) and writes at base + r NS (base mod 16 < 16 - (R-1) NS mod 16) -- so
 // each butterfly computes one padded base and every element adds a
 // compile-time offset (an immediate in the LDS instruction).
-template <typename T, int N, int E, int DIR, int NS>
-__device__ __forceinline__ void fft_stage(C<T> (&v)[E], int t, C<T>* lds, int LS, const C<T>* __restrict__ tw)
+template <typename T, int N, int E, int DIR, int NS, typename TW>
+__device__ __forceinline__ void fft_stage(C<T> (&v)[E], int t, C<T>* lds, int LS, TW tw)
 {
     constexpr int R = (N / NS < E) ? (N / NS) : E;
     constexpr bool LAST = (NS * R == N);
@@ -146,7 +146,7 @@ __device__ __forceinline__ void fft_stage(C<T> (&v)[E], int t, C<T>* lds, int LS
     int zoff = 0;
     asm volatile("" : "+s"(zoff));
     asm volatile("" : "+v"(t));
-    const C<T>* tws = tw + zoff;
+    const TW tws = tw + zoff;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int b = t + q * G;
@@ -175,7 +175,7 @@ __device__ __forceinline__ void fft_stage(C<T> (&v)[E], int t, C<T>* lds, int LS
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i] = rp[(i * G + ((i * G) >> 4)) * LS];
         __syncthreads();
-        fft_stage<T, N, E, DIR, NS * R>(v, t, lds, LS, tw);
+        fft_stage<T, N, E, DIR, NS * R, TW>(v, t, lds, LS, tw);
     }
 }
 
@@ -183,9 +183,9 @@ __device__ __forceinline__ void fft_stage(C<T> (&v)[E], int t, C<T>* lds, int LS
 // stage together: one set of twiddle loads and one pair of barriers per
 // stage serves both, and the two butterfly streams interleave to hide LDS
 // latency.  lds0 / lds1 are two disjoint exchange buffers.
-template <typename T, int N, int E, int DIR, int NS>
+template <typename T, int N, int E, int DIR, int NS, typename TW>
 __device__ __forceinline__ void fft2_stage(C<T> (&v0)[E], C<T> (&v1)[E], int t, C<T>* lds0, C<T>* lds1,
-                                           int LS, const C<T>* __restrict__ tw)
+                                           int LS, TW tw)
 {
     constexpr int R = (N / NS < E) ? (N / NS) : E;
     constexpr bool LAST = (NS * R == N);
@@ -194,7 +194,7 @@ __device__ __forceinline__ void fft2_stage(C<T> (&v0)[E], C<T> (&v1)[E], int t, 
     int zoff = 0;
     asm volatile("" : "+s"(zoff));
     asm volatile("" : "+v"(t));
-    const C<T>* tws = tw + zoff;
+    const TW tws = tw + zoff;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int b = t + q * G;
@@ -240,24 +240,26 @@ __device__ __forceinline__ void fft2_stage(C<T> (&v0)[E], C<T> (&v1)[E], int t, 
             v1[i] = lds1[rb + (i * G + ((i * G) >> 4)) * LS];
         }
         __syncthreads();
-        fft2_stage<T, N, E, DIR, NS * R>(v0, v1, t, lds0, lds1, LS, tw);
+        fft2_stage<T, N, E, DIR, NS * R, TW>(v0, v1, t, lds0, lds1, LS, tw);
     }
 }
 
-template <typename T, int N, int E, int DIR>
+template <typename T, int N, int E, int DIR, typename TW>
 __device__ __forceinline__ void fft2(C<T> (&v0)[E], C<T> (&v1)[E], int t, C<T>* lds0, C<T>* lds1, int LS,
-                                     const C<T>* __restrict__ tw)
+                                     TW tw)
 {
-    if constexpr (N > 1) fft2_stage<T, N, E, DIR, 1>(v0, v1, t, lds0, lds1, LS, tw);
+    if constexpr (N > 1) fft2_stage<T, N, E, DIR, 1, TW>(v0, v1, t, lds0, lds1, LS, tw);
 }
 
 // Full FFT.  All threads of the workgroup must call this together (it
-// contains workgroup barriers whenever N > E).  tw points at tw_N.
-template <typename T, int N, int E, int DIR>
-__device__ __forceinline__ void fft(C<T> (&v)[E], int t, C<T>* lds, int LS, const C<T>* __restrict__ tw)
+// contains workgroup barriers whenever N > E).  tw is the twiddle source
+// zeta_N^j: a pointer to tw_N in global memory, or any type with the same
+// `tw + offset` and `tw[j]` operations (LdsTw below).
+template <typename T, int N, int E, int DIR, typename TW>
+__device__ __forceinline__ void fft(C<T> (&v)[E], int t, C<T>* lds, int LS, TW tw)
 {
     static_assert(N % E == 0, "E must divide N");
-    if constexpr (N > 1) fft_stage<T, N, E, DIR, 1>(v, t, lds, LS, tw);
+    if constexpr (N > 1) fft_stage<T, N, E, DIR, 1, TW>(v, t, lds, LS, tw);
 }
 
 // Compile-time loop: f(std::integral_constant<int, i>{}) for i = 0..n-1.

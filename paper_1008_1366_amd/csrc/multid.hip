@@ -33,6 +33,7 @@ ColArgs col_args(const DevTables& tb, int dt)
     a.nsub = 1;
     a.tw = tb.tw[dt];
     a.tw3 = tb.tw3[dt];
+    a.ncu = tb.ncu;
     a.scale = 1.0;
     return a;
 }

@@ -17,6 +17,7 @@ constexpr int kTw3Log = 16;
 struct DevTables {
     const void* tw[2];   // [0] complex64, [1] complex128: concatenated zeta_N^j, offset N - 1
     const void* tw3[2];  // concatenated zeta_{3N}^j (j < N), offset N - 1
+    int ncu;             // compute units
 };
 
 // Tables of the current device, created on first use (FP64 on the host,

@@ -98,6 +98,10 @@ const DevTables* tables()
         gen_roots(3 * N, N, tw3.data() + 2 * (N - 1));
     }
     DevTables t{};
+    if ((e = hipDeviceGetAttribute(&t.ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) {
+        hip_fail(e, "hipDeviceGetAttribute");
+        return nullptr;
+    }
     if ((e = upload<float>(tw, &t.tw[0])) != hipSuccess ||
         (e = upload<double>(tw, &t.tw[1])) != hipSuccess ||
         (e = upload<float>(tw3, &t.tw3[0])) != hipSuccess ||

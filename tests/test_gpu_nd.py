@@ -118,6 +118,34 @@ def test_complex_2d_c3_workload(dt):
 
 
 @pytest.mark.parametrize("dt", DT)
+def test_complex_2d_long_columns_ragged(dt):
+    """Long outer axis (m0 = 1500 -> N0 = 2048, the persistent column-pass
+    form), ragged inner axis (700 columns: a partial last tile), M = 2,
+    enough tiles that workgroups walk uneven tile sequences.  Sampled outputs
+    vs the oracle; pair 0 is rank one and checked on the full field against
+    outer products of 1D oracle results."""
+    ic = need_gpu()
+    say(f"complex2d long columns {dt.__name__}")
+    B, M, m0, m1 = 3, 2, 1500, 700
+    f = synth.unit_disk((B, M, m0, m1), 71)
+    g = synth.unit_disk((B, M, m0, m1), 72)
+    vec = [synth.unit_disk(n, s) for n, s in ((m0, 73), (m1, 74), (m0, 75), (m1, 76))]
+    for i in range(M):
+        f[0, i] = np.outer(vec[0], vec[1]) * (i + 1)
+        g[0, i] = np.outer(vec[2], vec[3])
+    h = ic.conv2d(to_dev(f, dt), to_dev(g, dt)).cpu().numpy()
+    rng = synth.rng(77)
+    pts = np.concatenate([[[0, 0], [m0 - 1, m1 - 1], [m0 - 1, 0], [0, m1 - 1], [1024, 696]],
+                          np.stack([rng.integers(0, m0, 8), rng.integers(0, m1, 8)], 1)])
+    for b in range(1, B):
+        ref = sum(oracle.convnd_complex_at(rounded(f[b, i], dt), rounded(g[b, i], dt), pts) for i in range(M))
+        assert rel(h[b][pts[:, 0], pts[:, 1]], ref) < TOL[dt], b
+    va, vb, vc, vd = vec
+    full = sum((i + 1) for i in range(M)) * np.outer(oracle.conv1d_complex(va, vc), oracle.conv1d_complex(vb, vd))
+    assert rel(h[0], full) < TOL[dt]
+
+
+@pytest.mark.parametrize("dt", DT)
 def test_hermitian_3d_c4_workload(dt):
     """512 x 512 x 257 storage (m = 256 per axis, zero slots), M = 3 pairs,
     |k|^-11/6 random-phase spectra; sampled outputs vs the oracle."""
