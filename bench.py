@@ -341,7 +341,10 @@ def wl_c5(args):
     F = torch.from_numpy(f).to("cuda", cdt).requires_grad_(True)
     G = torch.from_numpy(g).to("cuda", cdt).requires_grad_(True)
     Wt = torch.from_numpy(w).to("cuda", cdt)
-    plan = ic.RaggedPlan(ms, offs, dtype=cdt)
+    # schedule: the four-step split of each long class is autotuned at plan
+    # creation, outside the timed region
+    plan = ic.RaggedPlan(ms, offs, dtype=cdt, autotune=not args.no_autotune)
+    sched = [{k: c[k] for k in ("N", "pairs", "method", "N1", "N2") if k in c} for c in plan.schedule()]
     cs = 8 if cdt == torch.complex64 else 16
 
     def run():
@@ -406,7 +409,8 @@ def wl_c5(args):
 
     cfg = {"workload": f"{len(ms)} uneven complex 1D pairs, m = 2^round(U(6,16)), packed, forward + backward "
                        f"(both gradients) per step, {'complex64' if cdt == torch.complex64 else 'complex128'}",
-           "pairs": int(len(ms)), "sum_m": tot, "dtype": args.dtype}
+           "pairs": int(len(ms)), "sum_m": tot, "dtype": args.dtype, "schedule": sched,
+           "autotuned": not args.no_autotune}
     return dict(run=run, explicit=None, convs=len(ms), step_bytes=step_bytes, kbytes_step=kbytes_step,
                 kflops_step=kflops_step, cfg=cfg, cpu=cpu_baseline, out=lambda: run().detach().cpu().numpy())
 
@@ -424,6 +428,7 @@ def main():
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-explicit", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="c5: keep the default four-step splits")
     # oracle sample sizes (about 10 s of host work each)
     ap.add_argument("--cpu-points", type=int, default=65536, help="c3: sampled output points over the batch")
     ap.add_argument("--cpu-rows", type=int, default=0, help="c1/c2: convolutions (0: workload default)")

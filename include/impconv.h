@@ -182,9 +182,10 @@ impconv_status impconv_conv3d(int kind, int dtype, int64_t batch, int64_t M, con
  * arrays (pairs must not overlap).  The plan copies the descriptors to the
  * device once (synchronously, at creation) and groups pairs by FFT size;
  * executing it launches nothing but kernels, so it may be captured in a
- * hipGraph.  The plan is immutable; concurrent executions need distinct
- * workspaces.  REV_F / CONJ_G / REV_OUT apply per pair as in
- * impconv_conv1d_complex.
+ * hipGraph.  Only impconv_ragged_plan_autotune changes a plan (its schedule,
+ * never its results' definition); it must not overlap executions of the
+ * same plan.  Concurrent executions need distinct workspaces.  REV_F /
+ * CONJ_G / REV_OUT apply per pair as in impconv_conv1d_complex.
  * ---------------------------------------------------------------------- */
 typedef struct impconv_ragged_plan impconv_ragged_plan;
 
@@ -195,6 +196,30 @@ impconv_status impconv_ragged_execute(const impconv_ragged_plan* plan, const voi
                                       const void* g, void* h, void* work, size_t work_bytes,
                                       uint32_t flags, void* stream);
 impconv_status impconv_ragged_plan_destroy(impconv_ragged_plan* plan);
+
+/* Autotuner of the plan's schedule.  Size classes whose FFT size N exceeds
+ * one workgroup's transform (N > 8192) run the four-step form, whose split
+ * N = N1 x N2 sets the FFT sizes (and radices) of its row and column passes.
+ * For each such class this call times every supported split (16 <= N2 <=
+ * 4096, 16 <= N1 <= 8192) on zero-filled temporary arrays of the plan's
+ * packed extent, three executions each after one warm-up, on `stream`, and
+ * keeps the fastest in the plan.  It allocates and frees device memory
+ * (3 x extent elements plus the workspace size) and synchronizes the stream:
+ * call it outside graph capture.  Results of a tuned plan equal those of the
+ * untuned one up to rounding.  Errors: E_ARG (null plan, other device),
+ * E_HIP (allocation, launch or timing failure; the plan keeps its previous
+ * schedule for the classes not yet tuned).  A plan without four-step classes
+ * returns IMPCONV_OK at once. */
+impconv_status impconv_ragged_plan_autotune(impconv_ragged_plan* plan, void* stream);
+
+/* The plan's schedule as JSON text: one object per size class, longest
+ * first, with its FFT size N, pair count, method ("fused" or "four-step"),
+ * the split N1, N2 in use and the autotuner's times per candidate N2 (ms).
+ * Writes at most cap - 1 characters and a terminating NUL to buf (buf may be
+ * NULL with cap 0) and the full length to *len.  Errors: E_ARG (null plan or
+ * len). */
+impconv_status impconv_ragged_plan_schedule(const impconv_ragged_plan* plan, char* buf, size_t cap,
+                                            size_t* len);
 
 #ifdef __cplusplus
 }

@@ -84,6 +84,8 @@ def lib():
             "impconv_ragged_workspace": ([_p, ctypes.POINTER(_sz)], st),
             "impconv_ragged_execute": ([_p, _p, _p, _p, _p, _sz, _u32, _p], st),
             "impconv_ragged_plan_destroy": ([_p], st),
+            "impconv_ragged_plan_autotune": ([_p, _p], st),
+            "impconv_ragged_plan_schedule": ([_p, ctypes.c_char_p, _sz, ctypes.POINTER(_sz)], st),
             "impconv_timing_enable": ([ctypes.c_int], None),
             "impconv_timing_report": ([ctypes.c_char_p, _sz], _sz),
         }
@@ -276,7 +278,7 @@ class RaggedPlan:
     """Uneven-length batch of complex 1D convolutions packed in one array:
     pair j uses elements offsets[j] .. offsets[j] + ms[j] - 1."""
 
-    def __init__(self, ms, offsets, dtype=torch.complex64, device=None):
+    def __init__(self, ms, offsets, dtype=torch.complex64, device=None, autotune: bool = False):
         import numpy as np
         self.ms = np.ascontiguousarray(np.asarray(ms, dtype=np.int64))
         self.offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
@@ -297,6 +299,24 @@ class RaggedPlan:
         _check(lib().impconv_ragged_workspace(self._h, ctypes.byref(out)), "impconv_ragged_workspace")
         self.work_bytes = out.value
         self._work = _work(self.work_bytes, self.device)
+        if autotune:
+            self.autotune()
+
+    def autotune(self):
+        """Time every supported four-step split of the long size classes on
+        this device and keep the fastest (synchronous; not under capture)."""
+        with torch.cuda.device(self.device):
+            _check(lib().impconv_ragged_plan_autotune(self._h, ctypes.c_void_p(_stream(self.device))),
+                   "impconv_ragged_plan_autotune")
+
+    def schedule(self) -> list:
+        """Per size class: N, pair count, method, split and autotuner times."""
+        import json
+        n = _sz()
+        _check(lib().impconv_ragged_plan_schedule(self._h, None, 0, ctypes.byref(n)), "schedule")
+        buf = ctypes.create_string_buffer(n.value + 1)
+        _check(lib().impconv_ragged_plan_schedule(self._h, buf, n.value + 1, ctypes.byref(n)), "schedule")
+        return json.loads(buf.value.decode())
 
     def execute(self, f, g, flags: int = 0, out=None, work=None):
         _dev(f, g)

@@ -63,6 +63,14 @@ void fourstep_split(int64_t N, int64_t* N1, int64_t* N2)
     *N1 = N / *N2;
 }
 
+std::vector<int64_t> fourstep_splits(int64_t N)
+{
+    std::vector<int64_t> v;
+    for (int64_t n2 = 16; n2 <= kColMax && n2 < N; n2 *= 2)
+        if (N / n2 <= kRowMax && N / n2 >= 16) v.push_back(n2);
+    return v;
+}
+
 impconv_status large1d_plan(int dt, int64_t batch, int64_t M, int64_t m, size_t* work)
 {
     const int64_t N = next_pow2(m);
@@ -80,10 +88,14 @@ impconv_status large1d_plan(int dt, int64_t batch, int64_t M, int64_t m, size_t*
 static impconv_status fourstep(const DevTables& tb, int dt, int64_t batch, int64_t M, int64_t m,
                                int64_t N, const void* f, const void* g, void* h, void* work,
                                const int64_t* d_off, const int64_t* d_m, uint32_t flags,
-                               hipStream_t s)
+                               hipStream_t s, int64_t n2 = 0)
 {
     int64_t N1, N2;
     fourstep_split(N, &N1, &N2);
+    if (n2 > 0) {
+        N2 = n2;
+        N1 = N / n2;
+    }
     const size_t cs = csize(dt);
     char* w = static_cast<char*>(work);
     const size_t arr = size_t(batch) * M * N * cs;
@@ -155,9 +167,9 @@ impconv_status large1d_run(const DevTables& tb, int dt, int64_t batch, int64_t M
 impconv_status large1d_run_ragged(const DevTables& tb, int dt, int64_t count, int64_t N, int64_t maxm,
                                   const void* f, const void* g, void* h, void* work,
                                   const int64_t* d_off, const int64_t* d_m, uint32_t flags,
-                                  hipStream_t s)
+                                  hipStream_t s, int64_t n2)
 {
-    return fourstep(tb, dt, count, 1, maxm, N, f, g, h, work, d_off, d_m, flags, s);
+    return fourstep(tb, dt, count, 1, maxm, N, f, g, h, work, d_off, d_m, flags, s, n2);
 }
 
 // ------------------------------------------------------------------ nD

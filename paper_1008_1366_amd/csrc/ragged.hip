@@ -8,7 +8,13 @@
 // Classes are issued longest first so the long multi-pass classes start
 // while the GPU is empty.  Execution performs no allocation, copy or
 // synchronization, so it can be captured in a hipGraph.
+//
+// Autotuning (impconv_ragged_plan_autotune, outside any capture): for every
+// four-step class the plan times each supported split N = N1 x N2 (the row
+// and column FFT sizes, hence the radix schedule of both passes) on
+// temporary arrays of the plan's packed shape and keeps the fastest.
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <string>
@@ -28,6 +34,8 @@ struct impconv_ragged_plan {
         int64_t N, count, maxm;
         const int64_t* d_off;
         const int64_t* d_m;
+        int64_t n2;                       // four-step column length (0: default split)
+        std::vector<std::pair<int64_t, double>> tuned;  // (n2, ms) measured by the autotuner
     };
     std::vector<Class> classes;
     void* dmem;
@@ -102,7 +110,7 @@ impconv_status impconv_ragged_plan_create(int dtype, int64_t npairs, const int64
         }
     }
     const int64_t* d = static_cast<const int64_t*>(p->dmem);
-    for (const auto& q : pend) p->classes.push_back({q.N, q.count, q.maxm, d + q.off_at, d + q.m_at});
+    for (const auto& q : pend) p->classes.push_back({q.N, q.count, q.maxm, d + q.off_at, d + q.m_at, 0, {}});
     *plan = p;
     return IMPCONV_OK;
 }
@@ -157,9 +165,111 @@ impconv_status impconv_ragged_execute(const impconv_ragged_plan* p, const void* 
             HIPCHK(launch_row_complex(p->dt, int(c.N), a, s), "ragged row class");
         } else {
             impconv_status st = large1d_run_ragged(*tb, p->dt, c.count, c.N, c.maxm, f, g, h, work,
-                                                   c.d_off, c.d_m, flags, s);
+                                                   c.d_off, c.d_m, flags, s, c.n2);
             if (st) return st;
         }
+    }
+    return IMPCONV_OK;
+}
+
+impconv_status impconv_ragged_plan_autotune(impconv_ragged_plan* p, void* stream)
+{
+    if (!p) return fail(IMPCONV_E_ARG, "plan is NULL");
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    if (dev != p->device) return fail(IMPCONV_E_ARG, "plan was created on another device");
+    bool any = false;
+    for (const auto& c : p->classes) any = any || c.N > kRowMax;
+    if (!any) return IMPCONV_OK;
+    const DevTables* tb = tables();
+    if (!tb) return IMPCONV_E_HIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t cs = p->dt ? 16 : 8;
+    const size_t bytes = size_t(p->extent) * cs;
+    void *f = nullptr, *g = nullptr, *h = nullptr, *w = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    impconv_status st = IMPCONV_OK;
+    auto cleanup = [&]() {
+        for (void* q : {f, g, h, w})
+            if (q) (void)hipFree(q);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    hipError_t e = hipMalloc(&f, bytes);
+    if (e == hipSuccess) e = hipMalloc(&g, bytes);
+    if (e == hipSuccess) e = hipMalloc(&h, bytes);
+    if (e == hipSuccess) e = hipMalloc(&w, std::max<size_t>(p->work, 256));
+    if (e == hipSuccess) e = hipMemsetAsync(f, 0, bytes, s);
+    if (e == hipSuccess) e = hipMemsetAsync(g, 0, bytes, s);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "autotune buffers");
+    }
+    for (auto& c : p->classes) {
+        if (c.N <= kRowMax) continue;
+        c.tuned.clear();
+        double best = 1e30;
+        int64_t best_n2 = 0;
+        for (int64_t n2 : fourstep_splits(c.N)) {
+            constexpr int reps = 3;
+            for (int r = 0; r <= reps && !st; ++r) {
+                if (r == 1 && (e = hipEventRecord(e0, s)) != hipSuccess) st = hip_fail(e, "autotune event");
+                if (!st) st = large1d_run_ragged(*tb, p->dt, c.count, c.N, c.maxm, f, g, h, w, c.d_off, c.d_m, 0, s, n2);
+            }
+            float ms = 0;
+            if (!st && (e = hipEventRecord(e1, s)) != hipSuccess) st = hip_fail(e, "autotune event");
+            if (!st && (e = hipEventSynchronize(e1)) != hipSuccess) st = hip_fail(e, "autotune sync");
+            if (!st && (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) st = hip_fail(e, "autotune timing");
+            if (st) break;
+            const double t = double(ms) / reps;
+            c.tuned.push_back({n2, t});
+            if (t < best) {
+                best = t;
+                best_n2 = n2;
+            }
+        }
+        if (st) break;
+        c.n2 = best_n2;
+    }
+    cleanup();
+    return st;
+}
+
+impconv_status impconv_ragged_plan_schedule(const impconv_ragged_plan* p, char* buf, size_t cap, size_t* len)
+{
+    if (!p || !len) return fail(IMPCONV_E_ARG, "null argument");
+    std::string js = "[";
+    for (size_t i = 0; i < p->classes.size(); ++i) {
+        const auto& c = p->classes[i];
+        int64_t N1 = 0, N2 = 0;
+        if (c.N > kRowMax) {
+            fourstep_split(c.N, &N1, &N2);
+            if (c.n2) {
+                N2 = c.n2;
+                N1 = c.N / c.n2;
+            }
+        }
+        js += (i ? "," : "") + std::string("{\"N\":") + std::to_string(c.N) + ",\"pairs\":" + std::to_string(c.count) +
+              ",\"method\":\"" + (c.N <= kRowMax ? "fused" : "four-step") + "\"";
+        if (c.N > kRowMax) {
+            js += ",\"N1\":" + std::to_string(N1) + ",\"N2\":" + std::to_string(N2) + ",\"tuned_ms\":{";
+            for (size_t j = 0; j < c.tuned.size(); ++j) {
+                char t[64];
+                std::snprintf(t, sizeof(t), "%s\"%lld\":%.5f", j ? "," : "", (long long)c.tuned[j].first, c.tuned[j].second);
+                js += t;
+            }
+            js += "}";
+        }
+        js += "}";
+    }
+    js += "]";
+    *len = js.size();
+    if (buf && cap > 0) {
+        const size_t n = std::min(cap - 1, js.size());
+        std::memcpy(buf, js.data(), n);
+        buf[n] = 0;
     }
     return IMPCONV_OK;
 }

@@ -131,6 +131,70 @@ __device__ __forceinline__ C<T> ldz(const C<T>* U, int j, int m)
 // size-N transforms of zeta_{2N}^{rk} f_k (r = 0, 1); their products are
 // transformed forward and recombined as (F_0 + zeta_{2N}^{-k} F_1) / 2N.
 // ======================================================================
+// One M = 1 row by one group: f and g are read once; both residues r = 0, 1
+// are formed from the same registers (x0 = f, x1 = zeta_{2N}^k f, likewise
+// g) and transformed together, through two exchange buffers (fft2, DUAL) or
+// one after the other through one.
+template <typename T, int N, bool DUAL>
+__device__ __forceinline__ void conv_complex_row(const RowArgs& a, const RowCtx& c, int t, C<T>* lds,
+                                                 C<T>* lds1)
+{
+    constexpr int E = fft_E<T>(N), G = N / E;
+    const C<T>* twb = (const C<T>*)a.tw;
+    const C<T>* twN = twb + tw_off(N);
+    const C<T>* tw2N = twb + tw_off(2 * N);
+    const C<T>* F = (const C<T>*)a.f + c.of;
+    const C<T>* Gp = (const C<T>*)a.g + c.og;
+    C<T>* H = (C<T>*)a.h + c.oh;
+    const bool revf = a.flags & kRevF, cjg = a.flags & kConjG, revo = a.flags & kRevOut;
+    const T s = T(1) / T(2 * N);
+    auto pair = [&](auto& a0, auto& a1, auto dir) {
+        constexpr int D = decltype(dir)::value;
+        if constexpr (DUAL) {
+            fft2<T, N, E, D>(a0, a1, t, lds, lds1, 1, twN);
+        } else {
+            fft<T, N, E, D>(a0, t, lds, 1, twN);
+            fft<T, N, E, D>(a1, t, lds, 1, twN);
+        }
+    };
+    C<T> x0[E], x1[E];
+    {
+        const int z = opaque_zero();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = t + e * G;
+            x0[e] = ldz(F + z, revf ? c.m - 1 - k : k, c.m);
+            x1[e] = x0[e] * tw2N[k + z];
+        }
+    }
+    pair(x0, x1, std::integral_constant<int, +1>{});
+    {
+        C<T> y[E];
+        const int z = opaque_zero();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            C<T> gv = ldz(Gp + z, t + e * G, c.m);
+            y[e] = cjg ? conj(gv) : gv;
+        }
+        C<T> y1[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) y1[e] = y[e] * tw2N[t + e * G + z];
+        pair(y, y1, std::integral_constant<int, +1>{});
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            x0[e] = x0[e] * y[e];
+            x1[e] = x1[e] * y1[e];
+        }
+    }
+    pair(x0, x1, std::integral_constant<int, -1>{});
+    const int z = opaque_zero();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = t + e * G;
+        if (k < c.m) H[revo ? c.m - 1 - k : k] = scale(x0[e] + mulc(x1[e], tw2N[k + z]), s);
+    }
+}
+
 template <typename T, int N, bool ACCG, bool MD>
 __global__ void __launch_bounds__(row_block<T>(N), row_waves<T>(N))
 k_conv1d_complex(RowArgs a)
@@ -143,6 +207,12 @@ k_conv1d_complex(RowArgs a)
     const int grp = threadIdx.x / G, t = threadIdx.x % G;
     const RowCtx c = row_ctx(a, (int64_t)blockIdx.x * GPB + grp);
     C<T>* lds = sh + grp * LDSN;
+
+    if constexpr (!MD) {
+        conv_complex_row<T, N, DUAL>(a, c, t, lds, DUAL ? sh + (GPB + grp) * LDSN : lds);
+        return;
+    }
+
     const C<T>* twb = (const C<T>*)a.tw;
     const C<T>* twN = twb + tw_off(N);
     const C<T>* tw2N = twb + tw_off(2 * N);
@@ -151,59 +221,6 @@ k_conv1d_complex(RowArgs a)
     C<T>* H = (C<T>*)a.h + c.oh;
     const bool revf = a.flags & kRevF, cjg = a.flags & kConjG, revo = a.flags & kRevOut;
     const T s = T(1) / T(2 * N);
-
-    if constexpr (!MD) {
-        // M = 1: f and g are read once; both residues r = 0, 1 are formed
-        // from the same registers (x0 = f, x1 = zeta_{2N}^k f, likewise g)
-        // and transformed together (fft2) through two exchange buffers.
-        C<T>* lds1 = DUAL ? sh + (GPB + grp) * LDSN : lds;
-        auto pair = [&](auto& a0, auto& a1, auto dir) {
-            constexpr int D = decltype(dir)::value;
-            if constexpr (DUAL) {
-                fft2<T, N, E, D>(a0, a1, t, lds, lds1, 1, twN);
-            } else {
-                fft<T, N, E, D>(a0, t, lds, 1, twN);
-                fft<T, N, E, D>(a1, t, lds, 1, twN);
-            }
-        };
-        C<T> x0[E], x1[E];
-        {
-            const int z = opaque_zero();
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int k = t + e * G;
-                x0[e] = ldz(F + z, revf ? c.m - 1 - k : k, c.m);
-                x1[e] = x0[e] * tw2N[k + z];
-            }
-        }
-        pair(x0, x1, std::integral_constant<int, +1>{});
-        {
-            C<T> y[E];
-            const int z = opaque_zero();
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                C<T> gv = ldz(Gp + z, t + e * G, c.m);
-                y[e] = cjg ? conj(gv) : gv;
-            }
-            C<T> y1[E];
-#pragma unroll
-            for (int e = 0; e < E; ++e) y1[e] = y[e] * tw2N[t + e * G + z];
-            pair(y, y1, std::integral_constant<int, +1>{});
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                x0[e] = x0[e] * y[e];
-                x1[e] = x1[e] * y1[e];
-            }
-        }
-        pair(x0, x1, std::integral_constant<int, -1>{});
-        const int z = opaque_zero();
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int k = t + e * G;
-            if (k < c.m) H[revo ? c.m - 1 - k : k] = scale(x0[e] + mulc(x1[e], tw2N[k + z]), s);
-        }
-        return;
-    }
 
     C<T> acc[ACCG ? 1 : E];
 #pragma unroll

@@ -107,3 +107,9 @@ def test_ragged_plan_validation(L):
     st = L.impconv_ragged_plan_create(0, 1, ms0.ctypes.data_as(ctypes.c_void_p),
                                       offs.ctypes.data_as(ctypes.c_void_p), ctypes.byref(p))
     assert st == 2
+
+
+def test_ragged_autotune_and_schedule_null_arguments(L):
+    n = ctypes.c_size_t()
+    assert L.impconv_ragged_plan_autotune(None, None) == 1
+    assert L.impconv_ragged_plan_schedule(None, None, 0, ctypes.byref(n)) == 1

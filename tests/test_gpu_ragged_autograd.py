@@ -71,6 +71,48 @@ def test_ragged_c5_workload():
         assert rel(h[o + ks], r) < TOL[np.complex64]
 
 
+def test_ragged_autotuned_schedule():
+    """The autotuner times every supported four-step split of the long
+    classes and keeps one; the tuned plan's results match the oracle and
+    the untuned plan, and the tuned plan replays under hipGraph capture."""
+    ic = need_gpu()
+    import torch
+    ms = np.array([64, 5000, 16384, 40000, 65536, 9, 20000])
+    offs, f = packed(ms, 161)
+    _, g = packed(ms, 162)
+    F, G = to_dev(f, np.complex64), to_dev(g, np.complex64)
+    base = ic.RaggedPlan(ms, offs, dtype=torch.complex64)
+    ref_gpu = base.execute(F, G).cpu().numpy()
+    plan = ic.RaggedPlan(ms, offs, dtype=torch.complex64, autotune=True)
+    sch = plan.schedule()
+    say(f"schedule {sch}")
+    long = [c for c in sch if c["method"] == "four-step"]
+    assert {c["N"] for c in long} == {16384, 32768, 65536}
+    for c in long:
+        assert c["N1"] * c["N2"] == c["N"]
+        assert str(c["N2"]) in c["tuned_ms"] and len(c["tuned_ms"]) >= 3
+        assert c["tuned_ms"][str(c["N2"])] == min(c["tuned_ms"].values())
+    h = plan.execute(F, G).cpu().numpy()
+    assert rel(h, ref_gpu) < TOL[np.complex64]
+    fr, gr = rounded(f, np.complex64), rounded(g, np.complex64)
+    for m, o in zip(ms, offs):
+        ks = np.array([0, 1, m // 3, m - 1]) if m > 3 else np.arange(m)
+        r = oracle.convnd_complex_at(fr[o:o + m], gr[o:o + m], ks[:, None])
+        assert rel(h[o + ks], r) < TOL[np.complex64], m
+    out = torch.zeros_like(F)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        plan.execute(F, G, out=out)
+    for rep in range(3):
+        out.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), h), rep
+
+
 def test_ragged_graph_replay_matches_eager():
     ic = need_gpu()
     import torch
