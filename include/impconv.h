@@ -221,6 +221,54 @@ impconv_status impconv_ragged_plan_autotune(impconv_ragged_plan* plan, void* str
 impconv_status impconv_ragged_plan_schedule(const impconv_ragged_plan* plan, char* buf, size_t cap,
                                             size_t* len);
 
+/* ----------------------------------------------------------------------
+ * Descriptor-based plans: one create / execute pair for every kind and
+ * dimension.  impconv_plan_create validates the descriptor with the same
+ * rules (and error codes) as the matching one-shot call, creates the twiddle
+ * tables of the current device and fixes the workspace size, so that
+ * impconv_execute only launches kernels (it may be captured in a hipGraph).
+ * A plan is immutable and holds no data-sized memory; it may be executed
+ * concurrently with distinct workspaces, on the device it was created on.
+ * ---------------------------------------------------------------------- */
+typedef struct impconv_desc {
+    int kind;         /* impconv_kind */
+    int dtype;        /* impconv_dtype */
+    int ndim;         /* 1, 2 or 3 (ternary: 1) */
+    int64_t m[3];     /* logical modes per axis; m[0] in 1D */
+    int64_t n[3];     /* storage extents per axis (2D/3D; see impconv_conv2d) */
+    int64_t batch;    /* independent convolutions */
+    int64_t M;        /* dot-product width (Sec. 3.3); ignored for ternary */
+    uint32_t flags;   /* as for the one-shot call of this kind */
+} impconv_desc;
+
+typedef struct impconv_plan impconv_plan;
+
+/* Errors: E_ARG (null plan/desc, bad ndim or kind), E_SIZE / E_UNSUPPORTED
+ * (sizes, as the one-shot calls; ternary with ndim > 1 is E_UNSUPPORTED),
+ * E_HIP (twiddle table creation).  *plan is NULL on error. */
+impconv_status impconv_plan_create(impconv_plan** plan, const impconv_desc* desc);
+impconv_status impconv_workspace_bytes(const impconv_plan* plan, size_t* bytes);
+/* Runs the plan's convolution: the one-shot call of its kind and dimension
+ * with the descriptor's sizes and flags.  e is the third input of a ternary
+ * plan and must be NULL for every other kind (E_ARG). */
+impconv_status impconv_execute(const impconv_plan* plan, const void* f, const void* g, const void* e,
+                               void* h, void* work, size_t work_bytes, void* stream);
+impconv_status impconv_plan_destroy(impconv_plan* plan);
+
+/* One-shot ragged batch: impconv_ragged_execute on a plan the library keeps
+ * in a process-wide cache (16 most recently used layouts) keyed by device,
+ * dtype and the contents of m_host / offset_host.  The first call with a
+ * layout creates the plan (synchronous descriptor upload: not under stream
+ * capture); later calls only launch kernels.  Evicting a plan synchronizes
+ * the device.  Errors as impconv_ragged_plan_create and
+ * impconv_ragged_execute. */
+impconv_status impconv_conv1d_complex_ragged_workspace(int dtype, int64_t npairs, const int64_t* m_host,
+                                                       const int64_t* offset_host, size_t* bytes);
+impconv_status impconv_conv1d_complex_ragged(int dtype, int64_t npairs, const int64_t* m_host,
+                                             const int64_t* offset_host, const void* f, const void* g,
+                                             void* h, void* work, size_t work_bytes, uint32_t flags,
+                                             void* stream);
+
 #ifdef __cplusplus
 }
 #endif

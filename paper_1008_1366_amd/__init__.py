@@ -56,6 +56,13 @@ class ImpconvError(RuntimeError):
         self.status = status
 
 
+class Desc(ctypes.Structure):
+    """impconv_desc of the C ABI."""
+    _fields_ = [("kind", ctypes.c_int), ("dtype", ctypes.c_int), ("ndim", ctypes.c_int),
+                ("m", ctypes.c_int64 * 3), ("n", ctypes.c_int64 * 3), ("batch", ctypes.c_int64),
+                ("M", ctypes.c_int64), ("flags", ctypes.c_uint32)]
+
+
 def lib():
     """The loaded C library (ctypes).  Raises if it has not been built."""
     global _lib
@@ -85,6 +92,12 @@ def lib():
             "impconv_ragged_execute": ([_p, _p, _p, _p, _p, _sz, _u32, _p], st),
             "impconv_ragged_plan_destroy": ([_p], st),
             "impconv_ragged_plan_autotune": ([_p, _p], st),
+            "impconv_plan_create": ([ctypes.POINTER(_p), ctypes.POINTER(Desc)], st),
+            "impconv_workspace_bytes": ([_p, ctypes.POINTER(_sz)], st),
+            "impconv_execute": ([_p, _p, _p, _p, _p, _p, _sz, _p], st),
+            "impconv_plan_destroy": ([_p], st),
+            "impconv_conv1d_complex_ragged_workspace": ([ctypes.c_int, _i64, _p, _p, ctypes.POINTER(_sz)], st),
+            "impconv_conv1d_complex_ragged": ([ctypes.c_int, _i64, _p, _p, _p, _p, _p, _p, _sz, _u32, _p], st),
             "impconv_ragged_plan_schedule": ([_p, ctypes.c_char_p, _sz, ctypes.POINTER(_sz)], st),
             "impconv_timing_enable": ([ctypes.c_int], None),
             "impconv_timing_report": ([ctypes.c_char_p, _sz], _sz),
@@ -343,6 +356,64 @@ class RaggedPlan:
                 _lib.impconv_ragged_plan_destroy(self._h)
         except Exception:
             pass
+
+
+class Plan:
+    """Descriptor-based plan (impconv_plan_create / impconv_execute): kind in
+    {"complex", "hermitian", "ternary"}, logical sizes m per axis, storage
+    extents n (2D/3D; default m for complex), batch, dot-product width M."""
+
+    def __init__(self, kind: str, dtype, m, n=None, batch: int = 1, M: int = 1, flags: int = 0, device=None):
+        m = tuple(int(x) for x in (m if hasattr(m, "__len__") else (m,)))
+        nd = len(m)
+        n = tuple(int(x) for x in (n if n is not None else m))
+        self.kind = {"complex": COMPLEX, "hermitian": HERMITIAN, "ternary": TERNARY}[kind]
+        self.dtype = dtype
+        self.m, self.n, self.batch, self.M = m, n, int(batch), int(M)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        d = Desc(self.kind, C64 if dtype == torch.complex64 else C128, nd, (ctypes.c_int64 * 3)(*m),
+                 (ctypes.c_int64 * 3)(*n), self.batch, self.M, flags)
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().impconv_plan_create(ctypes.byref(self._h), ctypes.byref(d)), "impconv_plan_create")
+        out = _sz()
+        _check(lib().impconv_workspace_bytes(self._h, ctypes.byref(out)), "impconv_workspace_bytes")
+        self.work_bytes = out.value
+
+    def execute(self, f, g, e=None, out=None, work=None):
+        _dev(*(x for x in (f, g, e) if x is not None))
+        oshape = (self.batch, *self.n) if len(self.m) > 1 else (self.batch, self.m[0])
+        h = torch.empty(oshape, dtype=self.dtype, device=f.device) if out is None else out
+        w = _work(self.work_bytes, f.device) if work is None else work
+        _check(lib().impconv_execute(self._h, _ptr(f), _ptr(g), _ptr(e) if e is not None else None, _ptr(h),
+                                     _ptr(w), self.work_bytes, ctypes.c_void_p(_stream(f.device))), "impconv_execute")
+        return h
+
+    def __del__(self):
+        try:
+            if self._h and _lib is not None:
+                _lib.impconv_plan_destroy(self._h)
+        except Exception:
+            pass
+
+
+def conv1d_complex_ragged(f, g, ms, offsets, flags: int = 0):
+    """One-shot ragged batch (impconv_conv1d_complex_ragged; the library
+    caches the plan of each layout)."""
+    import numpy as np
+    _dev(f, g)
+    ms = np.ascontiguousarray(np.asarray(ms, dtype=np.int64))
+    offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    dt = _dtype_code(f)
+    out = _sz()
+    _check(lib().impconv_conv1d_complex_ragged_workspace(dt, len(ms), ms.ctypes.data_as(_p), offs.ctypes.data_as(_p),
+                                                          ctypes.byref(out)), "ragged workspace")
+    w = _work(out.value, f.device)
+    h = torch.zeros_like(f)
+    _check(lib().impconv_conv1d_complex_ragged(dt, len(ms), ms.ctypes.data_as(_p), offs.ctypes.data_as(_p),
+                                               _ptr(f), _ptr(g), _ptr(h), _ptr(w), out.value, flags,
+                                               ctypes.c_void_p(_stream(f.device))), "conv1d_complex_ragged")
+    return h
 
 
 # ---------------------------------------------------------------- autograd

@@ -113,3 +113,32 @@ def test_ragged_autotune_and_schedule_null_arguments(L):
     n = ctypes.c_size_t()
     assert L.impconv_ragged_plan_autotune(None, None) == 1
     assert L.impconv_ragged_plan_schedule(None, None, 0, ctypes.byref(n)) == 1
+
+
+def test_plan_create_validation(L):
+    """The descriptor plan rejects bad descriptors with the one-shot calls'
+    codes before touching a device."""
+    import paper_1008_1366_amd as ic
+    p = ctypes.c_void_p()
+
+    def create(kind=0, dtype=0, ndim=1, m=(16, 0, 0), n=(0, 0, 0), batch=1, M=1, flags=0):
+        d = ic.Desc(kind, dtype, ndim, (ctypes.c_int64 * 3)(*m), (ctypes.c_int64 * 3)(*n), batch, M, flags)
+        return L.impconv_plan_create(ctypes.byref(p), ctypes.byref(d))
+
+    assert L.impconv_plan_create(ctypes.byref(p), None) == 1
+    assert create(ndim=0) == 1 and create(ndim=4) == 1
+    assert create(kind=7) == 1
+    assert create(dtype=5) == 1
+    assert create(m=(0, 0, 0)) == 2
+    assert create(M=0) == 2
+    assert create(batch=-1) == 2
+    assert create(kind=2, ndim=2, m=(4, 4, 0), n=(8, 5, 0)) == 5  # ternary is 1D
+    assert create(kind=1, ndim=2, m=(4, 4, 0), n=(9, 5, 0)) == 2  # centered axis needs 2m-1 or 2m
+    assert create(kind=0, ndim=2, m=(4, 4, 0), n=(4, 5, 0)) == 2  # complex storage n == m
+    assert create(flags=1 << 7) == 1
+    n = ctypes.c_size_t()
+    assert L.impconv_workspace_bytes(None, ctypes.byref(n)) == 1
+    assert L.impconv_execute(None, None, None, None, None, None, 0, None) == 1
+    assert L.impconv_plan_destroy(None) == 0
+    assert L.impconv_conv1d_complex_ragged(0, -1, None, None, None, None, None, None, 0, 0, None) == 2
+    assert L.impconv_conv1d_complex_ragged(0, 2, None, None, None, None, None, None, 0, 0, None) == 1
