@@ -56,6 +56,9 @@ def _load():
             "orc_convnd_hermitian_at": ([ctypes.c_int, _p, _p, _i64, ctypes.c_int, _p, _p, _i64,
                                          _p, _p], None),
             "orc_hermitian_expand": ([ctypes.c_int, _p, _p, ctypes.c_int, _p, _p], None),
+            "orc_convnd_ternary": ([ctypes.c_int, _p, _p, ctypes.c_int, _p, _p, _p, _p], ctypes.c_int),
+            "orc_convnd_ternary_at": ([ctypes.c_int, _p, _p, ctypes.c_int, _p, _p, _p, _i64, _p, _p],
+                                      ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -232,6 +235,37 @@ def convnd_hermitian_at(f, g, m, pts, symmetrize=True) -> np.ndarray:
     out = np.empty(len(pts), np.complex128)
     _load().orc_convnd_hermitian_at(ndim, _ptr(mm), _ptr(n), M, int(bool(symmetrize)),
                                     _ptr(f), _ptr(g), len(pts), _ptr(pts), _ptr(out))
+    return out
+
+
+def convnd_ternary(f, g, e, m, symmetrize=True) -> np.ndarray:
+    """Sec. 4 centered Hermitian ternary sum in nD (tconv2 for 2D), in the
+    storage layout of convnd_hermitian: h_k = sum f_p g_q e_{k-p-q} over p,
+    q, k-p-q in the box, k in the box with k_last >= 0."""
+    f, g, e = _c(f), _c(g), _c(e)
+    if not (f.shape == g.shape == e.shape):
+        raise ValueError("f, g, e must have equal shapes")
+    ndim = len(m)
+    n = _i64arr(f.shape)
+    mm = _i64arr(m)
+    h = np.empty(f.shape, np.complex128)
+    if _load().orc_convnd_ternary(ndim, _ptr(mm), _ptr(n), int(bool(symmetrize)), _ptr(f), _ptr(g), _ptr(e),
+                                  _ptr(h)):
+        raise MemoryError("oracle allocation failed")
+    return h
+
+
+def convnd_ternary_at(f, g, e, m, pts, symmetrize=True) -> np.ndarray:
+    """convnd_ternary at logical wavenumbers pts (npts, ndim), k_last >= 0."""
+    f, g, e = _c(f), _c(g), _c(e)
+    ndim = len(m)
+    n = _i64arr(f.shape)
+    mm = _i64arr(m)
+    pts = _i64arr(pts).reshape(-1, ndim)
+    out = np.empty(len(pts), np.complex128)
+    if _load().orc_convnd_ternary_at(ndim, _ptr(mm), _ptr(n), int(bool(symmetrize)), _ptr(f), _ptr(g),
+                                     _ptr(e), len(pts), _ptr(pts), _ptr(out)):
+        raise MemoryError("oracle allocation failed")
     return out
 
 

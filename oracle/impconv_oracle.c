@@ -20,7 +20,8 @@
  *   Sec. 3.1/3.3  -- 2D and 3D complex convolutions (componentwise origin at 0)
  *   Sec. 3.2/3.4  -- 2D and 3D centered Hermitian convolutions
  *   Sec. 3.3      -- M-vector inputs: f*g read as sum_i f_i*g_i
- *   Sec. 4        -- centered ternary sum over p+q+r = k
+ *   Sec. 4        -- centered ternary sum over p+q+r = k (1D tconv; nD over the
+ *                    box, the 2D case being tconv2)
  *   Concluding remarks -- the Hermitian symmetry of the k_last = 0 line/plane
  *                    is enforced by the convolution routine itself.
  *
@@ -399,4 +400,115 @@ void orc_hermitian_expand(int ndim, const int64_t *m, const int64_t *n, int sym,
         for (int d = 0; d < ndim; ++d) p[d] = idx[d] - (m[d] - 1);
         full[lin] = hval(&L, u, p);
     }
+}
+
+/* ---------------------------------------------------------------------------
+ * Centered Hermitian nD ternary sum (Sec. 4; tconv2 for ndim = 2):
+ *   h_k = sum_{p in B} sum_{q in B, k-p-q in B} f_p g_q e_{k-p-q},
+ * for k in B with k_last >= 0, the full fields built from the stored halves
+ * exactly as for the binary sum above (same storage layout, same reading of
+ * the k_last = 0 hyperplane).  Zero slots of h are written as 0.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int ndim;
+    int64_t a[3], fe[3], fst[3];
+    const dc *F, *G, *E;
+} tfull;
+
+static int64_t tfidx(const tfull *T, const int64_t *p)
+{
+    int64_t x = 0;
+    for (int d = 0; d < T->ndim; ++d) x += (p[d] + T->a[d]) * T->fst[d];
+    return x;
+}
+
+static dc tnd_point(const tfull *T, const int64_t *k)
+{
+    const int nd = T->ndim;
+    int64_t p[3] = {0, 0, 0}, q[3] = {0, 0, 0}, r[3] = {0, 0, 0};
+    int64_t plo[3] = {0, 0, 0}, phi[3] = {0, 0, 0};
+    for (int d = 0; d < nd; ++d) { plo[d] = -T->a[d]; phi[d] = T->a[d]; }
+    dc s = 0;
+    for (p[0] = plo[0]; p[0] <= phi[0]; ++p[0])
+        for (p[1] = plo[1]; p[1] <= phi[1]; ++p[1])
+            for (p[2] = plo[2]; p[2] <= phi[2]; ++p[2]) {
+                /* q and r = k - p - q both in the box */
+                int64_t qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
+                int empty = 0;
+                for (int d = 0; d < nd; ++d) {
+                    const int64_t c = k[d] - p[d], a = T->a[d];
+                    qlo[d] = (c - a > -a) ? c - a : -a;
+                    qhi[d] = (c + a < a) ? c + a : a;
+                    if (qlo[d] > qhi[d]) empty = 1;
+                }
+                if (empty) continue;
+                const dc fp = T->F[tfidx(T, p)];
+                dc t = 0;
+                for (q[0] = qlo[0]; q[0] <= qhi[0]; ++q[0])
+                    for (q[1] = qlo[1]; q[1] <= qhi[1]; ++q[1])
+                        for (q[2] = qlo[2]; q[2] <= qhi[2]; ++q[2]) {
+                            for (int d = 0; d < nd; ++d) r[d] = k[d] - p[d] - q[d];
+                            t += T->G[tfidx(T, q)] * T->E[tfidx(T, r)];
+                        }
+                s += fp * t;
+            }
+    return s;
+}
+
+static int tfull_init(tfull *T, int ndim, const int64_t *m, const int64_t *n, int sym, const dc *f,
+                      const dc *g, const dc *e, dc **buf)
+{
+    T->ndim = ndim;
+    int64_t vol = 1;
+    for (int d = 0; d < 3; ++d) { T->a[d] = 0; T->fe[d] = 1; }
+    for (int d = 0; d < ndim; ++d) { T->a[d] = m[d] - 1; T->fe[d] = 2 * m[d] - 1; vol *= T->fe[d]; }
+    T->fst[2] = 1;
+    T->fst[1] = T->fe[2];
+    T->fst[0] = T->fe[1] * T->fe[2];
+    if (ndim == 2) { T->fst[1] = 1; T->fst[0] = T->fe[1]; }
+    if (ndim == 1) T->fst[0] = 1;
+    *buf = (dc *)malloc(3 * vol * sizeof(dc));
+    if (!*buf) return -1;
+    orc_hermitian_expand(ndim, m, n, sym, f, *buf);
+    orc_hermitian_expand(ndim, m, n, sym, g, *buf + vol);
+    orc_hermitian_expand(ndim, m, n, sym, e, *buf + 2 * vol);
+    T->F = *buf;
+    T->G = *buf + vol;
+    T->E = *buf + 2 * vol;
+    return 0;
+}
+
+/* Full output in the storage layout. */
+int orc_convnd_ternary(int ndim, const int64_t *m, const int64_t *n, int sym, const dc *f,
+                       const dc *g, const dc *e, dc *h)
+{
+    hlay L;
+    hlay_init(&L, ndim, m, n, sym);
+    tfull T;
+    dc *buf = NULL;
+    if (tfull_init(&T, ndim, m, n, sym, f, g, e, &buf)) return -1;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t lin = 0; lin < L.vol; ++lin) {
+        int64_t idx[3], k[3];
+        unflatten(ndim, L.n, lin, idx);
+        for (int d = 0; d < ndim; ++d) k[d] = idx[d] - L.off[d];
+        if (!in_box(&L, k) || k[ndim - 1] < 0) { h[lin] = 0; continue; }
+        h[lin] = tnd_point(&T, k);
+    }
+    free(buf);
+    return 0;
+}
+
+/* Sampled outputs at logical wavenumbers pts[j][0..ndim-1] (k in B,
+ * k_last >= 0). */
+int orc_convnd_ternary_at(int ndim, const int64_t *m, const int64_t *n, int sym, const dc *f,
+                          const dc *g, const dc *e, int64_t npts, const int64_t *pts, dc *out)
+{
+    tfull T;
+    dc *buf = NULL;
+    if (tfull_init(&T, ndim, m, n, sym, f, g, e, &buf)) return -1;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = 0; j < npts; ++j) out[j] = tnd_point(&T, pts + j * ndim);
+    free(buf);
+    return 0;
 }

@@ -412,3 +412,82 @@ def test_nd_sampled_1d_forms(orc):
     full = np.convolve(herm_full_np(f), herm_full_np(g))
     ref = full[2 * (m - 1) + ks[:, 0]]
     assert rel(orc.convnd_hermitian_at(f, g, (m,), ks), ref) < TOL
+
+
+# ---------------------------------------------------------------- ternary nD (tconv2)
+
+@pytest.mark.parametrize("m,n", [((3, 4), (5, 4)), ((4, 4), (8, 5)), ((2, 3), (4, 4)), ((3, 2, 3), (6, 3, 4))])
+def test_ternary_nd_vs_scipy(orc, m, n):
+    """Definition via two library convolutions of the expanded fields:
+    (F * G) * E over the full index range, restricted to the box."""
+    f, g, e = herm_storage(m, n, 81), herm_storage(m, n, 82), herm_storage(m, n, 83)
+    F, G, E = expand_np(f, m), expand_np(g, m), expand_np(e, m)
+    full = scipy.signal.convolve(scipy.signal.convolve(F, G, method="direct"), E, method="direct")
+    h = orc.convnd_ternary(f, g, e, m)
+    nd = len(m)
+    for idx in np.ndindex(*n):
+        k = [idx[d] - (n[d] - m[d]) if d < nd - 1 else idx[d] for d in range(nd)]
+        inside = all(abs(k[d]) <= m[d] - 1 for d in range(nd)) and k[-1] >= 0
+        if not inside:
+            assert h[idx] == 0
+        else:
+            ref = full[tuple(k[d] + 3 * (m[d] - 1) for d in range(nd))]
+            assert abs(h[idx] - ref) < 1e-12 * max(1, abs(ref))
+
+
+def test_ternary_2d_brute_force(orc):
+    """Four nested loops over p and q on a tiny grid, fields expanded by
+    expand_np."""
+    m, n = (2, 2), (4, 3)
+    f, g, e = herm_storage(m, n, 84), herm_storage(m, n, 85), herm_storage(m, n, 86)
+    F, G, E = expand_np(f, m), expand_np(g, m), expand_np(e, m)
+    a = [x - 1 for x in m]
+    h = orc.convnd_ternary(f, g, e, m)
+    for kx in range(-a[0], a[0] + 1):
+        for ky in range(0, a[1] + 1):
+            s = 0
+            for px in range(-a[0], a[0] + 1):
+                for py in range(-a[1], a[1] + 1):
+                    for qx in range(-a[0], a[0] + 1):
+                        for qy in range(-a[1], a[1] + 1):
+                            rx, ry = kx - px - qx, ky - py - qy
+                            if abs(rx) <= a[0] and abs(ry) <= a[1]:
+                                s += F[px + a[0], py + a[1]] * G[qx + a[0], qy + a[1]] * E[rx + a[0], ry + a[1]]
+            assert abs(h[kx + n[0] - m[0], ky] - s) < 1e-13
+
+
+def test_ternary_nd_delta_is_binary(orc):
+    """e = delta at the origin reduces the ternary sum to the binary one."""
+    m, n = (4, 3), (8, 4)
+    f, g = herm_storage(m, n, 87), herm_storage(m, n, 88)
+    e = np.zeros(n, complex)
+    e[n[0] - m[0], 0] = 1.0
+    assert rel(orc.convnd_ternary(f, g, e, m), orc.convnd_hermitian(f, g, m)) < TOL
+
+
+def test_ternary_2d_separable(orc):
+    """U = A (x) b for each field: the sum factors into a full centered
+    ternary sum in x (two numpy convolutions) and the 1D Hermitian ternary
+    sum in y."""
+    mx, my = 7, 9
+    A, C, P = (herm_full_np(rnd(mx, s)) for s in (89, 90, 91))
+    b, d, q = rnd(my, 92), rnd(my, 93), rnd(my, 94)
+    for v in (b, d, q):
+        v[0] = v[0].real
+    f, g, e = np.outer(A, b), np.outer(C, d), np.outer(P, q)
+    h = orc.convnd_ternary(f, g, e, (mx, my))
+    xfull = np.convolve(np.convolve(A, C), P)[2 * (mx - 1):4 * (mx - 1) + 1]
+    ref = np.outer(xfull, orc.conv1d_ternary(b, d, q))
+    assert rel(h, ref) < TOL
+
+
+def test_ternary_nd_symmetric_and_sampled(orc):
+    m, n = (3, 4, 3), (6, 7, 4)
+    f, g, e = herm_storage(m, n, 95), herm_storage(m, n, 96), herm_storage(m, n, 97)
+    h = orc.convnd_ternary(f, g, e, m)
+    assert rel(orc.convnd_ternary(e, f, g, m), h) < TOL
+    assert rel(orc.convnd_ternary(g, e, f, m), h) < TOL
+    pts = np.array([[0, 0, 0], [-2, 3, 2], [2, -3, 0], [1, 0, 1]])
+    got = orc.convnd_ternary_at(f, g, e, m, pts)
+    ref = [h[p[0] + 3, p[1] + 3, p[2]] for p in pts]
+    assert rel(got, ref) < TOL
