@@ -175,6 +175,23 @@ impconv_status impconv_conv3d(int kind, int dtype, int64_t batch, int64_t M, con
                               const int64_t* n, const void* f, const void* g, void* h,
                               void* work, size_t work_bytes, uint32_t flags, void* stream);
 
+/* 2D centered Hermitian ternary convolution, Sec. 4 (tconv2): f, g, e and h
+ * are [batch][n0][n1] in the 2D Hermitian storage of impconv_conv2d
+ * (x centered, n0 in {2m0-1, 2m0}; y the Hermitian half, n1 in {m1, m1+1}),
+ *   h_k = sum_{p, q in B, k-p-q in B} f_p g_q e_{k-p-q},
+ * k in B = [-m0+1, m0-1] x [-m1+1, m1-1] with k_y >= 0, the full fields
+ * defined by U_{-k} = conj U_k.  The k_y = 0 line is symmetrized on load as
+ * in impconv_conv2d (IMPCONV_NO_SYMMETRIZE: its Hermitian projection);
+ * zero slots of h are written as 0.  The x axis uses the ternary rule (two
+ * residues of the centered transform padded to 4 N0', N0' = 2^ceil(log2 m0),
+ * transforms of size 2 N0'), every row the 1D ternary convolution.  Workspace
+ * (impconv_convnd_workspace with kind IMPCONV_TERNARY, ndim 2, M = 1):
+ * 8 * batch * 2 N0' * n1 complex values.  This build: m0 <= 2048,
+ * m1 <= 8192; E_UNSUPPORTED beyond and for IMPCONV_EXPLICIT_PADDED. */
+impconv_status impconv_conv2d_ternary(int dtype, int64_t batch, const int64_t* m, const int64_t* n,
+                                      const void* f, const void* g, const void* e, void* h,
+                                      void* work, size_t work_bytes, uint32_t flags, void* stream);
+
 /* ----------------------------------------------------------------------
  * Ragged batch of complex 1D convolutions of uneven lengths (Sec. 2.1 sum
  * per pair).  Pair j has length m_host[j] >= 1 and occupies elements
@@ -233,7 +250,7 @@ impconv_status impconv_ragged_plan_schedule(const impconv_ragged_plan* plan, cha
 typedef struct impconv_desc {
     int kind;         /* impconv_kind */
     int dtype;        /* impconv_dtype */
-    int ndim;         /* 1, 2 or 3 (ternary: 1) */
+    int ndim;         /* 1, 2 or 3 (ternary: 1 or 2) */
     int64_t m[3];     /* logical modes per axis; m[0] in 1D */
     int64_t n[3];     /* storage extents per axis (2D/3D; see impconv_conv2d) */
     int64_t batch;    /* independent convolutions */
@@ -244,7 +261,7 @@ typedef struct impconv_desc {
 typedef struct impconv_plan impconv_plan;
 
 /* Errors: E_ARG (null plan/desc, bad ndim or kind), E_SIZE / E_UNSUPPORTED
- * (sizes, as the one-shot calls; ternary with ndim > 1 is E_UNSUPPORTED),
+ * (sizes, as the one-shot calls; ternary with ndim 3 is E_UNSUPPORTED),
  * E_HIP (twiddle table creation).  *plan is NULL on error. */
 impconv_status impconv_plan_create(impconv_plan** plan, const impconv_desc* desc);
 impconv_status impconv_workspace_bytes(const impconv_plan* plan, size_t* bytes);

@@ -93,6 +93,7 @@ def lib():
             "impconv_ragged_plan_destroy": ([_p], st),
             "impconv_ragged_plan_autotune": ([_p, _p], st),
             "impconv_plan_create": ([ctypes.POINTER(_p), ctypes.POINTER(Desc)], st),
+            "impconv_conv2d_ternary": ([ctypes.c_int, _i64, _p, _p, _p, _p, _p, _p, _p, _sz, _u32, _p], st),
             "impconv_workspace_bytes": ([_p, ctypes.POINTER(_sz)], st),
             "impconv_execute": ([_p, _p, _p, _p, _p, _p, _sz, _p], st),
             "impconv_plan_destroy": ([_p], st),
@@ -264,6 +265,29 @@ def conv2d(f, g, kind: str = "complex", m=None, symmetrize: bool = True, method:
     elif method != "implicit":
         raise ValueError("method must be 'implicit' or 'explicit'")
     return _convnd(2, f, g, kind, m, flags)
+
+
+def conv2d_ternary(f, g, e, m, symmetrize: bool = True):
+    """2D centered Hermitian ternary convolution (Sec. 4, tconv2) of inputs
+    (n0, n1) or (B, n0, n1) in the 2D Hermitian storage; m = (m0, m1)."""
+    if not (f.shape == g.shape == e.shape) or not (f.dtype == g.dtype == e.dtype):
+        raise ValueError("f, g, e must share shape and dtype")
+    dev = _dev(f, g, e)
+    n = tuple(f.shape[-2:])
+    B = 1 if f.dim() == 2 else f.shape[0]
+    m = tuple(int(x) for x in m)
+    dt = _dtype_code(f)
+    flags = 0 if symmetrize else NO_SYMMETRIZE
+    marr = (ctypes.c_int64 * 2)(*m)
+    narr = (ctypes.c_int64 * 2)(*n)
+    out = _sz()
+    _check(lib().impconv_convnd_workspace(TERNARY, dt, 2, marr, narr, B, 1, flags, ctypes.byref(out)),
+           "impconv_convnd_workspace")
+    w = _work(out.value, dev)
+    h = torch.empty((B, *n), dtype=f.dtype, device=dev)
+    _check(lib().impconv_conv2d_ternary(dt, B, marr, narr, _ptr(f), _ptr(g), _ptr(e), _ptr(h), _ptr(w), out.value,
+                                        flags, ctypes.c_void_p(_stream(dev))), "conv2d_ternary")
+    return h.view(*n) if f.dim() == 2 else h
 
 
 def conv3d(f, g, kind: str = "complex", m=None, symmetrize: bool = True):

@@ -18,6 +18,15 @@
 //             3N U_k = sum_r zeta_{3N}^{-rk} F_r(k mod N), |k| < m; zero slots 0
 //   kFft    : plain FFT of direction DIR of in[0] (n_in rows, zero padded to
 //             N) into out[0] (n_out rows), scaled by s (explicit comparator)
+//   kTerBwd : in[0] (centered, wavenumber k at row k + off_in, |k| < m) ->
+//             out[r] = FFT+ of size N (= 2 N', N' >= m) of
+//             a_{r,j} = zeta_{2N}^{r(j - N')} U_{j-N'}, j = 0..N-1, r = 0, 1:
+//             the residues of the centered transform padded to 2N (Sec. 4.1,
+//             fft0tpadBackward; the sign (-1)^l of each residue is dropped,
+//             it cancels in a ternary product and the forward pass)
+//   kTerFwd : in[0], in[1] (N rows each) -> out (wavenumber k at row
+//             k + off_out): 2N U_k = F0(k + N') + zeta_{2N}^{-(k)} F1(k + N')
+//             for |k| < m (Sec. 4.1, fft0tpadForward); zero slots 0
 //   kFsBwd / kFsFwd : first and last pass of the four-step form of the 1D
 //             complex convolution of length NF = N1 * N (N1 = ncols): a 1D
 //             input f_k, k = k1 + N1 k2, is read as an N x N1 matrix; the
@@ -30,13 +39,15 @@
 
 namespace impconv {
 
-enum ColMode { kPadBwd = 0, kPadFwd = 1, kCenBwd = 2, kCenFwd = 3, kFft = 4, kFsBwd = 5, kFsFwd = 6 };
+enum ColMode { kPadBwd = 0, kPadFwd = 1, kCenBwd = 2, kCenFwd = 3, kFft = 4, kFsBwd = 5, kFsFwd = 6,
+               kTerBwd = 7, kTerFwd = 8 };
 
 __host__ __device__ constexpr const char* col_mode_name(int mode)
 {
     return mode == kPadBwd ? "colpass_pad_bwd" : mode == kPadFwd ? "colpass_pad_fwd"
          : mode == kCenBwd ? "colpass_cen_bwd" : mode == kCenFwd ? "colpass_cen_fwd"
-         : mode == kFft ? "colpass_fft" : mode == kFsBwd ? "colpass_fourstep_bwd" : "colpass_fourstep_fwd";
+         : mode == kFft ? "colpass_fft" : mode == kFsBwd ? "colpass_fourstep_bwd"
+         : mode == kFsFwd ? "colpass_fourstep_fwd" : mode == kTerBwd ? "colpass_ter_bwd" : "colpass_ter_fwd";
 }
 #define MODE_NAME(x) col_mode_name(x)
 
@@ -260,6 +271,67 @@ k_colpass(ColArgs a)
             const int k = t + e * G;
             if (k < a.m) strow(0, k + a.off_out, scale(ap[e], s));
             if (k >= 1 && k - N > -a.m) strow(0, k - N + a.off_out, scale(an[e], s));
+        }
+        // zero slots: rows whose wavenumber lies outside |k| < m
+        for (int row = t; row < a.n_out; row += G) {
+            const int k = row - a.off_out;
+            if (k <= -a.m || k >= a.m) strow(0, row, zero<T>());
+        }
+    } else if constexpr (MODE == kTerBwd) {
+        // U_{j - N/2} of this thread's rows j = t + eG, with the conjugate
+        // mirror of the k_last = 0 line (2D rule: column 0)
+        constexpr int NH = N / 2;
+        const bool plane = a.sym == 1 && c == 0;
+        const C<T>* base = (const C<T>*)a.in[0] + s1 * a.in_bs + s2 * a.in_bs2;
+        const C<T>* tw2N = twb + tw_off(2 * N);
+        int tl = t;
+        asm volatile("" : "+v"(tl));
+        C<T> x[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = tl + e * G - NH;
+            const bool in = cact && k > -a.m && k < a.m;
+            const bool mir = plane && k < 0;
+            const int kk = in ? (mir ? -k : k) : 0;
+            C<T> v = base[cc + int64_t(kk + a.off_in) * a.in_ld];
+            if (mir) v = conj(v);
+            if (plane && k == 0) v.im = T(0);
+            x[e] = in ? v : zero<T>();
+        }
+        C<T> y[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) y[e] = x[e];
+        fft<T, N, E, +1>(y, t, lds, TC, twN);
+#pragma unroll
+        for (int e = 0; e < E; ++e) strow(0, t + e * G, y[e]);
+        // residue 1: zeta_{2N}^{j - N/2} = -i zeta_{2N}^j
+        const int z = opaque_zero();
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = muli<-1>(x[e] * tw2N[t + e * G + z]);
+        fft<T, N, E, +1>(x, t, lds, TC, twN);
+#pragma unroll
+        for (int e = 0; e < E; ++e) strow(1, t + e * G, x[e]);
+    } else if constexpr (MODE == kTerFwd) {
+        constexpr int NH = N / 2;
+        const C<T>* tw2N = twb + tw_off(2 * N);
+        C<T> x[E], y[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = ldrow(0, t + e * G, N);
+        fft<T, N, E, -1>(x, t, lds, TC, twN);
+        {
+            const int z = opaque_zero();
+#pragma unroll
+            for (int e = 0; e < E; ++e) y[e] = ldrow(1, t + e * G + z, N);
+        }
+        fft<T, N, E, -1>(y, t, lds, TC, twN);
+        const T s = T(a.scale);
+        const int z = opaque_zero();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int j = t + e * G, k = j - NH;
+            // zeta_{2N}^{-(j - N/2)} = i conj(zeta_{2N}^j)
+            const C<T> v = x[e] + muli<+1>(mulc(y[e], tw2N[j + z]));
+            if (k > -a.m && k < a.m) strow(0, k + a.off_out, scale(v, s));
         }
         // zero slots: rows whose wavenumber lies outside |k| < m
         for (int row = t; row < a.n_out; row += G) {

@@ -50,6 +50,8 @@ hipError_t launch_col(int dt, int N, int mode, int dir, const ColArgs& a, hipStr
         case kPadFwd: return launch_col_pad(dt, N, mode, a, s);
         case kCenBwd:
         case kCenFwd: return launch_col_cen(dt, N, mode, a, s);
+        case kTerBwd:
+        case kTerFwd: return launch_col_ter(dt, N, mode, a, s);
         case kFft: return launch_col_fft(dt, N, dir, a, s);
         case kFsBwd:
         case kFsFwd: return launch_col_fs(dt, N, mode, a, s);

@@ -33,6 +33,7 @@ struct ColArgs;
 hipError_t launch_col(int dt, int N, int mode, int dir, const ColArgs& a, hipStream_t s);
 hipError_t launch_col_pad(int dt, int N, int mode, const ColArgs& a, hipStream_t s);
 hipError_t launch_col_cen(int dt, int N, int mode, const ColArgs& a, hipStream_t s);
+hipError_t launch_col_ter(int dt, int N, int mode, const ColArgs& a, hipStream_t s);
 hipError_t launch_col_fft(int dt, int N, int dir, const ColArgs& a, hipStream_t s);
 hipError_t launch_col_fs(int dt, int N, int mode, const ColArgs& a, hipStream_t s);
 

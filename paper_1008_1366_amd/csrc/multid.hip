@@ -187,7 +187,10 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
                       int64_t M, uint32_t flags, PlanND* p)
 {
     if (dt != IMPCONV_C64 && dt != IMPCONV_C128) return fail(IMPCONV_E_ARG, "bad dtype");
-    if (kind != IMPCONV_COMPLEX && kind != IMPCONV_HERMITIAN) return fail(IMPCONV_E_ARG, "nD kind must be COMPLEX or HERMITIAN");
+    if (kind != IMPCONV_COMPLEX && kind != IMPCONV_HERMITIAN && kind != IMPCONV_TERNARY)
+        return fail(IMPCONV_E_ARG, "nD kind must be COMPLEX, HERMITIAN or TERNARY");
+    if (kind == IMPCONV_TERNARY && nd != 2) return fail(IMPCONV_E_UNSUPPORTED, "ternary nD convolutions are 2D (tconv2)");
+    if (kind == IMPCONV_TERNARY && M != 1) return fail(IMPCONV_E_SIZE, "ternary convolutions take M = 1");
     if (!m || !n) return fail(IMPCONV_E_ARG, "m or n is NULL");
     if (batch < 0 || M < 1) return fail(IMPCONV_E_SIZE, "batch must be >= 0 and M >= 1");
     const uint32_t known = IMPCONV_NO_SYMMETRIZE | IMPCONV_EXPLICIT_PADDED;
@@ -210,8 +213,11 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
         }
         p->Np[d] = next_pow2(m[d]);
         if (!last && p->Np[d] > kColMax) return fail(IMPCONV_E_UNSUPPORTED, "outer axis too long (m <= 4096)");
+        if (!last && kind == IMPCONV_TERNARY && 2 * p->Np[d] > kColMax)
+            return fail(IMPCONV_E_UNSUPPORTED, "ternary outer axis too long (m <= 2048)");
         if (last) {
-            int64_t L = kind == IMPCONV_COMPLEX ? p->Np[d] : std::max<int64_t>(p->Np[d], 2) / 2;
+            int64_t L = kind == IMPCONV_COMPLEX || kind == IMPCONV_TERNARY ? p->Np[d]
+                                                                          : std::max<int64_t>(p->Np[d], 2) / 2;
             if (L > kRowMax) return fail(IMPCONV_E_UNSUPPORTED, "innermost axis too long");
         }
     }
@@ -224,7 +230,10 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
         p->work = size_t(2) * batch * M * P0 * P1 * cs;
         return IMPCONV_OK;
     }
-    if (nd == 2) {
+    if (kind == IMPCONV_TERNARY) {
+        // x residues of f, g, e (2 each, 2 Np0 rows) and the two row outputs
+        p->work = size_t(8) * batch * 2 * p->Np[0] * n[1] * cs;
+    } else if (nd == 2) {
         // residue arrays [b][x'][i][y] for f and g
         p->work = size_t(2) * R * batch * M * p->Np[0] * n[1] * cs;
     } else {
@@ -320,10 +329,105 @@ impconv_status inner_rows(const DevTables& tb, const PlanND& p, void* f, const v
     return IMPCONV_OK;
 }
 
+// 2D centered Hermitian ternary convolution (Sec. 4, tconv2): the x axis
+// is transformed with the ternary rule (two residues of the centered
+// transform padded to 4 N0', kTerBwd), every row of each residue is
+// convolved with the 1D ternary kernel, and the x axis is transformed back
+// (kTerFwd).  Layouts: f, g, e, h [b][n0][n1]; residues [b][2 N0'][n1].
+impconv_status run2d_ternary(int dt, int64_t batch, const int64_t* m, const int64_t* n, const void* f,
+                             const void* g, const void* e, void* h, void* work, size_t wb, uint32_t flags,
+                             void* stream)
+{
+    PlanND p;
+    impconv_status st = plannd(IMPCONV_TERNARY, dt, 2, m, n, batch, 1, flags, &p);
+    if (st) return st;
+    if (batch == 0) return IMPCONV_OK;
+    const size_t cs = csize(dt);
+    if (!f || !g || !e || !h) return fail(IMPCONV_E_ARG, "null data pointer");
+    for (const void* q : {f, g, e, (const void*)h})
+        if (reinterpret_cast<uintptr_t>(q) % cs) return fail(IMPCONV_E_ALIGN, "data pointer misaligned");
+    const int64_t n0 = n[0], n1 = n[1], m0 = m[0], m1 = m[1];
+    const size_t vol = size_t(batch) * n0 * n1 * cs;
+    auto ov = [](const void* a, size_t na, const void* b, size_t nb) {
+        const char* x = (const char*)a; const char* y = (const char*)b;
+        return x < y + nb && y < x + na;
+    };
+    if (ov(h, vol, f, vol) || ov(h, vol, g, vol) || ov(h, vol, e, vol)) return fail(IMPCONV_E_ARG, "h overlaps an input");
+    if (wb < p.work) return fail(IMPCONV_E_WORKSPACE, "workspace too small: need " + std::to_string(p.work) + " bytes");
+    if (!work) return fail(IMPCONV_E_ARG, "work is NULL");
+    if (reinterpret_cast<uintptr_t>(work) % cs) return fail(IMPCONV_E_ALIGN, "work misaligned");
+    const DevTables* tbp = tables();
+    if (!tbp) return IMPCONV_E_HIP;
+    const DevTables& tb = *tbp;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool sym = !(flags & IMPCONV_NO_SYMMETRIZE);
+    const int64_t P0 = 2 * p.Np[0];  // x transform size (residues of the 4 N0' padding)
+    const size_t arr = size_t(batch) * P0 * n1 * cs;
+    char* w = static_cast<char*>(work);
+    void* X[3][2];
+    for (int q = 0; q < 3; ++q)
+        for (int r = 0; r < 2; ++r) X[q][r] = w + (2 * q + r) * arr;
+    void* Q[2] = {w + 6 * arr, w + 7 * arr};
+    const void* src[3] = {f, g, e};
+    for (int q = 0; q < 3; ++q) {
+        ColArgs a = col_args(tb, dt);
+        a.in[0] = src[q];
+        a.out[0] = X[q][0];
+        a.out[1] = X[q][1];
+        a.nslab = batch;
+        a.in_bs = n0 * n1;
+        a.out_bs = P0 * n1;
+        a.ncols = n1;
+        a.in_ld = a.out_ld = n1;
+        a.n_in = int(n0);
+        a.m = int(m0);
+        a.off_in = int(n0 - m0);
+        a.sym = sym ? 1 : 0;
+        a.mask_nz = n1;  // columns k_y < m1 carry data; k_y = m1 is a zero slot
+        a.mask_ylo = 0;
+        a.mask_yhi = 1;
+        a.mask_zhi = int(m1);
+        HIPCHK(launch_col(dt, int(P0), kTerBwd, 1, a, s), "ternary x backward pass");
+    }
+    for (int r = 0; r < 2; ++r) {
+        RowArgs a = row_args(tb, dt);
+        a.f = X[0][r];
+        a.g = X[1][r];
+        a.e = X[2][r];
+        a.h = Q[r];
+        a.nrows = batch * P0;
+        a.m = m1;
+        a.M = 1;
+        a.f_row = a.g_row = a.e_row = a.h_row = n1;
+        a.h_pad = n1;
+        HIPCHK(launch_row_ternary(dt, int(p.Np[1]), a, s), "ternary row convolutions");
+    }
+    ColArgs a = col_args(tb, dt);
+    a.in[0] = Q[0];
+    a.in[1] = Q[1];
+    a.out[0] = h;
+    a.nslab = batch;
+    a.in_bs = P0 * n1;
+    a.out_bs = n0 * n1;
+    a.ncols = n1;
+    a.in_ld = a.out_ld = n1;
+    a.n_out = int(n0);
+    a.m = int(m0);
+    a.off_out = int(n0 - m0);
+    a.mask_nz = n1;
+    a.mask_ylo = 0;
+    a.mask_yhi = 1;
+    a.mask_zhi = int(m1);
+    a.scale = 1.0 / double(2 * P0);
+    HIPCHK(launch_col(dt, int(P0), kTerFwd, 1, a, s), "ternary x forward pass");
+    return IMPCONV_OK;
+}
+
 impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const int64_t* m,
                      const int64_t* n, const void* f, const void* g, void* h, void* work, size_t wb,
                      uint32_t flags, void* stream)
 {
+    if (kind == IMPCONV_TERNARY) return fail(IMPCONV_E_ARG, "ternary 2D convolutions use impconv_conv2d_ternary");
     PlanND p;
     impconv_status st = plannd(kind, dt, nd, m, n, batch, M, flags, &p);
     if (st) return st;
@@ -540,6 +644,13 @@ impconv_status impconv_conv3d(int kind, int dtype, int64_t batch, int64_t M, con
                               size_t work_bytes, uint32_t flags, void* stream)
 {
     return runnd(kind, dtype, 3, batch, M, m, n, f, g, h, work, work_bytes, flags, stream);
+}
+
+impconv_status impconv_conv2d_ternary(int dtype, int64_t batch, const int64_t* m, const int64_t* n,
+                                      const void* f, const void* g, const void* e, void* h, void* work,
+                                      size_t work_bytes, uint32_t flags, void* stream)
+{
+    return run2d_ternary(dtype, batch, m, n, f, g, e, h, work, work_bytes, flags, stream);
 }
 
 }  // extern "C"

@@ -31,9 +31,10 @@ impconv_status validate(const impconv_desc* d, size_t* work)
     if (d->ndim == 1)
         return impconv_conv1d_workspace(d->kind, d->dtype, d->batch, d->kind == IMPCONV_TERNARY ? 1 : d->M,
                                         d->m[0], d->flags, work);
-    if (d->kind == IMPCONV_TERNARY)
-        return fail(IMPCONV_E_UNSUPPORTED, "ternary convolutions are one-dimensional in this build");
-    return impconv_convnd_workspace(d->kind, d->dtype, d->ndim, d->m, d->n, d->batch, d->M, d->flags, work);
+    if (d->kind == IMPCONV_TERNARY && d->ndim != 2)
+        return fail(IMPCONV_E_UNSUPPORTED, "ternary convolutions are 1D or 2D in this build");
+    return impconv_convnd_workspace(d->kind, d->dtype, d->ndim, d->m, d->n, d->batch,
+                                    d->kind == IMPCONV_TERNARY ? 1 : d->M, d->flags, work);
 }
 
 // One-shot ragged wrapper: plans keyed by device, dtype and the descriptor
@@ -125,6 +126,8 @@ impconv_status impconv_execute(const impconv_plan* plan, const void* f, const vo
                 return impconv_conv1d_ternary(d.dtype, d.batch, d.m[0], f, g, e, h, work, work_bytes, d.flags, stream);
         }
     }
+    if (d.ndim == 2 && d.kind == IMPCONV_TERNARY)
+        return impconv_conv2d_ternary(d.dtype, d.batch, d.m, d.n, f, g, e, h, work, work_bytes, d.flags, stream);
     if (d.ndim == 2)
         return impconv_conv2d(d.kind, d.dtype, d.batch, d.M, d.m, d.n, f, g, h, work, work_bytes, d.flags, stream);
     return impconv_conv3d(d.kind, d.dtype, d.batch, d.M, d.m, d.n, f, g, h, work, work_bytes, d.flags, stream);

@@ -633,14 +633,18 @@ k_conv1d_ternary(RowArgs a)
     C<T> acc[ACCG ? 1 : E];
     tern_residue<T, NN, 0, ACCG>(a, c, m, t, lds, acc);
     tern_residue<T, NN, 1, ACCG>(a, c, m, t, lds, acc);
+    C<T>* H = (C<T>*)a.h + c.oh;
     if constexpr (!ACCG) {
-        C<T>* H = (C<T>*)a.h + c.oh;
         const T s = T(1) / T(4 * NN);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = t + e * G;
             if (k < m) H[k] = scale(acc[e], s);
         }
+    }
+    // stored slots past the logical length (zero slots of multi-D rows)
+    if (c.act) {
+        for (int64_t j = m + t; j < a.h_pad; j += G) H[j] = zero<T>();
     }
 }
 

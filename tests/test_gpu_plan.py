@@ -89,3 +89,14 @@ def test_oneshot_ragged_matches_plan():
     for m, o in zip(ms[:4], offs[:4]):
         assert rel(hr[o:o + m], oracle.conv1d_complex(rounded(f[o:o + m], np.complex64),
                                                       rounded(g[o:o + m], np.complex64))) < TOL[np.complex64]
+
+
+def test_plan_ternary_2d():
+    ic = need_gpu()
+    import torch
+    m, n = (6, 9), (12, 10)
+    f, g, e = (synth.unit_disk((2, *n), s) for s in (181, 182, 183))
+    F, G, E = (to_dev(x, np.complex128) for x in (f, g, e))
+    h = ic.Plan("ternary", torch.complex128, m, n=n, batch=2).execute(F, G, E)
+    assert torch.equal(h, ic.conv2d_ternary(F, G, E, m))
+    assert rel(h[1].cpu().numpy(), oracle.convnd_ternary(f[1], g[1], e[1], m)) < 1e-12

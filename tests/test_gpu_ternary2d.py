@@ -1,0 +1,106 @@
+"""GPU parity of the 2D centered Hermitian ternary convolution (Sec. 4,
+tconv2) against the FP64 oracle: full fields on small grids spanning several
+tiles, odd and even storage and ragged sizes; the symmetrization readings; a
+rank-one input on a 2048-mode x axis checked on the full field against
+outer products of 1D oracle results; sampled outputs of random inputs."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import TOL, need_gpu, rel, rounded, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+DT = [np.complex128, np.complex64]
+
+
+def storage(m, n, seed):
+    u = synth.unit_disk(n, seed)
+    if n[0] == 2 * m[0]:
+        u[0] = 0
+    if n[1] == m[1] + 1:
+        u[:, m[1]] = 0
+    return u
+
+
+@pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("m,n", [((1, 1), (1, 1)), ((1, 1), (2, 2)), ((2, 2), (4, 3)), ((3, 5), (5, 5)),
+                                 ((5, 4), (10, 5)), ((8, 8), (16, 9)), ((9, 17), (17, 17)),
+                                 ((16, 20), (32, 21))])
+def test_tconv2_full_field(dt, m, n):
+    ic = need_gpu()
+    say(f"tconv2 m={m} n={n} {dt.__name__}")
+    B = 2
+    f = np.stack([storage(m, n, 301 + b) for b in range(B)])
+    g = np.stack([storage(m, n, 303 + b) for b in range(B)])
+    e = np.stack([storage(m, n, 305 + b) for b in range(B)])
+    h = ic.conv2d_ternary(to_dev(f, dt), to_dev(g, dt), to_dev(e, dt), m).cpu().numpy()
+    for b in range(B):
+        ref = oracle.convnd_ternary(rounded(f[b], dt), rounded(g[b], dt), rounded(e[b], dt), m)
+        assert rel(h[b], ref) < TOL[dt], b
+    if n[0] == 2 * m[0]:
+        assert np.all(h[:, 0] == 0)
+    if n[1] == m[1] + 1:
+        assert np.all(h[:, :, m[1]] == 0)
+
+
+def test_tconv2_symmetrization_readings():
+    ic = need_gpu()
+    m, n = (6, 5), (12, 6)
+    f, g, e = storage(m, n, 311), storage(m, n, 312), storage(m, n, 313)
+    F, G, E = (to_dev(x, np.complex128) for x in (f, g, e))
+    h = ic.conv2d_ternary(F, G, E, m).cpu().numpy()
+    assert rel(h, oracle.convnd_ternary(f, g, e, m)) < 1e-12
+    hp = ic.conv2d_ternary(F, G, E, m, symmetrize=False).cpu().numpy()
+    assert rel(hp, oracle.convnd_ternary(f, g, e, m, symmetrize=False)) < 1e-12
+
+
+@pytest.mark.parametrize("dt", DT)
+def test_tconv2_rank_one_long_x(dt):
+    """U = A (x) b per input, m = (2048, 512): the result factors into a
+    full centered ternary sum in x (two numpy convolutions of the FP64
+    vectors) and the 1D Hermitian ternary oracle in y."""
+    ic = need_gpu()
+    say(f"tconv2 rank one 2048 x 512 {dt.__name__}")
+    mx, my = 2048, 512
+    n = (2 * mx, my + 1)
+    vecs = []
+    for s in (321, 322, 323):
+        a = synth.unit_disk(mx, s)
+        a[0] = a[0].real
+        full = np.concatenate([np.conj(a[:0:-1]), a])  # k = -mx+1 .. mx-1
+        vecs.append(full)
+    ys = []
+    for s in (324, 325, 326):
+        b = synth.unit_disk(my, s)
+        b[0] = b[0].real
+        ys.append(b)
+    fields = []
+    for A, b in zip(vecs, ys):
+        u = np.zeros(n, complex)
+        u[1:, :my] = np.outer(A, b)
+        fields.append(u)
+    h = ic.conv2d_ternary(*(to_dev(u, dt) for u in fields), (mx, my)).cpu().numpy()
+    Ar = [rounded(A, dt) for A in vecs]
+    br = [rounded(b, dt) for b in ys]
+    xfull = np.convolve(np.convolve(Ar[0], Ar[1]), Ar[2])[2 * (mx - 1):4 * (mx - 1) + 1]
+    yref = oracle.conv1d_ternary(*br)
+    ref = np.zeros(n, complex)
+    ref[1:, :my] = np.outer(xfull, yref)
+    # the input products of rounded vectors differ from the rounded products
+    # by one rounding; the FP32 tolerance covers it
+    assert rel(h, ref) < TOL[dt]
+    assert np.all(h[0] == 0) and np.all(h[:, my] == 0)
+
+
+@pytest.mark.parametrize("dt", DT)
+def test_tconv2_sampled(dt):
+    ic = need_gpu()
+    m, n = (64, 48), (127, 49)
+    f, g, e = storage(m, n, 331), storage(m, n, 332), storage(m, n, 333)
+    h = ic.conv2d_ternary(to_dev(f, dt), to_dev(g, dt), to_dev(e, dt), m).cpu().numpy()
+    pts = np.array([[0, 0], [-63, 47], [63, 0], [5, 3], [-20, 40], [31, 1]])
+    ref = oracle.convnd_ternary_at(rounded(f, dt), rounded(g, dt), rounded(e, dt), m, pts)
+    got = h[pts[:, 0] + 63, pts[:, 1]]
+    assert rel(got, ref) < TOL[dt]
