@@ -50,6 +50,16 @@ def flops_row_complex(N: int) -> float:
     return 6 * 5.0 * N * np.log2(max(N, 2)) + 34.0 * N
 
 
+def flops_row_ternary(NN: int) -> float:
+    """Algorithmic flops of one fused Hermitian ternary row (Sec. 4.2, tconv)
+    with packed FFT size NN (real length 2 NN per residue): for each of the
+    two residues three c2r and one r2c transform at 2.5 L log2 L (L = 2 NN),
+    the residue shifts (3 NN products), the triple real product and the
+    recombination."""
+    L = 2 * NN
+    return 2 * 4 * 2.5 * L * np.log2(max(L, 2)) + 2 * (3 * 6.0 * NN + 4.0 * L) + 8.0 * NN
+
+
 def flops_row_hermitian(NC: int, M: int = 1) -> float:
     """Algorithmic flops of one fused Hermitian row convolution with NC
     complex modes (m = 2 NC reals per transform, Sec. 2.3): for each of the
@@ -415,7 +425,93 @@ def wl_c5(args):
                 kflops_step=kflops_step, cfg=cfg, cpu=cpu_baseline, out=lambda: run().detach().cpu().numpy())
 
 
-WORKLOADS = {"c1": wl_c1, "c2": wl_c2, "c3": wl_c3, "c4": wl_c4, "c5": wl_c5}
+def wl_t2(args):
+    """2D centered Hermitian ternary convolution (Sec. 4, tconv2) of three
+    fields per pair: m = (M, M) modes, storage (2M, M + 1), batch B, spectra
+    |k|^-1 with random phase and a Hermitian k_y = 0 line."""
+    import torch
+    import paper_1008_1366_amd as ic
+    import synth
+    cdt = torch.complex64 if args.dtype == "c64" else torch.complex128
+    dt_np = np.complex64 if cdt == torch.complex64 else np.complex128
+    mm = args.t2_m
+    m, n = (mm, mm), (2 * mm, mm + 1)
+    B = args.batch or 8
+
+    def field(mv, nv, seed):
+        u = synth.power_spectrum_centered(mv, nv, 1.0, seed)
+        off = nv[0] - mv[0]
+        u[off - np.arange(1, mv[0]), 0] = np.conj(u[off + np.arange(1, mv[0]), 0])
+        return u
+
+    fs = [np.stack([field(m, n, 400 + 3 * b + q) for b in range(B)]) for q in range(3)]
+    F, G, E = (torch.from_numpy(x).to("cuda", cdt) for x in fs)
+    cs = 8 if cdt == torch.complex64 else 16
+    S = B * n[0] * n[1] * cs
+    run = lambda: ic.conv2d_ternary(F, G, E, m)
+    expl = (lambda: ic.conv2d_ternary(F, G, E, m, method="explicit")) if mm <= 1024 else None
+    P0 = 2 * (1 << int(np.ceil(np.log2(mm))))
+    # per launch: x backward reads one input (S) and writes two residues (2S);
+    # rows read three residue arrays and write one; x forward reads 2S, writes S
+    kbytes = {"colpass_ter_bwd": 3 * S, "k_conv1d_ternary": 4 * S, "colpass_ter_fwd": 3 * S}
+    kflops = {"k_conv1d_ternary": B * P0 * flops_row_ternary(1 << int(np.ceil(np.log2(mm))))}
+    step_bytes = 20 * S
+
+    def cpu_baseline(h_gpu, h_expl=None):
+        """The oracle's direct sum costs O(|box|^2) per output (1.8e13
+        multiply-adds per point at M = 1024), so it is timed on the full
+        field of a reduced instance of the same recipe (M = 20) and its rate
+        extrapolated by multiply-add count.  Errors at full size: a rank-one
+        triple (U = A (x) b per field) against outer products of a numpy
+        centered ternary sum in x and the 1D ternary oracle in y; on the
+        reduced instance, the full field of the GPU result."""
+        import oracle
+        ms_, ns_ = (20, 20), (40, 21)
+        small = [field(ms_, ns_, 500 + q) for q in range(3)]
+        sr = [np.asarray(x.astype(dt_np), np.complex128) for x in small]
+        t0 = time.perf_counter()
+        ref = oracle.convnd_ternary(*sr, ms_)
+        t_or = time.perf_counter() - t0
+        box = (2 * ms_[0] - 1) * (2 * ms_[1] - 1)
+        macs_small = box * box * ms_[0] * (2 * ms_[0] - 1) / 2.0  # ~ |box|^2 / 2 per output, half the outputs
+        boxf = (2 * mm - 1) ** 2
+        macs_full = boxf * boxf * mm * (2 * mm - 1) / 2.0
+        hs = ic.conv2d_ternary(*(torch.from_numpy(x).to("cuda", cdt) for x in small), ms_).cpu().numpy()
+        err_small = float(np.linalg.norm(hs - ref) / np.linalg.norm(ref))
+        # rank-one triple at full size
+        vecs, ys, us = [], [], []
+        for q in range(3):
+            a = synth.unit_disk(mm, 511 + q)
+            a[0] = a[0].real
+            A = np.concatenate([np.conj(a[:0:-1]), a])
+            b = synth.unit_disk(mm, 521 + q)
+            b[0] = b[0].real
+            u = np.zeros(n, complex)
+            u[1:, :mm] = np.outer(A, b)
+            vecs.append(np.asarray(A.astype(dt_np), np.complex128))
+            ys.append(np.asarray(b.astype(dt_np), np.complex128))
+            us.append(u)
+        h1 = ic.conv2d_ternary(*(torch.from_numpy(u).to("cuda", cdt) for u in us), m).cpu().numpy()
+        xfull = np.convolve(np.convolve(vecs[0], vecs[1]), vecs[2])[2 * (mm - 1):4 * (mm - 1) + 1]
+        yref = oracle.conv1d_ternary(*ys)
+        r1 = np.zeros(n, complex)
+        r1[1:, :mm] = np.outer(xfull, yref)
+        err = {"rank_one_full_field": float(np.linalg.norm(h1 - r1) / np.linalg.norm(r1)),
+               "reduced_instance_full_field": err_small}
+        return {"value": 1.0 / (t_or / macs_small * macs_full), "unit": "convs/s", "cores": oracle.num_threads(),
+                "kind": "oracle",
+                "sample": f"full field of a {ms_[0]}x{ms_[1]} instance of the same recipe ({t_or:.2f} s), "
+                          f"extrapolated to M = {mm} by multiply-add count"}, err
+
+    cfg = {"workload": f"2D centered Hermitian ternary convolution (tconv2) {mm}x{mm} modes, storage "
+                       f"{n[0]}x{n[1]}, batch {B} triples per step, "
+                       f"{'complex64' if cdt == torch.complex64 else 'complex128'}",
+           "m": list(m), "n": list(n), "batch": B, "dtype": args.dtype}
+    return dict(run=run, explicit=expl, convs=B, step_bytes=step_bytes, kbytes=kbytes, kflops=kflops, cfg=cfg,
+                cpu=cpu_baseline, out=lambda: run().cpu().numpy())
+
+
+WORKLOADS = {"c1": wl_c1, "c2": wl_c2, "c3": wl_c3, "c4": wl_c4, "c5": wl_c5, "t2": wl_t2}
 
 
 def main():
@@ -429,6 +525,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-explicit", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="c5: keep the default four-step splits")
+    ap.add_argument("--t2-m", type=int, default=1024, help="t2: modes per axis")
     # oracle sample sizes (about 10 s of host work each)
     ap.add_argument("--cpu-points", type=int, default=65536, help="c3: sampled output points over the batch")
     ap.add_argument("--cpu-rows", type=int, default=0, help="c1/c2: convolutions (0: workload default)")
@@ -537,7 +634,7 @@ def main():
             cpu, err = W["cpu"](h, W["explicit"]().cpu().numpy())
         else:
             cpu, err = W["cpu"](h)
-        out["cpu_baseline"] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in cpu.items()}
+        out["cpu_baseline"] = {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in cpu.items()}
         out["rel_err_vs_oracle"] = err
     print(json.dumps(out), flush=True)
 

@@ -121,7 +121,10 @@ impconv_status impconv_conv1d_hermitian(int dtype, int64_t batch, int64_t M, int
 
 /* Centered Hermitian ternary 1D convolution, Sec. 4 (Fourier size 4N):
  * f, g, e are [batch][m] Hermitian halves (Im of entry 0 ignored);
- *   h_k = sum_{p,q,r in [-m+1, m-1], p+q+r=k} f_p g_q e_r,   k = 0..m-1. */
+ *   h_k = sum_{p,q,r in [-m+1, m-1], p+q+r=k} f_p g_q e_r,   k = 0..m-1.
+ * IMPCONV_EXPLICIT_PADDED: conventional comparator (half spectra copied into
+ * real-FFT buffers of length 2^ceil(log2(4m-3)), physical-space triple
+ * product; m <= 4096). */
 impconv_status impconv_conv1d_ternary(int dtype, int64_t batch, int64_t m, const void* f,
                                       const void* g, const void* e, void* h, void* work,
                                       size_t work_bytes, uint32_t flags, void* stream);
@@ -187,7 +190,13 @@ impconv_status impconv_conv3d(int kind, int dtype, int64_t batch, int64_t M, con
  * transforms of size 2 N0'), every row the 1D ternary convolution.  Workspace
  * (impconv_convnd_workspace with kind IMPCONV_TERNARY, ndim 2, M = 1):
  * 8 * batch * 2 N0' * n1 complex values.  This build: m0 <= 2048,
- * m1 <= 8192; E_UNSUPPORTED beyond and for IMPCONV_EXPLICIT_PADDED. */
+ * m1 <= 8192; E_UNSUPPORTED beyond.
+ * IMPCONV_EXPLICIT_PADDED: the conventional comparator -- f, g, e copied into
+ * zero-padded [4 N0'][2 N1' + 1] arrays (x wavenumbers wrapped modulo 4 N0'),
+ * full-size complex FFTs along x, real cyclic triple products of length
+ * 4 N1' along y, inverse x FFT, crop; it reads the k_y = 0 line as its
+ * Hermitian projection (m0 <= 1024, m1 <= 4096; workspace
+ * 3 * batch * 4 N0' * (2 N1' + 1) complex values). */
 impconv_status impconv_conv2d_ternary(int dtype, int64_t batch, const int64_t* m, const int64_t* n,
                                       const void* f, const void* g, const void* e, void* h,
                                       void* work, size_t work_bytes, uint32_t flags, void* stream);

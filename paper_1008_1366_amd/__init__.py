@@ -204,8 +204,10 @@ def conv1d_hermitian(f, g, method: str = "implicit"):
     return _conv1d(HERMITIAN, f, g, method, 0)
 
 
-def conv1d_ternary(f, g, e):
-    """Centered Hermitian ternary convolution (Sec. 4) of (m,) or (B, m) halves."""
+def conv1d_ternary(f, g, e, method: str = "implicit"):
+    """Centered Hermitian ternary convolution (Sec. 4) of (m,) or (B, m) halves;
+    method="explicit" runs the explicitly zero-padded comparator."""
+    flags = {"implicit": 0, "explicit": EXPLICIT_PADDED}[method]
     if not (f.shape == g.shape == e.shape) or not (f.dtype == g.dtype == e.dtype):
         raise ValueError("f, g, e must share shape and dtype")
     dev = _dev(f, g, e)
@@ -213,9 +215,9 @@ def conv1d_ternary(f, g, e):
     B, m = F.shape
     dt = _dtype_code(f)
     h = torch.empty((B, m), dtype=f.dtype, device=dev)
-    wb = workspace_bytes(TERNARY, dt, B, 1, m, 0)
+    wb = workspace_bytes(TERNARY, dt, B, 1, m, flags)
     w = _work(wb, dev)
-    _check(lib().impconv_conv1d_ternary(dt, B, m, _ptr(F), _ptr(G), _ptr(Ev), _ptr(h), _ptr(w), wb, 0,
+    _check(lib().impconv_conv1d_ternary(dt, B, m, _ptr(F), _ptr(G), _ptr(Ev), _ptr(h), _ptr(w), wb, flags,
                                         ctypes.c_void_p(_stream(dev))), "conv1d_ternary")
     return h.view(m) if f.dim() == 1 else h
 
@@ -267,9 +269,10 @@ def conv2d(f, g, kind: str = "complex", m=None, symmetrize: bool = True, method:
     return _convnd(2, f, g, kind, m, flags)
 
 
-def conv2d_ternary(f, g, e, m, symmetrize: bool = True):
+def conv2d_ternary(f, g, e, m, symmetrize: bool = True, method: str = "implicit"):
     """2D centered Hermitian ternary convolution (Sec. 4, tconv2) of inputs
-    (n0, n1) or (B, n0, n1) in the 2D Hermitian storage; m = (m0, m1)."""
+    (n0, n1) or (B, n0, n1) in the 2D Hermitian storage; m = (m0, m1).
+    method="explicit" runs the explicitly zero-padded comparator."""
     if not (f.shape == g.shape == e.shape) or not (f.dtype == g.dtype == e.dtype):
         raise ValueError("f, g, e must share shape and dtype")
     dev = _dev(f, g, e)
@@ -277,7 +280,7 @@ def conv2d_ternary(f, g, e, m, symmetrize: bool = True):
     B = 1 if f.dim() == 2 else f.shape[0]
     m = tuple(int(x) for x in m)
     dt = _dtype_code(f)
-    flags = 0 if symmetrize else NO_SYMMETRIZE
+    flags = (0 if symmetrize else NO_SYMMETRIZE) | {"implicit": 0, "explicit": EXPLICIT_PADDED}[method]
     marr = (ctypes.c_int64 * 2)(*m)
     narr = (ctypes.c_int64 * 2)(*n)
     out = _sz()

@@ -106,9 +106,17 @@ impconv_status plan1d(int kind, int dt, int64_t batch, int64_t M, int64_t m, uin
             p->work = size_t(batch) * (2 * M + 1) * (Ne / 2 + 1) * cs;
         }
     } else if (kind == IMPCONV_TERNARY) {
-        if (p->explicit_) return fail(IMPCONV_E_UNSUPPORTED, "no explicit ternary comparator");
         p->N = next_pow2(m);
-        if (p->N > kRowMax) return fail(IMPCONV_E_UNSUPPORTED, "ternary convolution supports m <= 8192");
+        if (!p->explicit_) {
+            if (p->N > kRowMax) return fail(IMPCONV_E_UNSUPPORTED, "ternary convolution supports m <= 8192");
+        } else {
+            // conventional: real transform length 2^ceil(log2(4m-3)) (no wave beating of
+            // three factors), half spectrum + 1 per padded row of f, g, e and h
+            const int64_t Ne = next_pow2(std::max<int64_t>(4 * m - 3, 2));
+            p->Ne = Ne;
+            if (Ne / 2 > kRowMax) return fail(IMPCONV_E_UNSUPPORTED, "explicit ternary comparator supports m <= 4096");
+            p->work = size_t(batch) * 4 * (Ne / 2 + 1) * cs;
+        }
     } else {
         return fail(IMPCONV_E_ARG, "unknown kind");
     }
@@ -218,9 +226,16 @@ static impconv_status run1d(int kind, int dtype, int64_t batch, int64_t M, int64
     void* fp = w;
     void* gp = w + size_t(batch) * M * L * cs;
     void* hp = w + size_t(batch) * 2 * M * L * cs;
+    void* ep = w + size_t(batch) * 3 * M * L * cs;  // ternary (M = 1)
     if ((err = launch_pad_rows(dt, f, fp, batch * M, m, m, L, s)) != hipSuccess) return hip_fail(err, "pad");
     if ((err = launch_pad_rows(dt, g, gp, batch * M, m, m, L, s)) != hipSuccess) return hip_fail(err, "pad");
+    if (kind == IMPCONV_TERNARY && (err = launch_pad_rows(dt, e, ep, batch, m, m, L, s)) != hipSuccess)
+        return hip_fail(err, "pad");
     a.f = fp; a.g = gp; a.h = hp;
+    if (kind == IMPCONV_TERNARY) {
+        a.e = ep;
+        a.e_row = L;
+    }
     a.f_row = a.g_row = M * L;
     a.f_i = a.g_i = L;
     a.h_row = L;

@@ -195,7 +195,7 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
     if (batch < 0 || M < 1) return fail(IMPCONV_E_SIZE, "batch must be >= 0 and M >= 1");
     const uint32_t known = IMPCONV_NO_SYMMETRIZE | IMPCONV_EXPLICIT_PADDED;
     if (flags & ~known) return fail(IMPCONV_E_ARG, "unsupported flag for an nD convolution");
-    if ((flags & IMPCONV_EXPLICIT_PADDED) && (kind != IMPCONV_COMPLEX || nd != 2))
+    if ((flags & IMPCONV_EXPLICIT_PADDED) && kind == IMPCONV_HERMITIAN)
         return fail(IMPCONV_E_UNSUPPORTED, "the explicitly padded comparator covers 2D complex convolutions");
     std::memset(p, 0, sizeof(*p));
     p->kind = kind; p->dt = dt; p->nd = nd; p->batch = batch; p->M = M; p->flags = flags;
@@ -223,14 +223,20 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
     }
     const size_t cs = csize(dt);
     const int R = kind == IMPCONV_COMPLEX ? 2 : 3;
-    if (flags & IMPCONV_EXPLICIT_PADDED) {
+    if ((flags & IMPCONV_EXPLICIT_PADDED) && kind == IMPCONV_COMPLEX) {
         // padded f and g, [b][2N0][M][2N1]
         const int64_t P0 = 2 * p->Np[0], P1 = 2 * p->Np[1];
         if (P0 > kColMax || P1 > kRowMax) return fail(IMPCONV_E_UNSUPPORTED, "explicit 2D comparator supports m <= 2048 per axis");
         p->work = size_t(2) * batch * M * P0 * P1 * cs;
         return IMPCONV_OK;
     }
-    if (kind == IMPCONV_TERNARY) {
+    if (kind == IMPCONV_TERNARY && (flags & IMPCONV_EXPLICIT_PADDED)) {
+        // padded f, g, e: [b][4 Np0][2 Np1 + 1] (x padded to 4 Np0, y real length 4 Np1)
+        const int64_t P0 = 4 * p->Np[0], L = 2 * p->Np[1] + 1;
+        if (P0 > kColMax || 2 * p->Np[1] > kRowMax)
+            return fail(IMPCONV_E_UNSUPPORTED, "explicit ternary 2D comparator supports m0 <= 1024, m1 <= 4096");
+        p->work = size_t(3) * batch * P0 * L * cs;
+    } else if (kind == IMPCONV_TERNARY) {
         // x residues of f, g, e (2 each, 2 Np0 rows) and the two row outputs
         p->work = size_t(8) * batch * 2 * p->Np[0] * n[1] * cs;
     } else if (nd == 2) {
@@ -361,6 +367,66 @@ impconv_status run2d_ternary(int dt, int64_t batch, const int64_t* m, const int6
     const DevTables& tb = *tbp;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const bool sym = !(flags & IMPCONV_NO_SYMMETRIZE);
+    if (flags & IMPCONV_EXPLICIT_PADDED) {
+        // Conventional method: f, g, e copied into zero-padded [4 N0'][2 N1' + 1]
+        // arrays (k_x at row k_x mod 4 N0', so every x point of the transform is
+        // a real field in y; k_y < m1 at column k_y), a full-size complex FFT
+        // along x, a real cyclic triple product of length 4 N1' along y, the
+        // inverse x FFT, and the crop.  No alias of |k_x| <= 3(m0-1) reaches
+        // an output |k_x| < m0 since 4 N0' >= 4 m0.  The k_y = 0 line is read
+        // by the c2r transform, i.e. as its Hermitian projection (the same as
+        // the implicit path for symmetric input).
+        const int64_t P0 = 4 * p.Np[0], NC = 2 * p.Np[1], L = NC + 1;
+        const size_t arr = size_t(batch) * P0 * L * cs;
+        char* w = static_cast<char*>(work);
+        void* W[3] = {w, w + arr, w + 2 * arr};
+        const void* src[3] = {f, g, e};
+        const int64_t r0 = n0 - m0;          // stored row of k_x = 0
+        const int64_t s0 = n0 - (2 * m0 - 1);  // stored row of k_x = -m0+1
+        auto rowp = [&](const void* base, int64_t row, int64_t ld) {
+            return static_cast<const char*>(base) + row * ld * int64_t(cs);
+        };
+        for (int q = 0; q < 3; ++q) {
+            // k_x >= 0 (and zero fill of the whole array), then k_x < 0 at the top
+            HIPCHK(launch_copy2d(dt, rowp(src[q], r0, n1), W[q], batch, 1, n0 * n1, 0, n1, P0 * L, 0, L, m0, m1,
+                                 P0, L, s), "explicit pad");
+            HIPCHK(launch_copy2d(dt, rowp(src[q], s0, n1), (void*)rowp(W[q], P0 - m0 + 1, L), batch, 1, n0 * n1, 0,
+                                 n1, P0 * L, 0, L, m0 - 1, m1, m0 - 1, L, s), "explicit pad");
+            ColArgs a = col_args(tb, dt);
+            a.in[0] = a.out[0] = W[q];
+            a.nslab = batch;
+            a.in_bs = a.out_bs = P0 * L;
+            a.ncols = L;
+            a.in_ld = a.out_ld = L;
+            a.n_in = a.n_out = int(P0);
+            HIPCHK(launch_col(dt, int(P0), kFft, 1, a, s), "explicit x FFT");
+        }
+        RowArgs ra = row_args(tb, dt);
+        ra.f = W[0]; ra.g = W[1]; ra.e = W[2]; ra.h = W[0];
+        ra.nrows = batch * P0;
+        ra.m = L;
+        ra.m_out = m1;
+        ra.M = 1;
+        ra.f_row = ra.g_row = ra.e_row = ra.h_row = L;
+        ra.scale = 1.0 / double(2 * NC);
+        HIPCHK(launch_row_realcyclic(dt, int(NC), ra, s), "explicit y triple product");
+        ColArgs a = col_args(tb, dt);
+        a.in[0] = a.out[0] = W[0];
+        a.nslab = batch;
+        a.in_bs = a.out_bs = P0 * L;
+        a.ncols = m1;
+        a.in_ld = a.out_ld = L;
+        a.n_in = a.n_out = int(P0);
+        a.scale = 1.0 / double(P0);
+        HIPCHK(launch_col(dt, int(P0), kFft, -1, a, s), "explicit inverse x FFT");
+        HIPCHK(launch_copy2d(dt, W[0], (void*)rowp(h, r0, n1), batch, 1, P0 * L, 0, L, n0 * n1, 0, n1, m0, m1, m0,
+                             n1, s), "explicit crop");
+        HIPCHK(launch_copy2d(dt, rowp(W[0], P0 - m0 + 1, L), (void*)rowp(h, s0, n1), batch, 1, P0 * L, 0, L,
+                             n0 * n1, 0, n1, m0 - 1, m1, m0 - 1, n1, s), "explicit crop");
+        if (s0 > 0)  // zero slot row k_x = -m0
+            HIPCHK(launch_copy2d(dt, h, h, batch, 1, 0, 0, 0, n0 * n1, 0, n1, 0, 0, 1, n1, s), "zero slot");
+        return IMPCONV_OK;
+    }
     const int64_t P0 = 2 * p.Np[0];  // x transform size (residues of the 4 N0' padding)
     const size_t arr = size_t(batch) * P0 * n1 * cs;
     char* w = static_cast<char*>(work);

@@ -619,27 +619,92 @@ __device__ __forceinline__ void tern_residue(const RowArgs& a, const RowCtx& c, 
 // complex-to-real at length 2N, the three real transforms are multiplied,
 // transformed back, and 4N H_k = sum_r zeta_{4N}^{-rk} V_r(k).
 // ======================================================================
+template <typename T>
+__device__ __forceinline__ C<T>* sh_dual(C<T>* sh, int GPB, int LDSN, int grp)
+{
+    return sh + (GPB + grp) * LDSN;
+}
+
 template <typename T, int NN, bool ACCG>
 __global__ void __launch_bounds__((row_block<T, 1>(NN)), row_waves<T>(NN))
 k_conv1d_ternary(RowArgs a)
 {
     constexpr int E = row_E<T, 1>(NN), G = NN / E, GPB = row_GPB<T, 1>(NN), LDSN = row_lds<T, 1>(NN);
-    __shared__ C<T> sh[GPB * LDSN];
+    constexpr bool DUALS = !ACCG && 2 * GPB * LDSN * int(sizeof(C<T>)) <= 160 * 1024;
+    __shared__ C<T> sh[(DUALS ? 2 : 1) * GPB * LDSN];
     static_assert(sizeof(sh) <= 160 * 1024, "LDS footprint exceeds 160 KB");
     const int grp = threadIdx.x / G, t = threadIdx.x % G;
     const RowCtx c = row_ctx(a, (int64_t)blockIdx.x * GPB + grp);
     C<T>* lds = sh + grp * LDSN;
     const int m = c.m;
-    C<T> acc[ACCG ? 1 : E];
-    tern_residue<T, NN, 0, ACCG>(a, c, m, t, lds, acc);
-    tern_residue<T, NN, 1, ACCG>(a, c, m, t, lds, acc);
     C<T>* H = (C<T>*)a.h + c.oh;
-    if constexpr (!ACCG) {
+    if constexpr (ACCG) {
+        // large rows: one residue at a time, accumulating in h
+        C<T> acc[1];
+        tern_residue<T, NN, 0, ACCG>(a, c, m, t, lds, acc);
+        tern_residue<T, NN, 1, ACCG>(a, c, m, t, lds, acc);
+    } else {
+        // Each input row is read once; both residues are built from the
+        // same registers and transformed together (paired transforms share
+        // twiddles and barriers, through two exchange buffers when they fit).
+        constexpr bool DUAL = 2 * GPB * LDSN * int(sizeof(C<T>)) <= 160 * 1024;
+        C<T>* lds1 = DUAL ? sh_dual<T>(sh, GPB, LDSN, grp) : lds;
+        const C<T>* twb = (const C<T>*)a.tw;
+        const C<T>* twNN = twb + tw_off(NN);
+        const int mm = m < NN ? m : NN;
+        auto pair = [&](auto& a0, auto& a1, auto dir) {
+            constexpr int D = decltype(dir)::value;
+            if constexpr (DUAL) {
+                fft2<T, NN, E, D>(a0, a1, t, lds, lds1, 1, twNN);
+            } else {
+                fft<T, NN, E, D>(a0, t, lds, 1, twNN);
+                fft<T, NN, E, D>(a1, t, lds, 1, twNN);
+            }
+        };
+        // packed c2r inputs of residues 0 and 1: X_r(j) = zeta_{4NN}^{rj} U_j
+        // (U_0 real, U_NN = 0), Z_r(k) = c2r_pre(X_r(k), X_r(NN - k))
+        auto build = [&](const void* base, int64_t off, C<T> (&z0)[E], C<T> (&z1)[E]) {
+            const int q = opaque_zero();
+            const C<T>* U = (const C<T>*)base + off + q;
+            const C<T>* tw2N = twb + tw_off(2 * NN) + q;
+            const C<T>* tw4N = twb + tw_off(4 * NN) + q;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int k = t + e * G;
+                C<T> u = ldz(U, k, mm), v = ldz(U, NN - k, mm);
+                if (e == 0 && k == 0) u.im = T(0);
+                const C<T> w = tw2N[k];
+                z0[e] = c2r_pre(u, v, w);
+                z1[e] = c2r_pre(u * tw4N[k], v * tw4N[(NN - k) & (NN - 1)], w);
+            }
+        };
+        C<T> x0[E], x1[E];
+        build(a.f, c.of, x0, x1);
+        pair(x0, x1, std::integral_constant<int, +1>{});
+        static_for<2>([&](auto qi) {
+            C<T> y0[E], y1[E];
+            build(decltype(qi)::value == 0 ? a.g : a.e, decltype(qi)::value == 0 ? c.og : c.oe, y0, y1);
+            pair(y0, y1, std::integral_constant<int, +1>{});
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                x0[e] = C<T>{x0[e].re * y0[e].re, x0[e].im * y0[e].im};
+                x1[e] = C<T>{x1[e].re * y1[e].re, x1[e].im * y1[e].im};
+            }
+        });
+        pair(x0, x1, std::integral_constant<int, -1>{});
+        C<T> y0[E], y1[E];
+        mirror<T, NN, E>(x0, y0, t, lds);
+        mirror<T, NN, E>(x1, y1, t, lds);
+        const int q = opaque_zero();
+        const C<T>* tw2N = twb + tw_off(2 * NN) + q;
+        const C<T>* tw4N = twb + tw_off(4 * NN) + q;
         const T s = T(1) / T(4 * NN);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = t + e * G;
-            if (k < m) H[k] = scale(acc[e], s);
+            const C<T> w = tw2N[k];
+            const C<T> V = r2c_post(x0[e], y0[e], w) + mulc(r2c_post(x1[e], y1[e], w), tw4N[k]);
+            if (k < m) H[k] = scale(V, s);
         }
     }
     // stored slots past the logical length (zero slots of multi-D rows)
@@ -653,10 +718,10 @@ k_conv1d_ternary(RowArgs a)
 namespace impconv {
 
 // ======================================================================
-// Plain cyclic convolution of two real sequences of length 2 NC given by
-// their half spectra X_0..X_NC (rows of length >= NC + 1): the explicitly
-// padded centered Hermitian comparator (2/3 rule with materialized padding).
-// h_k = scale * r2c(c2r(f) c2r(g))_k, k < m_out.
+// Plain cyclic convolution of two (or, with a.e, three) real sequences of
+// length 2 NC given by their half spectra X_0..X_NC (rows of length >= NC + 1):
+// the explicitly padded centered Hermitian comparators (materialized
+// padding).  h_k = scale * r2c(c2r(f) c2r(g) [c2r(e)])_k, k < m_out.
 // ======================================================================
 template <typename T, int NC>
 __global__ void __launch_bounds__((row_block<T, 1>(NC)), row_waves<T>(NC))
@@ -700,10 +765,24 @@ k_conv1d_realcyclic(RowArgs a)
         }
         fft<T, NC, E, +1>(y, t, lds, 1, twNC);
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const C<T> p{x[e].re * y[e].re, x[e].im * y[e].im};
-            P[e] = i ? P[e] + p : p;
+        for (int e = 0; e < E; ++e) x[e] = C<T>{x[e].re * y[e].re, x[e].im * y[e].im};
+        if (a.e) {
+            // third real factor (explicitly padded ternary comparator)
+            const int z = opaque_zero();
+            const C<T>* Ep = (const C<T>*)a.e + c.oe + z;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int k = t + e * G;
+                C<T> xk = ldz(Ep, k, m), xm = ldz(Ep, NC - k, m);
+                if (k == 0) xk.im = T(0);
+                y[e] = c2r_pre(xk, xm, tw2[k + z]);
+            }
+            fft<T, NC, E, +1>(y, t, lds, 1, twNC);
+#pragma unroll
+            for (int e = 0; e < E; ++e) x[e] = C<T>{x[e].re * y[e].re, x[e].im * y[e].im};
         }
+#pragma unroll
+        for (int e = 0; e < E; ++e) P[e] = i ? P[e] + x[e] : x[e];
     }
     fft<T, NC, E, -1>(P, t, lds, 1, twNC);
     C<T> Pm[E];

@@ -134,7 +134,7 @@ def test_plan_create_validation(L):
     assert create(batch=-1) == 2
     assert create(kind=2, ndim=3, m=(4, 4, 4), n=(8, 8, 5)) == 5  # ternary is 1D or 2D
     assert create(kind=2, ndim=2, m=(4096, 4, 0), n=(8192, 5, 0)) == 5  # ternary x axis m <= 2048
-    assert create(kind=2, ndim=2, m=(4, 4, 0), n=(8, 5, 0), flags=1) == 5  # no explicit ternary
+    assert create(kind=2, ndim=2, m=(2048, 4, 0), n=(4096, 5, 0), flags=1) == 5  # explicit: m0 <= 1024
     assert create(kind=1, ndim=2, m=(4, 4, 0), n=(9, 5, 0)) == 2  # centered axis needs 2m-1 or 2m
     assert create(kind=0, ndim=2, m=(4, 4, 0), n=(4, 5, 0)) == 2  # complex storage n == m
     assert create(flags=1 << 7) == 1

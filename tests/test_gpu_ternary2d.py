@@ -104,3 +104,47 @@ def test_tconv2_sampled(dt):
     ref = oracle.convnd_ternary_at(rounded(f, dt), rounded(g, dt), rounded(e, dt), m, pts)
     got = h[pts[:, 0] + 63, pts[:, 1]]
     assert rel(got, ref) < TOL[dt]
+
+
+def symmetric_storage(m, n, seed):
+    """Storage whose k_y = 0 line is already Hermitian (the comparator reads
+    that line as its projection, the implicit path by its positive half)."""
+    u = storage(m, n, seed)
+    off = n[0] - m[0]
+    for k in range(1, m[0]):
+        u[off - k, 0] = np.conj(u[off + k, 0])
+    u[off, 0] = u[off, 0].real
+    return u
+
+
+@pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("m,n", [((1, 1), (1, 1)), ((2, 3), (4, 4)), ((5, 4), (9, 5)), ((12, 17), (24, 18))])
+def test_tconv2_explicit_comparator(dt, m, n):
+    ic = need_gpu()
+    say(f"tconv2 explicit m={m} n={n} {dt.__name__}")
+    B = 2
+    f = np.stack([symmetric_storage(m, n, 341 + b) for b in range(B)])
+    g = np.stack([symmetric_storage(m, n, 343 + b) for b in range(B)])
+    e = np.stack([symmetric_storage(m, n, 345 + b) for b in range(B)])
+    args = [to_dev(x, dt) for x in (f, g, e)]
+    he = ic.conv2d_ternary(*args, m, method="explicit").cpu().numpy()
+    hi = ic.conv2d_ternary(*args, m).cpu().numpy()
+    for b in range(B):
+        ref = oracle.convnd_ternary(rounded(f[b], dt), rounded(g[b], dt), rounded(e[b], dt), m)
+        assert rel(he[b], ref) < TOL[dt], b
+        assert rel(hi[b], ref) < TOL[dt], b
+    if n[0] == 2 * m[0]:
+        assert np.all(he[:, 0] == 0)
+    if n[1] == m[1] + 1:
+        assert np.all(he[:, :, m[1]] == 0)
+
+
+@pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("m", [1, 2, 7, 64, 300])
+def test_ternary_1d_explicit_comparator(dt, m):
+    ic = need_gpu()
+    f, g, e = (synth.unit_disk((3, m), s) for s in (351, 352, 353))
+    h = ic.conv1d_ternary(to_dev(f, dt), to_dev(g, dt), to_dev(e, dt), method="explicit").cpu().numpy()
+    for b in range(3):
+        ref = oracle.conv1d_ternary(rounded(f[b], dt), rounded(g[b], dt), rounded(e[b], dt))
+        assert rel(h[b], ref) < TOL[dt]
