@@ -73,6 +73,7 @@ typedef enum impconv_kind {
 #define IMPCONV_CONJ_G (1u << 2)          /* complex 1D: read g conjugated */
 #define IMPCONV_REV_OUT (1u << 3)         /* complex 1D: write h reversed */
 #define IMPCONV_NO_SYMMETRIZE (1u << 4)   /* Hermitian nD: trust the k_last = 0 plane (see conv2d) */
+#define IMPCONV_HERMITIAN_ADJOINT (1u << 5) /* Hermitian 1D: f_0 read as 2 Re f_0, h_0 stored halved */
 
 /* Version as 10000*major + 100*minor + patch. */
 int impconv_version(void);
@@ -114,7 +115,14 @@ impconv_status impconv_conv1d_complex(int dtype, int64_t batch, int64_t M, int64
  * U_{-k} = conj U_k; Im f_0 and Im g_0 are ignored.
  *   h_k = sum_{i<M} sum_{p=k-m+1}^{m-1} f_{i,p} g_{i,k-p},   k = 0..m-1.
  * IMPCONV_EXPLICIT_PADDED: conventional comparator (half spectra copied into
- * a real-FFT buffer of size 2^ceil(log2(3m-2)), physical-space product). */
+ * a real-FFT buffer of size 2^ceil(log2(3m-2)), physical-space product).
+ * IMPCONV_HERMITIAN_ADJOINT gives the vector-Jacobian product: for a real
+ * loss L of h and gh = dL/dRe h + i dL/dIm h, the gradient with respect to
+ * the stored half of f is conv1d_hermitian(gh', g) with gh'_0 = 2 Re gh_0 and
+ * its entry 0 halved and real (the coupling f_{-p} = conj f_p folds the
+ * negative wavenumbers into the positive ones); this flag applies exactly
+ * those two edits, on load of the first input and on store.  Not accepted
+ * with IMPCONV_EXPLICIT_PADDED. */
 impconv_status impconv_conv1d_hermitian(int dtype, int64_t batch, int64_t M, int64_t m,
                                         const void* f, const void* g, void* h, void* work,
                                         size_t work_bytes, uint32_t flags, void* stream);
@@ -160,6 +168,9 @@ size_t impconv_timing_report(char* buf, size_t cap);
  *                      Hermitian projection (U_k + conj U_{-k}) / 2 instead
  *                      (identical for already-symmetric input).  Zero slots
  *                      of h are written as 0.
+ * IMPCONV_COMPLEX also accepts IMPCONV_REV_F / IMPCONV_CONJ_G /
+ * IMPCONV_REV_OUT as in 1D, each reversal applying to every axis within
+ * m[d] (the adjoint: dL/df = REV_OUT(conv(REV_F(dL/dh), CONJ_G(g)))).
  * IMPCONV_EXPLICIT_PADDED (2D complex only): the conventional comparator --
  * inputs copied into zero-padded 2N0 x 2N1 work arrays, full-size FFTs along
  * both axes, product, inverse, crop (m[d] <= 2048).

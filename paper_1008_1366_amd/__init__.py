@@ -33,7 +33,7 @@ __all__ = [
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libimpconv.so")
 
-EXPLICIT_PADDED, REV_F, CONJ_G, REV_OUT, NO_SYMMETRIZE = 1, 2, 4, 8, 16
+EXPLICIT_PADDED, REV_F, CONJ_G, REV_OUT, NO_SYMMETRIZE, HERMITIAN_ADJOINT = 1, 2, 4, 8, 16, 32
 COMPLEX, HERMITIAN, TERNARY = 0, 1, 2
 C64, C128 = 0, 1
 
@@ -198,10 +198,10 @@ def conv1d_complex(f, g, method: str = "implicit", flags: int = 0):
     return _conv1d(COMPLEX, f, g, method, flags)
 
 
-def conv1d_hermitian(f, g, method: str = "implicit"):
+def conv1d_hermitian(f, g, method: str = "implicit", flags: int = 0):
     """Centered Hermitian 1D convolution (Sec. 2.3) of non-negative-wavenumber
     halves; Im f[0] and Im g[0] are ignored."""
-    return _conv1d(HERMITIAN, f, g, method, 0)
+    return _conv1d(HERMITIAN, f, g, method, flags)
 
 
 def conv1d_ternary(f, g, e, method: str = "implicit"):
@@ -223,6 +223,7 @@ def conv1d_ternary(f, g, e, method: str = "implicit"):
 
 
 def _convnd(nd: int, f, g, kind: str, m, flags: int):
+    """nD convolution of (*n), (B, *n) or (B, M, *n) inputs."""
     if f.shape != g.shape or f.dtype != g.dtype:
         raise ValueError("f and g must have the same shape and dtype")
     dev = _dev(f, g)
@@ -479,6 +480,80 @@ def conv1d_complex_ad(f, g):
     """Differentiable conv1d_complex (hand-written adjoint, no autograd tape
     through the kernels)."""
     return _Conv1dComplexFn.apply(f, g)
+
+
+def _per_term(fn, gh, F, G, flags):
+    """Vector-Jacobian products of an M-term dot product h = sum_i f_i * g_i:
+    grad f_i = fn(gh, g_i, flags) for each i (the upstream gradient gh is
+    shared by the terms).  F, G: (B, M, ...); returns (B, M, ...)."""
+    return torch.stack([fn(gh, G[:, i].contiguous(), flags) for i in range(F.shape[1])], 1)
+
+
+class _Conv1dHermitianFn(torch.autograd.Function):
+    # For the centered Hermitian sum (Sec. 2.3) the stored halves define the
+    # full fields through f_{-p} = conj f_p, with Im f_0 ignored.  For a real
+    # loss L and gh = dL/dRe h + i dL/dIm h (k = 0..m-1) the gradient with
+    # respect to the stored half of f is the Hermitian convolution of gh',
+    # the Hermitian extension of gh with gh'_0 = 2 Re gh_0, with g, entry 0
+    # halved and real (the HERMITIAN_ADJOINT flag applies both edits in the
+    # kernel); symmetrically for g.
+    @staticmethod
+    def forward(ctx, f, g):
+        ctx.save_for_backward(f, g)
+        return conv1d_hermitian(f, g)
+
+    @staticmethod
+    def backward(ctx, gh):
+        f, g = ctx.saved_tensors
+        F, G = _as_bmm(f), _as_bmm(g)
+        GH = gh.contiguous().reshape(F.shape[0], F.shape[2])
+        fn = lambda a, b, fl: conv1d_hermitian(a, b, flags=fl)
+        gf = _per_term(fn, GH, F, G, HERMITIAN_ADJOINT).reshape(f.shape) if ctx.needs_input_grad[0] else None
+        gg = _per_term(fn, GH, G, F, HERMITIAN_ADJOINT).reshape(g.shape) if ctx.needs_input_grad[1] else None
+        return gf, gg
+
+
+def conv1d_hermitian_ad(f, g):
+    """Differentiable conv1d_hermitian (hand-written adjoint)."""
+    return _Conv1dHermitianFn.apply(f, g)
+
+
+class _ConvNdComplexFn(torch.autograd.Function):
+    # nD complex sum (Secs. 3.1, 3.4): the vector-Jacobian product is the
+    # correlation grad f = REV_OUT(conv(REV_F(gh), CONJ_G(g))) with every
+    # reversal applied along all axes, evaluated by the same kernels through
+    # their load / store flags.
+    @staticmethod
+    def forward(ctx, nd, f, g):
+        ctx.nd = nd
+        ctx.save_for_backward(f, g)
+        return _convnd(nd, f, g, "complex", None, 0)
+
+    @staticmethod
+    def backward(ctx, gh):
+        f, g = ctx.saved_tensors
+        nd = ctx.nd
+        n = f.shape[-nd:]
+        lead = f.shape[:-nd]
+        B = lead[0] if len(lead) >= 1 else 1
+        M = lead[1] if len(lead) == 2 else 1
+        F, G = f.reshape(B, M, *n), g.reshape(B, M, *n)
+        GH = gh.contiguous().reshape(B, *n)
+        fl = REV_F | CONJ_G | REV_OUT
+        fn = lambda a, b, flags: _convnd(nd, a, b, "complex", None, flags)
+        gf = _per_term(fn, GH, F, G, fl).reshape(f.shape) if ctx.needs_input_grad[1] else None
+        gg = _per_term(fn, GH, G, F, fl).reshape(g.shape) if ctx.needs_input_grad[2] else None
+        return None, gf, gg
+
+
+def conv2d_ad(f, g):
+    """Differentiable complex conv2d (hand-written adjoint)."""
+    return _ConvNdComplexFn.apply(2, f, g)
+
+
+def conv3d_ad(f, g):
+    """Differentiable complex conv3d (hand-written adjoint)."""
+    return _ConvNdComplexFn.apply(3, f, g)
 
 
 class _RaggedFn(torch.autograd.Function):

@@ -76,10 +76,14 @@ impconv_status plan1d(int kind, int dt, int64_t batch, int64_t M, int64_t m, uin
     if (m < 1) return fail(IMPCONV_E_SIZE, "m must be >= 1");
     if (batch < 0) return fail(IMPCONV_E_SIZE, "batch must be >= 0");
     if (M < 1) return fail(IMPCONV_E_SIZE, "M must be >= 1");
-    const uint32_t known = IMPCONV_EXPLICIT_PADDED | IMPCONV_REV_F | IMPCONV_CONJ_G | IMPCONV_REV_OUT;
+    const uint32_t known = IMPCONV_EXPLICIT_PADDED | IMPCONV_REV_F | IMPCONV_CONJ_G | IMPCONV_REV_OUT |
+                           IMPCONV_HERMITIAN_ADJOINT;
     if (flags & ~known) return fail(IMPCONV_E_ARG, "unknown flag bits for a 1D convolution");
-    const bool adj = flags & (IMPCONV_REV_F | IMPCONV_CONJ_G | IMPCONV_REV_OUT);
-    if (adj && kind != IMPCONV_COMPLEX) return fail(IMPCONV_E_ARG, "REV/CONJ flags apply to complex convolutions only");
+    const bool adj = flags & (IMPCONV_REV_F | IMPCONV_CONJ_G | IMPCONV_REV_OUT | IMPCONV_HERMITIAN_ADJOINT);
+    if ((flags & (IMPCONV_REV_F | IMPCONV_CONJ_G | IMPCONV_REV_OUT)) && kind != IMPCONV_COMPLEX)
+        return fail(IMPCONV_E_ARG, "REV/CONJ flags apply to complex convolutions only");
+    if ((flags & IMPCONV_HERMITIAN_ADJOINT) && kind != IMPCONV_HERMITIAN)
+        return fail(IMPCONV_E_ARG, "HERMITIAN_ADJOINT applies to Hermitian convolutions only");
     *p = Plan1D{kind, dt, batch, M, m, flags, 0, bool(flags & IMPCONV_EXPLICIT_PADDED), 0, 0};
     if (p->explicit_ && adj) return fail(IMPCONV_E_ARG, "REV/CONJ flags are not accepted with EXPLICIT_PADDED");
     const size_t cs = csize(dt);
@@ -203,7 +207,7 @@ static impconv_status run1d(int kind, int dtype, int64_t batch, int64_t M, int64
     a.nrows = batch;
     a.m = m;
     a.M = M;
-    a.flags = flags & (kRevF | kConjG | kRevOut);
+    a.flags = flags & (kRevF | kConjG | kRevOut | kHermAdj);
     if (!p.explicit_) {
         a.f = f; a.g = g; a.e = e; a.h = h;
         if (kind == IMPCONV_TERNARY) {

@@ -74,7 +74,8 @@ struct ColArgs {
     int64_t nf;                    // four-step: full 1D length N1 * N
     const int64_t* slab_off;       // four-step, optional: element offset of each s1 slab's 1D data
     const int64_t* slab_m;         // four-step, optional: logical length of each s1 slab
-    uint32_t fsflags;              // four-step: 1 = reverse (input of kFsBwd, output of kFsFwd), 2 = conj input
+    uint32_t fsflags;              // 1 = reverse within m (input of kFsBwd / kPadBwd, output of kFsFwd /
+                                   // kPadFwd), 2 = conjugate the input (kFsBwd / kPadBwd)
     double scale;
     const void* tw;
     const void* tw3;
@@ -147,9 +148,15 @@ k_colpass(ColArgs a)
     };
 
     if constexpr (MODE == kPadBwd) {
+        // adjoint forms: rows read reversed within m and/or conjugated
+        const bool rev = a.fsflags & 1, cj = a.fsflags & 2;
         C<T> x[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) x[e] = ldrow(0, t + e * G, a.m);
+        for (int e = 0; e < E; ++e) {
+            const int row = t + e * G;
+            x[e] = ldrow(0, rev ? a.m - 1 - row : row, a.m);
+            if (cj) x[e] = conj(x[e]);
+        }
         C<T> y[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) y[e] = x[e];
@@ -174,10 +181,11 @@ k_colpass(ColArgs a)
         }
         fft<T, N, E, -1>(y, t, lds, TC, twN);
         const T s = T(a.scale);
+        const bool rev = a.fsflags & 1;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = t + e * G;
-            if (k < a.m) strow(0, k, scale(x[e] + mulc(y[e], tw2N[k]), s));
+            if (k < a.m) strow(0, rev ? a.m - 1 - k : k, scale(x[e] + mulc(y[e], tw2N[k]), s));
         }
     } else if constexpr (MODE == kCenBwd) {
         // U_k and U_{k-N} of this thread's frequencies, with the optional
@@ -585,10 +593,15 @@ k_colpipe(ColArgs a)
         r.ob = s1 * a.out_bs + s2 * a.out_bs2 + tile * TC;
         return r;
     };
-    const uint32_t ioff = uint32_t((col + int64_t(t) * in_ld) * int64_t(sizeof(C<T>)));
-    const uint32_t ooff = uint32_t((col + int64_t(t) * out_ld) * int64_t(sizeof(C<T>)));
-    const uint32_t istep = uint32_t(int64_t(G) * in_ld * int64_t(sizeof(C<T>)));
-    const uint32_t ostep = uint32_t(int64_t(G) * out_ld * int64_t(sizeof(C<T>)));
+    // adjoint forms: the backward pass reads rows reversed within m (row
+    // m-1-j for j < m) and/or conjugated, the forward pass writes them
+    // reversed; a reversed sequence runs at a negative row step
+    const bool rev = a.fsflags & 1, cj = MODE == kPadBwd && (a.fsflags & 2);
+    const int64_t rt = rev ? int64_t(a.m) - 1 - t : t;  // first row of this thread (may be < 0: masked)
+    const uint32_t ioff = uint32_t((col + (MODE == kPadBwd ? rt : int64_t(t)) * in_ld) * int64_t(sizeof(C<T>)));
+    const uint32_t ooff = uint32_t((col + (MODE == kPadFwd ? rt : int64_t(t)) * out_ld) * int64_t(sizeof(C<T>)));
+    const uint32_t istep = uint32_t((MODE == kPadBwd && rev ? -1 : 1) * int64_t(G) * in_ld * int64_t(sizeof(C<T>)));
+    const uint32_t ostep = uint32_t((MODE == kPadFwd && rev ? -1 : 1) * int64_t(G) * out_ld * int64_t(sizeof(C<T>)));
     // rows t + eG of in[q] for this thread's column, zero at rows >= nr.
     // (The thread offset goes through an empty asm so the compiler forms the
     // E offsets at each use instead of hoisting all of them out of the tile
@@ -598,7 +611,10 @@ k_colpipe(ColArgs a)
         uint32_t off = ioff;
         asm volatile("" : "+v"(off));
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = buf_load<T>(rs, t + e * G < nr ? off + uint32_t(e) * istep : kBufOff);
+        for (int e = 0; e < E; ++e) {
+            v[e] = buf_load<T>(rs, t + e * G < nr ? off + uint32_t(e) * istep : kBufOff);
+            if (cj) v[e] = conj(v[e]);
+        }
     };
     // rows t + eG of out[q] where keep(e) holds
     auto store = [&](const C<T> (&v)[E], int q, const Tile& tl, auto keep) {

@@ -193,8 +193,11 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
     if (kind == IMPCONV_TERNARY && M != 1) return fail(IMPCONV_E_SIZE, "ternary convolutions take M = 1");
     if (!m || !n) return fail(IMPCONV_E_ARG, "m or n is NULL");
     if (batch < 0 || M < 1) return fail(IMPCONV_E_SIZE, "batch must be >= 0 and M >= 1");
-    const uint32_t known = IMPCONV_NO_SYMMETRIZE | IMPCONV_EXPLICIT_PADDED;
+    const uint32_t adj = IMPCONV_REV_F | IMPCONV_CONJ_G | IMPCONV_REV_OUT;
+    const uint32_t known = IMPCONV_NO_SYMMETRIZE | IMPCONV_EXPLICIT_PADDED | adj;
     if (flags & ~known) return fail(IMPCONV_E_ARG, "unsupported flag for an nD convolution");
+    if ((flags & adj) && (kind != IMPCONV_COMPLEX || (flags & IMPCONV_EXPLICIT_PADDED)))
+        return fail(IMPCONV_E_ARG, "REV/CONJ flags apply to implicit complex nD convolutions");
     if ((flags & IMPCONV_EXPLICIT_PADDED) && kind == IMPCONV_HERMITIAN)
         return fail(IMPCONV_E_UNSUPPORTED, "the explicitly padded comparator covers 2D complex convolutions");
     std::memset(p, 0, sizeof(*p));
@@ -256,9 +259,11 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
 impconv_status outer_bwd(const DevTables& tb, const PlanND& p, const void* src, void* const* dst,
                          int64_t nslab1, int64_t in_bs1, int64_t n0, int64_t m0, int64_t N0,
                          int64_t cols, int sym, int64_t sym_nz, int sym_offy, int sym_ny,
-                         int64_t mask_nz, int mask_ylo, int mask_yhi, int mask_zhi, hipStream_t s)
+                         int64_t mask_nz, int mask_ylo, int mask_yhi, int mask_zhi, hipStream_t s,
+                         uint32_t fsflags = 0)
 {
     ColArgs a = col_args(tb, p.dt);
+    a.fsflags = fsflags;
     a.in[0] = src;
     for (int r = 0; r < 3; ++r) a.out[r] = dst[r];
     a.nslab = nslab1 * p.M;
@@ -289,9 +294,10 @@ impconv_status outer_bwd(const DevTables& tb, const PlanND& p, const void* src, 
 // Outer-axis forward pass: src[r]: [B][N0][ld=ldin] -> dst [B][n0][cols]
 impconv_status outer_fwd(const DevTables& tb, const PlanND& p, void* const* src, void* dst,
                          int64_t nslab, int64_t in_bs, int64_t in_ld, int64_t n0, int64_t m0,
-                         int64_t N0, int64_t cols, hipStream_t s)
+                         int64_t N0, int64_t cols, hipStream_t s, uint32_t fsflags = 0)
 {
     ColArgs a = col_args(tb, p.dt);
+    a.fsflags = fsflags;
     for (int r = 0; r < 3; ++r) a.in[r] = src[r];
     a.out[0] = dst;
     a.nslab = nslab;
@@ -311,7 +317,7 @@ impconv_status outer_fwd(const DevTables& tb, const PlanND& p, void* const* src,
 
 // Innermost-axis row convolutions over nrows rows, in place in f.
 impconv_status inner_rows(const DevTables& tb, const PlanND& p, void* f, const void* g,
-                          int64_t nrows, hipStream_t s)
+                          int64_t nrows, hipStream_t s, uint32_t rowflags = 0)
 {
     const int nd = p.nd;
     const int64_t m = p.m[nd - 1], n = p.n[nd - 1];
@@ -325,6 +331,7 @@ impconv_status inner_rows(const DevTables& tb, const PlanND& p, void* f, const v
     a.f_row = a.g_row = a.h_row = p.M * n;
     a.f_i = a.g_i = n;
     a.h_pad = n;
+    a.flags = rowflags;
     hipError_t e;
     if (p.kind == IMPCONV_COMPLEX) {
         e = launch_row_complex(p.dt, int(p.Np[nd - 1]), a, s);
@@ -573,6 +580,14 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
         return IMPCONV_OK;
     }
 
+    // adjoint forms (complex): f reversed along every axis (the first pass of
+    // each outer axis and the row loads), g conjugated once (in the x pass),
+    // the output reversed along every axis (row stores and the forward
+    // passes of the outer axes)
+    const uint32_t fs_f = (flags & IMPCONV_REV_F) ? 1u : 0u;
+    const uint32_t fs_g = (flags & IMPCONV_CONJ_G) ? 2u : 0u;
+    const uint32_t fs_o = (flags & IMPCONV_REV_OUT) ? 1u : 0u;
+    const uint32_t rowfl = ((flags & IMPCONV_REV_F) ? kRevF : 0u) | ((flags & IMPCONV_REV_OUT) ? kRevOut : 0u);
     if (nd == 2) {
         const int64_t N0 = p.Np[0], n0 = n[0], n1 = n[1], m0 = m[0], m1 = m[1];
         const size_t arr = size_t(batch) * M * N0 * n1 * cs;
@@ -582,12 +597,12 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
         // Hermitian: columns y < m1 carry data (slot m1 is a zero slot); k_y = 0 is column 0
         const int64_t mask_nz = herm ? n1 : 0;
         if ((st = outer_bwd(tb, p, f, Wf, batch, M * n0 * n1, n0, m0, N0, n1, sym ? 1 : 0, 0, 0, 0,
-                            mask_nz, 0, 1, int(m1), s))) return st;
+                            mask_nz, 0, 1, int(m1), s, fs_f))) return st;
         if ((st = outer_bwd(tb, p, g, Wg, batch, M * n0 * n1, n0, m0, N0, n1, sym ? 1 : 0, 0, 0, 0,
-                            mask_nz, 0, 1, int(m1), s))) return st;
+                            mask_nz, 0, 1, int(m1), s, fs_g))) return st;
         for (int r = 0; r < R; ++r)
-            if ((st = inner_rows(tb, p, Wf[r], Wg[r], batch * N0, s))) return st;
-        if ((st = outer_fwd(tb, p, Wf, h, batch, N0 * M * n1, M * n1, n0, m0, N0, n1, s))) return st;
+            if ((st = inner_rows(tb, p, Wf[r], Wg[r], batch * N0, s, rowfl))) return st;
+        if ((st = outer_fwd(tb, p, Wf, h, batch, N0 * M * n1, M * n1, n0, m0, N0, n1, s, fs_o))) return st;
         return IMPCONV_OK;
     }
     // 3D
@@ -607,9 +622,9 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
     const int ylo = herm ? int(n1 - (2 * m1 - 1)) : 0;
     const int64_t mask_nz = herm ? n2 : 0;
     if ((st = outer_bwd(tb, p, f, Xf, batch, M * n0 * n1 * n2, n0, m0, N0, n1 * n2, sym ? 2 : 0, n2,
-                        int(n1 - m1), int(n1), mask_nz, ylo, int(n1), int(m2), s))) return st;
+                        int(n1 - m1), int(n1), mask_nz, ylo, int(n1), int(m2), s, fs_f))) return st;
     if ((st = outer_bwd(tb, p, g, Xg, batch, M * n0 * n1 * n2, n0, m0, N0, n1 * n2, sym ? 2 : 0, n2,
-                        int(n1 - m1), int(n1), mask_nz, ylo, int(n1), int(m2), s))) return st;
+                        int(n1 - m1), int(n1), mask_nz, ylo, int(n1), int(m2), s, fs_g))) return st;
     void* Q[3];
     for (int rx = 0; rx < R; ++rx) {
         void* Yf[3]; void* Yg[3];
@@ -625,8 +640,9 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
         py.Np[0] = N1;
         const int64_t nplanes = batch * N0;
         // input layout after the x pass: [b][x'][i][y][z] -> slab (plane, i), rows y (ld n2)
-        auto ypass = [&](const void* src, void* const* dst) -> impconv_status {
+        auto ypass = [&](const void* src, void* const* dst, uint32_t fsf) -> impconv_status {
             ColArgs c = col_args(tb, dt);
+            c.fsflags = fsf;
             c.in[0] = src;
             for (int r = 0; r < 3; ++r) c.out[r] = dst[r];
             c.nslab = nplanes * M;
@@ -645,10 +661,10 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
             HIPCHK(launch_col(dt, int(N1), herm ? kCenBwd : kPadBwd, 1, c, s), "y backward pass");
             return IMPCONV_OK;
         };
-        if ((st = ypass(Xf[rx], Yf))) return st;
-        if ((st = ypass(Xg[rx], Yg))) return st;
+        if ((st = ypass(Xf[rx], Yf, fs_f))) return st;
+        if ((st = ypass(Xg[rx], Yg, 0))) return st;
         for (int ry = 0; ry < R; ++ry)
-            if ((st = inner_rows(tb, p, Yf[ry], Yg[ry], nplanes * N1, s))) return st;
+            if ((st = inner_rows(tb, p, Yf[ry], Yg[ry], nplanes * N1, s, rowfl))) return st;
         // y forward: [plane][y'][M][n2] (3 residues) -> Q[rx] [plane][n1][n2]
         Q[rx] = qb + size_t(rx) * qa;
         {
@@ -665,6 +681,7 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
             c.m = int(m1);
             c.off_out = int(n1 - m1);
             c.scale = 1.0 / double((herm ? 3 : 2) * N1);
+            c.fsflags = fs_o;
             HIPCHK(launch_col(dt, int(N1), herm ? kCenFwd : kPadFwd, 1, c, s), "y forward pass");
         }
         (void)a;
@@ -674,7 +691,7 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
     // x forward: Q[rx] [b][x'][n1 n2] -> h [b][n0][n1 n2]
     PlanND px = p;
     px.M = 1;
-    if ((st = outer_fwd(tb, px, Q, h, batch, N0 * n1 * n2, n1 * n2, n0, m0, N0, n1 * n2, s))) return st;
+    if ((st = outer_fwd(tb, px, Q, h, batch, N0 * n1 * n2, n1 * n2, n0, m0, N0, n1 * n2, s, fs_o))) return st;
     return IMPCONV_OK;
 }
 

@@ -18,6 +18,7 @@ enum : uint32_t {
     kRevF = 1u << 1,    // read f reversed within its logical length
     kConjG = 1u << 2,   // read g conjugated
     kRevOut = 1u << 3,  // write h reversed within its logical length
+    kHermAdj = 1u << 5, // Hermitian adjoint: f_0 read as 2 Re f_0, h_0 stored halved (real)
 };
 
 struct RowArgs {
@@ -402,7 +403,8 @@ __device__ __forceinline__ C<T> zeta3N(const C<T>* tw3N, int k)
 // w_{0,r} = Re U_0 and the real w_{NC,r}, Z_{k,r} = c2r_pre(w_{k,r}, w_{NC-k,r}).
 template <typename T, int NC, int E>
 __device__ __forceinline__ void herm_build3(const C<T>* U, int m, int t, C<T>* lds, const C<T>* tw3N,
-                                            const C<T>* twN, C<T> (&z0)[E], C<T> (&z1)[E], C<T> (&z2)[E])
+                                            const C<T>* twN, C<T> (&z0)[E], C<T> (&z1)[E], C<T> (&z2)[E],
+                                            T dc = T(1))
 {
     constexpr int N = 2 * NC, G = NC / E;
     const T h3 = T(0.86602540378443864676), sq3 = T(1.73205080756887729353);
@@ -414,6 +416,8 @@ __device__ __forceinline__ void herm_build3(const C<T>* U, int m, int t, C<T>* l
             lo[e] = ldz(U + z, t + e * G, m);
             hi[e] = ldz(U + z, NC + t + e * G, m);
         }
+        // U_0 scaled by dc (the adjoint's doubled mean; only its real part is read)
+        if (t == 0) lo[0] = scale(lo[0], dc);
     }
     mirror<T, NC, E>(lo, lom, t, lds);  // lom[e] = U_{(NC - k) mod NC}
     mirror<T, NC, E>(hi, him, t, lds);  // him[e] = U_{NC + (NC - k) mod NC}
@@ -475,7 +479,8 @@ k_conv1d_hermitian(RowArgs a)
     const int64_t nM = MD ? a.M : 1;
     for (int64_t i = 0; i < nM; ++i) {
         C<T> x0[E], x1[E], x2[E];
-        herm_build3<T, NC, E>((const C<T>*)a.f + c.of + i * a.f_i, m, t, lds, tw3N, twN, x0, x1, x2);
+        herm_build3<T, NC, E>((const C<T>*)a.f + c.of + i * a.f_i, m, t, lds, tw3N, twN, x0, x1, x2,
+                              (a.flags & kHermAdj) ? T(2) : T(1));
         fft<T, NC, E, +1>(x0, t, lds, 1, twNC);
         fft<T, NC, E, +1>(x1, t, lds, 1, twNC);
         fft<T, NC, E, +1>(x2, t, lds, 1, twNC);
@@ -532,7 +537,8 @@ k_conv1d_hermitian(RowArgs a)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = t + e * G;
-        if (k < m) H[k] = scale(olo[e], s);
+        if (k < m) H[k] = (e == 0 && k == 0 && (a.flags & kHermAdj)) ? C<T>{T(0.5) * s * olo[e].re, T(0)}
+                                                                     : scale(olo[e], s);
         if (k > 0 && N - k < m) H[N - k] = scale(ohi[e], s);
     }
     if (t == 0 && NC < m) H[NC] = scale(ocen, s);

@@ -491,3 +491,44 @@ def test_ternary_nd_symmetric_and_sampled(orc):
     got = orc.convnd_ternary_at(f, g, e, m, pts)
     ref = [h[p[0] + 3, p[1] + 3, p[2]] for p in pts]
     assert rel(got, ref) < TOL
+
+
+# ---------------------------------------------------------------- adjoints (Hermitian 1D, complex nD)
+
+def _fd_grad(L, x, eps=0.5):
+    """Central differences of a real function L that is affine in x: exact up
+    to rounding for any step.  Returns dL/dRe x + i dL/dIm x."""
+    g = np.zeros_like(x)
+    for idx in np.ndindex(*x.shape):
+        e = np.zeros_like(x)
+        e[idx] = eps
+        dr = (L(x + e) - L(x - e)) / (2 * eps)
+        di = (L(x + 1j * e) - L(x - 1j * e)) / (2 * eps)
+        g[idx] = dr + 1j * di
+    return g
+
+
+@pytest.mark.parametrize("m", [1, 2, 5, 12])
+def test_hermitian_adjoint_formula(orc, m):
+    """For L = Re sum conj(w) h(f, g) the gradient with respect to the stored
+    half of f is conv_herm(w', g) with w'_0 = 2 Re w_0, entry 0 halved and
+    real -- the reading the library's HERMITIAN_ADJOINT flag implements."""
+    f, g, w = rnd(m, 131), rnd(m, 132), rnd(m, 133)
+    L = lambda x: float(np.real(np.vdot(w, orc.conv1d_hermitian(x, g))))
+    fd = _fd_grad(L, f)
+    wp = w.copy()
+    wp[0] = 2 * w[0].real
+    an = orc.conv1d_hermitian(wp, g)
+    an[0] = an[0].real / 2
+    assert rel(an, fd) < 1e-12
+    assert fd[0].imag == pytest.approx(0, abs=1e-12)  # Im f_0 is ignored
+
+
+def test_complex_nd_adjoint_formula(orc):
+    """grad f = REV(conv(REV(w), conj g)) with every axis reversed."""
+    m = (4, 5)
+    f, g, w = synth.unit_disk(m, 134), synth.unit_disk(m, 135), synth.unit_disk(m, 136)
+    L = lambda x: float(np.real(np.vdot(w, orc.convnd_complex(x, g))))
+    fd = _fd_grad(L, f)
+    an = orc.convnd_complex(w[::-1, ::-1].copy(), np.conj(g))[::-1, ::-1]
+    assert rel(an, fd) < 1e-12
