@@ -6,7 +6,8 @@ complex64 inputs, a batch of 8 independent pairs per step, one call of
 conv2d.  Each step's result is a batch of 8 dealiased convolutions; value =
 convolutions per second, with inputs resident in HBM before the timed region.
 The explicitly zero-padded comparator (same FFT kernels, padded 4096 x 4096
-arrays materialized in HBM) is timed the same way.
+arrays materialized in HBM) and its pruned form (padding fused into the
+loads, no transform of an all-zero column) are timed the same way.
 
 Other workloads (--workload): c1 (1D complex m=1024 complex128, batch 16384),
 c2 (1D centered Hermitian m=16384, batch 256), c4 (3D centered Hermitian
@@ -150,6 +151,7 @@ def wl_c3(args):
     S = B * mx * my * cs                      # one stored batch of inputs
     run = lambda: ic.conv2d(F, G)
     expl = lambda: ic.conv2d(F, G, method="explicit")
+    pruned = lambda: ic.conv2d(F, G, method="pruned")
     # algorithmic bytes per launch: every pass moves 3 S (Sec. 3.1 schedule)
     kbytes = {"colpass_pad_bwd": 3 * S, "k_conv1d_complex": 3 * S, "colpass_pad_fwd": 3 * S}
     # the row kernel convolves 2 m_x rows per pair (one launch per x residue)
@@ -206,8 +208,8 @@ def wl_c3(args):
     cfg = {"workload": f"2D complex implicit dealiased convolution {mx}x{my}, batch {B} pairs per step, "
                        f"{'complex64' if cdt == torch.complex64 else 'complex128'}",
            "m": [mx, my], "batch": B, "M": 1, "dtype": args.dtype}
-    return dict(run=run, explicit=expl, convs=B, step_bytes=step_bytes, kbytes=kbytes, kflops=kflops, cfg=cfg,
-                cpu=cpu_baseline, out=lambda: run().cpu().numpy())
+    return dict(run=run, explicit=expl, pruned=pruned, convs=B, step_bytes=step_bytes, kbytes=kbytes,
+                kflops=kflops, cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy())
 
 
 def wl_c2(args):
@@ -450,6 +452,7 @@ def wl_t2(args):
     S = B * n[0] * n[1] * cs
     run = lambda: ic.conv2d_ternary(F, G, E, m)
     expl = (lambda: ic.conv2d_ternary(F, G, E, m, method="explicit")) if mm <= 1024 else None
+    pruned = (lambda: ic.conv2d_ternary(F, G, E, m, method="pruned")) if mm <= 1024 else None
     P0 = 2 * (1 << int(np.ceil(np.log2(mm))))
     # per launch: x backward reads one input (S) and writes two residues (2S);
     # rows read three residue arrays and write one; x forward reads 2S, writes S
@@ -507,8 +510,8 @@ def wl_t2(args):
                        f"{n[0]}x{n[1]}, batch {B} triples per step, "
                        f"{'complex64' if cdt == torch.complex64 else 'complex128'}",
            "m": list(m), "n": list(n), "batch": B, "dtype": args.dtype}
-    return dict(run=run, explicit=expl, convs=B, step_bytes=step_bytes, kbytes=kbytes, kflops=kflops, cfg=cfg,
-                cpu=cpu_baseline, out=lambda: run().cpu().numpy())
+    return dict(run=run, explicit=expl, pruned=pruned, convs=B, step_bytes=step_bytes, kbytes=kbytes,
+                kflops=kflops, cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy())
 
 
 WORKLOADS = {"c1": wl_c1, "c2": wl_c2, "c3": wl_c3, "c4": wl_c4, "c5": wl_c5, "t2": wl_t2}
@@ -618,6 +621,11 @@ def main():
         out["explicit_padded"] = {"ms_per_step": round(ms_e, 5), "value": round(W["convs"] * 1000.0 / ms_e, 2),
                                   "unit": "convs/s"}
         out["speedup_vs_explicit"] = round(ms_e / ms_clean, 3)
+    if W.get("pruned") is not None and not args.no_explicit:
+        ms_p = timed(W["pruned"], max(3, args.steps // 2), 1)
+        out["explicit_pruned"] = {"ms_per_step": round(ms_p, 5), "value": round(W["convs"] * 1000.0 / ms_p, 2),
+                                  "unit": "convs/s"}
+        out["speedup_vs_pruned"] = round(ms_p / ms_clean, 3)
 
     if args.profile_copy:
         n = args.profile_copy * (1 << 20) // 4

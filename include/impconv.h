@@ -74,6 +74,7 @@ typedef enum impconv_kind {
 #define IMPCONV_REV_OUT (1u << 3)         /* complex 1D: write h reversed */
 #define IMPCONV_NO_SYMMETRIZE (1u << 4)   /* Hermitian nD: trust the k_last = 0 plane (see conv2d) */
 #define IMPCONV_HERMITIAN_ADJOINT (1u << 5) /* Hermitian 1D: f_0 read as 2 Re f_0, h_0 stored halved */
+#define IMPCONV_EXPLICIT_PRUNED (1u << 6) /* with EXPLICIT_PADDED (2D): skip all-zero transforms, fuse padding */
 
 /* Version as 10000*major + 100*minor + patch. */
 int impconv_version(void);
@@ -173,7 +174,11 @@ size_t impconv_timing_report(char* buf, size_t cap);
  * m[d] (the adjoint: dL/df = REV_OUT(conv(REV_F(dL/dh), CONJ_G(g)))).
  * IMPCONV_EXPLICIT_PADDED (2D complex only): the conventional comparator --
  * inputs copied into zero-padded 2N0 x 2N1 work arrays, full-size FFTs along
- * both axes, product, inverse, crop (m[d] <= 2048).
+ * both axes, product, inverse, crop (m[d] <= 2048).  With
+ * IMPCONV_EXPLICIT_PRUNED as well: the pruned comparator -- the same padded
+ * transform sizes with the zero padding fused into the loads, no transform
+ * of an all-zero column and the crop fused into the last store (work
+ * 2 * batch * M * 2N0 * m1 complex values).
  * Outer axes support m[d] <= 4096 in this build; the innermost axis
  * m <= 8192 (complex) or m <= 16384 (Hermitian).
  * ---------------------------------------------------------------------- */
@@ -207,7 +212,8 @@ impconv_status impconv_conv3d(int kind, int dtype, int64_t batch, int64_t M, con
  * full-size complex FFTs along x, real cyclic triple products of length
  * 4 N1' along y, inverse x FFT, crop; it reads the k_y = 0 line as its
  * Hermitian projection (m0 <= 1024, m1 <= 4096; workspace
- * 3 * batch * 4 N0' * (2 N1' + 1) complex values). */
+ * 3 * batch * 4 N0' * (2 N1' + 1) complex values).  IMPCONV_EXPLICIT_PRUNED
+ * as well: the all-zero columns k_y >= m1 are not transformed. */
 impconv_status impconv_conv2d_ternary(int dtype, int64_t batch, const int64_t* m, const int64_t* n,
                                       const void* f, const void* g, const void* e, void* h,
                                       void* work, size_t work_bytes, uint32_t flags, void* stream);

@@ -33,7 +33,7 @@ __all__ = [
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libimpconv.so")
 
-EXPLICIT_PADDED, REV_F, CONJ_G, REV_OUT, NO_SYMMETRIZE, HERMITIAN_ADJOINT = 1, 2, 4, 8, 16, 32
+EXPLICIT_PADDED, REV_F, CONJ_G, REV_OUT, NO_SYMMETRIZE, HERMITIAN_ADJOINT, EXPLICIT_PRUNED = 1, 2, 4, 8, 16, 32, 64
 COMPLEX, HERMITIAN, TERNARY = 0, 1, 2
 C64, C128 = 0, 1
 
@@ -261,19 +261,18 @@ def _convnd(nd: int, f, g, kind: str, m, flags: int):
 def conv2d(f, g, kind: str = "complex", m=None, symmetrize: bool = True, method: str = "implicit"):
     """2D convolution (Secs. 3.1 / 3.2); inputs (n0, n1), (B, n0, n1) or
     (B, M, n0, n1); Hermitian needs m = (m0, m1).  method="explicit" runs the
-    explicitly zero-padded comparator (complex only)."""
+    explicitly zero-padded comparator, "pruned" its pruned form (complex
+    only)."""
     flags = 0 if symmetrize else NO_SYMMETRIZE
-    if method == "explicit":
-        flags |= EXPLICIT_PADDED
-    elif method != "implicit":
-        raise ValueError("method must be 'implicit' or 'explicit'")
+    flags |= {"implicit": 0, "explicit": EXPLICIT_PADDED, "pruned": EXPLICIT_PADDED | EXPLICIT_PRUNED}[method]
     return _convnd(2, f, g, kind, m, flags)
 
 
 def conv2d_ternary(f, g, e, m, symmetrize: bool = True, method: str = "implicit"):
     """2D centered Hermitian ternary convolution (Sec. 4, tconv2) of inputs
     (n0, n1) or (B, n0, n1) in the 2D Hermitian storage; m = (m0, m1).
-    method="explicit" runs the explicitly zero-padded comparator."""
+    method="explicit" runs the explicitly zero-padded comparator, "pruned"
+    its form without transforms of all-zero columns."""
     if not (f.shape == g.shape == e.shape) or not (f.dtype == g.dtype == e.dtype):
         raise ValueError("f, g, e must share shape and dtype")
     dev = _dev(f, g, e)
@@ -281,7 +280,8 @@ def conv2d_ternary(f, g, e, m, symmetrize: bool = True, method: str = "implicit"
     B = 1 if f.dim() == 2 else f.shape[0]
     m = tuple(int(x) for x in m)
     dt = _dtype_code(f)
-    flags = (0 if symmetrize else NO_SYMMETRIZE) | {"implicit": 0, "explicit": EXPLICIT_PADDED}[method]
+    flags = (0 if symmetrize else NO_SYMMETRIZE) | {"implicit": 0, "explicit": EXPLICIT_PADDED,
+                                                    "pruned": EXPLICIT_PADDED | EXPLICIT_PRUNED}[method]
     marr = (ctypes.c_int64 * 2)(*m)
     narr = (ctypes.c_int64 * 2)(*n)
     out = _sz()

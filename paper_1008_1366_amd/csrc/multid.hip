@@ -194,8 +194,10 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
     if (!m || !n) return fail(IMPCONV_E_ARG, "m or n is NULL");
     if (batch < 0 || M < 1) return fail(IMPCONV_E_SIZE, "batch must be >= 0 and M >= 1");
     const uint32_t adj = IMPCONV_REV_F | IMPCONV_CONJ_G | IMPCONV_REV_OUT;
-    const uint32_t known = IMPCONV_NO_SYMMETRIZE | IMPCONV_EXPLICIT_PADDED | adj;
+    const uint32_t known = IMPCONV_NO_SYMMETRIZE | IMPCONV_EXPLICIT_PADDED | IMPCONV_EXPLICIT_PRUNED | adj;
     if (flags & ~known) return fail(IMPCONV_E_ARG, "unsupported flag for an nD convolution");
+    if ((flags & IMPCONV_EXPLICIT_PRUNED) && !(flags & IMPCONV_EXPLICIT_PADDED))
+        return fail(IMPCONV_E_ARG, "EXPLICIT_PRUNED qualifies EXPLICIT_PADDED");
     if ((flags & adj) && (kind != IMPCONV_COMPLEX || (flags & IMPCONV_EXPLICIT_PADDED)))
         return fail(IMPCONV_E_ARG, "REV/CONJ flags apply to implicit complex nD convolutions");
     if ((flags & IMPCONV_EXPLICIT_PADDED) && kind == IMPCONV_HERMITIAN)
@@ -227,10 +229,10 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
     const size_t cs = csize(dt);
     const int R = kind == IMPCONV_COMPLEX ? 2 : 3;
     if ((flags & IMPCONV_EXPLICIT_PADDED) && kind == IMPCONV_COMPLEX) {
-        // padded f and g, [b][2N0][M][2N1]
+        // padded f and g, [b][2N0][M][2N1] (pruned: only the m1 data columns, [b][2N0][M][m1])
         const int64_t P0 = 2 * p->Np[0], P1 = 2 * p->Np[1];
         if (P0 > kColMax || P1 > kRowMax) return fail(IMPCONV_E_UNSUPPORTED, "explicit 2D comparator supports m <= 2048 per axis");
-        p->work = size_t(2) * batch * M * P0 * P1 * cs;
+        p->work = size_t(2) * batch * M * P0 * ((flags & IMPCONV_EXPLICIT_PRUNED) ? n[1] : P1) * cs;
         return IMPCONV_OK;
     }
     if (kind == IMPCONV_TERNARY && (flags & IMPCONV_EXPLICIT_PADDED)) {
@@ -384,6 +386,7 @@ impconv_status run2d_ternary(int dt, int64_t batch, const int64_t* m, const int6
         // by the c2r transform, i.e. as its Hermitian projection (the same as
         // the implicit path for symmetric input).
         const int64_t P0 = 4 * p.Np[0], NC = 2 * p.Np[1], L = NC + 1;
+        const bool pruned = flags & IMPCONV_EXPLICIT_PRUNED;
         const size_t arr = size_t(batch) * P0 * L * cs;
         char* w = static_cast<char*>(work);
         void* W[3] = {w, w + arr, w + 2 * arr};
@@ -403,7 +406,7 @@ impconv_status run2d_ternary(int dt, int64_t batch, const int64_t* m, const int6
             a.in[0] = a.out[0] = W[q];
             a.nslab = batch;
             a.in_bs = a.out_bs = P0 * L;
-            a.ncols = L;
+            a.ncols = pruned ? m1 : L;  // pruned: the all-zero columns k_y >= m1 stay zero
             a.in_ld = a.out_ld = L;
             a.n_in = a.n_out = int(P0);
             HIPCHK(launch_col(dt, int(P0), kFft, 1, a, s), "explicit x FFT");
@@ -411,7 +414,7 @@ impconv_status run2d_ternary(int dt, int64_t batch, const int64_t* m, const int6
         RowArgs ra = row_args(tb, dt);
         ra.f = W[0]; ra.g = W[1]; ra.e = W[2]; ra.h = W[0];
         ra.nrows = batch * P0;
-        ra.m = L;
+        ra.m = pruned ? m1 : L;
         ra.m_out = m1;
         ra.M = 1;
         ra.f_row = ra.g_row = ra.e_row = ra.h_row = L;
@@ -529,6 +532,58 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
     const bool sym = herm && !(flags & IMPCONV_NO_SYMMETRIZE);
     char* w = static_cast<char*>(work);
 
+    if ((flags & IMPCONV_EXPLICIT_PADDED) && (flags & IMPCONV_EXPLICIT_PRUNED)) {
+        // Pruned conventional method: the padded transforms with the zero
+        // padding fused into the loads and no transform of an all-zero
+        // column -- x FFTs of size 2N0 read the m0 stored rows of each of the
+        // m1 data columns straight from f and g, the rows of size 2N1 read
+        // their m1 data entries (zero beyond) and keep the m1 cropped outputs,
+        // and the inverse x FFT writes the m0 cropped rows straight to h.
+        const int64_t P0 = 2 * p.Np[0], P1 = 2 * p.Np[1], m0 = m[0], m1 = m[1];
+        const size_t arr = size_t(batch) * M * P0 * m1 * cs;
+        void* Fp = w;
+        void* Gp = w + arr;
+        for (int q = 0; q < 2; ++q) {
+            ColArgs a = col_args(tb, dt);
+            a.in[0] = q ? g : f;
+            a.out[0] = q ? Gp : Fp;
+            a.nslab = batch * M;
+            a.nsub = M;
+            a.in_bs = M * m0 * m1;
+            a.in_bs2 = m0 * m1;
+            a.in_ld = m1;
+            a.out_bs = P0 * M * m1;
+            a.out_bs2 = m1;
+            a.out_ld = M * m1;
+            a.ncols = m1;
+            a.n_in = int(m0);
+            a.n_out = int(P0);
+            HIPCHK(launch_col(dt, int(P0), kFft, 1, a, s), "pruned column FFT");
+        }
+        RowArgs ra = row_args(tb, dt);
+        ra.f = Fp; ra.g = Gp; ra.h = Fp;
+        ra.nrows = batch * P0;
+        ra.m = m1;
+        ra.m_out = m1;
+        ra.M = M;
+        ra.f_row = ra.g_row = ra.h_row = M * m1;
+        ra.f_i = ra.g_i = m1;
+        ra.scale = 1.0 / double(P0 * P1);
+        HIPCHK(launch_row_cyclic(dt, int(P1), ra, s), "pruned row convolution");
+        ColArgs a = col_args(tb, dt);
+        a.in[0] = Fp;
+        a.out[0] = h;
+        a.nslab = batch;
+        a.in_bs = P0 * M * m1;
+        a.in_ld = M * m1;
+        a.out_bs = m0 * m1;
+        a.out_ld = m1;
+        a.ncols = m1;
+        a.n_in = int(P0);
+        a.n_out = int(m0);
+        HIPCHK(launch_col(dt, int(P0), kFft, -1, a, s), "pruned inverse column FFT");
+        return IMPCONV_OK;
+    }
     if (flags & IMPCONV_EXPLICIT_PADDED) {
         // Conventional method (Sec. 1): copy the inputs into zero-padded
         // 2N0 x 2N1 arrays, transform both axes at the padded size, multiply,

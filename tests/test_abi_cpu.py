@@ -138,6 +138,7 @@ def test_plan_create_validation(L):
     assert create(kind=1, ndim=2, m=(4, 4, 0), n=(9, 5, 0)) == 2  # centered axis needs 2m-1 or 2m
     assert create(kind=0, ndim=2, m=(4, 4, 0), n=(4, 5, 0)) == 2  # complex storage n == m
     assert create(flags=1 << 7) == 1
+    assert create(kind=0, ndim=2, m=(4, 4, 0), n=(4, 4, 0), flags=1 << 6) == 1  # PRUNED needs EXPLICIT
     n = ctypes.c_size_t()
     assert L.impconv_workspace_bytes(None, ctypes.byref(n)) == 1
     assert L.impconv_execute(None, None, None, None, None, None, 0, None) == 1

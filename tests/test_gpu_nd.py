@@ -172,3 +172,15 @@ def test_explicit_complex_2d_matches_oracle(dt, shape):
     h = ic.conv2d(to_dev(f, dt), to_dev(g, dt), method="explicit").cpu().numpy()
     for b in range(B):
         assert rel(h[b], oracle.convnd_complex_M(rounded(f[b], dt), rounded(g[b], dt))) < TOL[dt]
+
+
+@pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("shape", [(1, 1), (5, 7), (33, 64), (100, 3)])
+def test_pruned_complex_2d_matches_oracle(dt, shape):
+    ic = need_gpu()
+    B, M = 2, 2
+    f = synth.unit_disk((B, M, *shape), 83)
+    g = synth.unit_disk((B, M, *shape), 84)
+    h = ic.conv2d(to_dev(f, dt), to_dev(g, dt), method="pruned").cpu().numpy()
+    for b in range(B):
+        assert rel(h[b], oracle.convnd_complex_M(rounded(f[b], dt), rounded(g[b], dt))) < TOL[dt]

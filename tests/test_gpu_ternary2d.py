@@ -128,10 +128,12 @@ def test_tconv2_explicit_comparator(dt, m, n):
     e = np.stack([symmetric_storage(m, n, 345 + b) for b in range(B)])
     args = [to_dev(x, dt) for x in (f, g, e)]
     he = ic.conv2d_ternary(*args, m, method="explicit").cpu().numpy()
+    hp = ic.conv2d_ternary(*args, m, method="pruned").cpu().numpy()
     hi = ic.conv2d_ternary(*args, m).cpu().numpy()
     for b in range(B):
         ref = oracle.convnd_ternary(rounded(f[b], dt), rounded(g[b], dt), rounded(e[b], dt), m)
         assert rel(he[b], ref) < TOL[dt], b
+        assert rel(hp[b], ref) < TOL[dt], b
         assert rel(hi[b], ref) < TOL[dt], b
     if n[0] == 2 * m[0]:
         assert np.all(he[:, 0] == 0)
