@@ -11,7 +11,9 @@ loads, no transform of an all-zero column) are timed the same way.
 
 Other workloads (--workload): c1 (1D complex m=1024 complex128, batch 16384),
 c2 (1D centered Hermitian m=16384, batch 256), c4 (3D centered Hermitian
-512x512x257, M=3), c5 (4096 uneven 1D complex pairs, forward + backward).
+512x512x257, M=3), c5 (4096 uneven 1D complex pairs, forward + backward),
+t2 (2D centered Hermitian ternary, 1024^2 modes, batch 8), e2 (2D Euler
+nonlinearity: Hermitian 2D with M = 2, 2048^2 modes).
 
 Output: one JSON line (rank 0) with the metric, per-step time (mean and the
 one-sided deviations below and above it), per-kernel algorithmic bytes and
@@ -514,7 +516,71 @@ def wl_t2(args):
                 kflops=kflops, cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy())
 
 
-WORKLOADS = {"c1": wl_c1, "c2": wl_c2, "c3": wl_c3, "c4": wl_c4, "c5": wl_c5, "t2": wl_t2}
+def wl_e2(args):
+    """Nonlinear term of the 2D incompressible Euler equations in vorticity
+    form (Sec. 3.3): one centered Hermitian 2D convolution with M = 2,
+    f = (i k_x w, i k_y w), g = (i k_y w / k^2, -i k_x w / k^2), for a
+    vorticity spectrum w ~ |k|^-1 (random phase, Hermitian k_y = 0 line) on
+    m = (M, M) modes, storage (2M, M + 1)."""
+    import torch
+    import paper_1008_1366_amd as ic
+    import synth
+    cdt = torch.complex64 if args.dtype == "c64" else torch.complex128
+    dt_np = np.complex64 if cdt == torch.complex64 else np.complex128
+    mm = args.e2_m
+    m, n = (mm, mm), (2 * mm, mm + 1)
+    w = synth.power_spectrum_centered(m, n, 1.0, 700)
+    off = n[0] - mm
+    ks = np.arange(1, mm)
+    w[off - ks, 0] = np.conj(w[off + ks, 0])
+    kx = (np.arange(n[0]) - off)[:, None].astype(np.float64)
+    ky = np.arange(n[1])[None, :].astype(np.float64)
+    k2 = kx * kx + ky * ky
+    inv = np.where(k2 > 0, 1.0 / np.where(k2 > 0, k2, 1.0), 0.0)
+    f = np.stack([1j * kx * w, 1j * ky * w])[None]
+    g = np.stack([1j * ky * w * inv, -1j * kx * w * inv])[None]
+    del kx, ky, k2, inv
+    F = torch.from_numpy(f).to("cuda", cdt)
+    G = torch.from_numpy(g).to("cuda", cdt)
+    cs = 8 if cdt == torch.complex64 else 16
+    S = n[0] * n[1] * cs
+    run = lambda: ic.conv2d(F, G, kind="hermitian", m=m)
+    N0 = 1 << int(np.ceil(np.log2(mm)))
+    NC = max(1 << int(np.ceil(np.log2(mm))), 2) // 2
+    # per step (S = one stored array): x backward reads 2S (M = 2) and writes
+    # three half-size residues per term (3S) for f and for g; each of the
+    # three row launches reads 2S and writes S/2; the x forward reads 1.5S and
+    # writes S
+    kbytes_step = {"colpass_cen_bwd": int(10 * S), "k_conv1d_hermitian": int(7.5 * S),
+                   "colpass_cen_fwd": int(2.5 * S)}
+    kflops_step = {"k_conv1d_hermitian": 3 * N0 * flops_row_hermitian(NC, 2)}
+
+    def cpu_baseline(h_gpu):
+        import oracle
+        rng = synth.rng(701)
+        npts = max(8, args.cpu_points // 64)
+        pts = np.stack([rng.integers(-mm + 1, mm, npts), rng.integers(0, mm, npts)], 1)
+        pts[:4] = [[0, 0], [mm - 1, mm - 1], [-mm + 1, 0], [1, 1]]
+        fr = np.asarray(f[0].astype(dt_np), np.complex128)
+        gr = np.asarray(g[0].astype(dt_np), np.complex128)
+        t0 = time.perf_counter()
+        ref = oracle.convnd_hermitian_at(fr, gr, m, pts)
+        dt = time.perf_counter() - t0
+        got = h_gpu[0][pts[:, 0] + off, pts[:, 1]]
+        err = {"sampled_points": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)), "points": int(npts)}
+        nout = (2 * mm - 1) * mm
+        return {"value": 1.0 / (dt / npts * nout), "unit": "convs/s", "cores": oracle.num_threads(),
+                "kind": "oracle", "sample": f"{npts} output points (direct FP64 M = 2 sums, {dt:.2f} s), "
+                                            f"extrapolated to the {nout} outputs"}, err
+
+    cfg = {"workload": f"2D Euler nonlinearity: centered Hermitian 2D convolution, M = 2, {mm}x{mm} modes, "
+                       f"storage {n[0]}x{n[1]}, {'complex64' if cdt == torch.complex64 else 'complex128'}",
+           "m": list(m), "n": list(n), "M": 2, "dtype": args.dtype}
+    return dict(run=run, explicit=None, convs=1, step_bytes=int(20 * S), kbytes_step=kbytes_step,
+                kflops_step=kflops_step, cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy())
+
+
+WORKLOADS = {"c1": wl_c1, "c2": wl_c2, "c3": wl_c3, "c4": wl_c4, "c5": wl_c5, "t2": wl_t2, "e2": wl_e2}
 
 
 def main():
@@ -529,6 +595,7 @@ def main():
     ap.add_argument("--no-explicit", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="c5: keep the default four-step splits")
     ap.add_argument("--t2-m", type=int, default=1024, help="t2: modes per axis")
+    ap.add_argument("--e2-m", type=int, default=2048, help="e2: modes per axis")
     # oracle sample sizes (about 10 s of host work each)
     ap.add_argument("--cpu-points", type=int, default=65536, help="c3: sampled output points over the batch")
     ap.add_argument("--cpu-rows", type=int, default=0, help="c1/c2: convolutions (0: workload default)")
