@@ -82,21 +82,42 @@ struct ColArgs {
     int ncu;                       // compute units of the device (persistent grids)
 };
 
+// Elements per thread of a column pass.  The centered passes keep three
+// arrays of E values live (U_k and U_{k-N} plus one residue; or two output
+// accumulators plus one residue).  The forward (accumulating) pass takes half
+// the FFT elements per thread at every length, which lifts it from one or two
+// waves per SIMD to three or four; the backward pass does so from N = 2048 on,
+// where the full count no longer fits the 128 registers its block allows.
+// Measured on 256-point columns, halving the backward pass costs 4%.
+#ifndef IMPCONV_CEN_BWD_HALF_E_MINN
+#define IMPCONV_CEN_BWD_HALF_E_MINN 2048
+#endif
+template <typename T, int MODE = -1>
+__host__ __device__ constexpr int col_E(int N)
+{
+    const int e = fft_E<T>(N);
+    const bool half = MODE == 3 || (MODE == 2 && N >= IMPCONV_CEN_BWD_HALF_E_MINN);  // kCenFwd, kCenBwd
+    return (half && e >= 4) ? e / 2 : e;
+}
+
 // Columns per tile: a 64-byte row segment (8 complex64 / 4 complex128), up to
 // 128 bytes for short transforms, limited by 1024 threads and ~140 KB of LDS.
 #ifndef IMPCONV_COL_SEG_BYTES
 #define IMPCONV_COL_SEG_BYTES 64
 #endif
-template <typename T>
+template <typename T, int MODE = -1>
 __host__ __device__ constexpr int col_TC(int N)
 {
     int tc = (N <= 512 ? 128 : IMPCONV_COL_SEG_BYTES) / int(sizeof(C<T>));
-    const int G = N / fft_E<T>(N);
-    while (tc > 1 && (tc * G > 1024 || (N > fft_E<T>(N) && tc * lpad_size(N) * int(sizeof(C<T>)) > 143360)))
+    const int G = N / col_E<T, MODE>(N);
+    while (tc > 1 && (tc * G > 1024 || (N > col_E<T, MODE>(N) && tc * lpad_size(N) * int(sizeof(C<T>)) > 143360)))
         tc /= 2;
     return tc;
 }
-template <typename T> __host__ __device__ constexpr int col_block(int N) { return col_TC<T>(N) * (N / fft_E<T>(N)); }
+template <typename T, int MODE = -1> __host__ __device__ constexpr int col_block(int N)
+{
+    return col_TC<T, MODE>(N) * (N / col_E<T, MODE>(N));
+}
 
 // blockIdx -> logical tile so that consecutive tiles (which share cache lines
 // and run concurrently) are issued to the same XCD: the hardware deals
@@ -110,10 +131,10 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t nblocks)
 }
 
 template <typename T, int N, int MODE, int DIR>
-__global__ void __launch_bounds__(col_block<T>(N))
+__global__ void __launch_bounds__((col_block<T, MODE>(N)))
 k_colpass(ColArgs a)
 {
-    constexpr int E = fft_E<T>(N), G = N / E, TC = col_TC<T>(N);
+    constexpr int E = col_E<T, MODE>(N), G = N / E, TC = col_TC<T, MODE>(N);
     constexpr int LDSN = N > E ? lpad_size(N) * TC : 1;
     __shared__ C<T> sh[LDSN];
     static_assert(sizeof(sh) <= 160 * 1024, "LDS footprint exceeds 160 KB");

@@ -8,10 +8,10 @@ namespace impconv {
 template <typename T, int N, int MODE>
 static hipError_t go(const ColArgs& a, hipStream_t s)
 {
-    const int64_t nb = a.nslab * ((a.ncols + col_TC<T>(N) - 1) / col_TC<T>(N));
+    const int64_t nb = a.nslab * ((a.ncols + col_TC<T, MODE>(N) - 1) / col_TC<T, MODE>(N));
     if (nb == 0) return hipSuccess;
     timing_begin(s);
-    hipLaunchKernelGGL((k_colpass<T, N, MODE, 1>), dim3(((nb + 7) / 8) * 8), dim3(col_block<T>(N)), 0, s, a);
+    hipLaunchKernelGGL((k_colpass<T, N, MODE, 1>), dim3(((nb + 7) / 8) * 8), dim3(col_block<T, MODE>(N)), 0, s, a);
     timing_end(MODE_NAME(MODE), s);
     return hipGetLastError();
 }
