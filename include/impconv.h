@@ -73,7 +73,7 @@ typedef enum impconv_kind {
 #define IMPCONV_CONJ_G (1u << 2)          /* complex 1D: read g conjugated */
 #define IMPCONV_REV_OUT (1u << 3)         /* complex 1D: write h reversed */
 #define IMPCONV_NO_SYMMETRIZE (1u << 4)   /* Hermitian nD: trust the k_last = 0 plane (see conv2d) */
-#define IMPCONV_HERMITIAN_ADJOINT (1u << 5) /* Hermitian 1D: f_0 read as 2 Re f_0, h_0 stored halved */
+#define IMPCONV_HERMITIAN_ADJOINT (1u << 5) /* Hermitian 1D/nD: vector-Jacobian product edits (see below) */
 #define IMPCONV_EXPLICIT_PRUNED (1u << 6) /* with EXPLICIT_PADDED (2D): skip all-zero transforms, fuse padding */
 
 /* Version as 10000*major + 100*minor + patch. */
@@ -172,6 +172,15 @@ size_t impconv_timing_report(char* buf, size_t cap);
  * IMPCONV_COMPLEX also accepts IMPCONV_REV_F / IMPCONV_CONJ_G /
  * IMPCONV_REV_OUT as in 1D, each reversal applying to every axis within
  * m[d] (the adjoint: dL/df = REV_OUT(conv(REV_F(dL/dh), CONJ_G(g)))).
+ * IMPCONV_HERMITIAN accepts IMPCONV_HERMITIAN_ADJOINT (not with
+ * IMPCONV_NO_SYMMETRIZE or IMPCONV_EXPLICIT_PADDED), the vector-Jacobian
+ * product: for a real loss L of h and gh = dL/dRe h + i dL/dIm h, the
+ * gradient with respect to the stored half of f is the Hermitian
+ * convolution of Gamma with g, where Gamma = gh off the k_last = 0
+ * hyperplane and gh_k + conj gh_{-k} on it (both halves), followed on that
+ * hyperplane by zero for the entries the symmetrization overwrites and the
+ * origin halved and real.  The flag makes the first outer pass load f as
+ * Gamma and the last outer pass apply the edits; pass gh as f.
  * IMPCONV_EXPLICIT_PADDED (2D complex only): the conventional comparator --
  * inputs copied into zero-padded 2N0 x 2N1 work arrays, full-size FFTs along
  * both axes, product, inverse, crop (m[d] <= 2048).  With

@@ -556,6 +556,46 @@ def conv3d_ad(f, g):
     return _ConvNdComplexFn.apply(3, f, g)
 
 
+class _ConvNdHermitianFn(torch.autograd.Function):
+    # nD centered Hermitian sum (Secs. 3.2, 3.4) with the k_last = 0
+    # hyperplane symmetrized on load.  For a real loss and gh = dL/dRe h +
+    # i dL/dIm h the gradient with respect to the stored half of f is the
+    # Hermitian convolution of Gamma with g, Gamma = gh with gh_k + conj gh_{-k}
+    # on the hyperplane, the entries the symmetrization overwrites zero and
+    # the origin halved and real (the HERMITIAN_ADJOINT flag applies the
+    # load and store edits in the first and last outer passes).
+    @staticmethod
+    def forward(ctx, nd, m, f, g):
+        ctx.nd, ctx.m = nd, m
+        ctx.save_for_backward(f, g)
+        return _convnd(nd, f, g, "hermitian", m, 0)
+
+    @staticmethod
+    def backward(ctx, gh):
+        f, g = ctx.saved_tensors
+        nd, m = ctx.nd, ctx.m
+        n = f.shape[-nd:]
+        lead = f.shape[:-nd]
+        B = lead[0] if len(lead) >= 1 else 1
+        M = lead[1] if len(lead) == 2 else 1
+        F, G = f.reshape(B, M, *n), g.reshape(B, M, *n)
+        GH = gh.contiguous().reshape(B, *n)
+        fn = lambda a, b, flags: _convnd(nd, a, b, "hermitian", m, flags)
+        gf = _per_term(fn, GH, F, G, HERMITIAN_ADJOINT).reshape(f.shape) if ctx.needs_input_grad[2] else None
+        gg = _per_term(fn, GH, G, F, HERMITIAN_ADJOINT).reshape(g.shape) if ctx.needs_input_grad[3] else None
+        return None, None, gf, gg
+
+
+def conv2d_hermitian_ad(f, g, m):
+    """Differentiable centered Hermitian conv2d (hand-written adjoint)."""
+    return _ConvNdHermitianFn.apply(2, tuple(int(x) for x in m), f, g)
+
+
+def conv3d_hermitian_ad(f, g, m):
+    """Differentiable centered Hermitian conv3d (hand-written adjoint)."""
+    return _ConvNdHermitianFn.apply(3, tuple(int(x) for x in m), f, g)
+
+
 class _RaggedFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, plan, f, g):

@@ -75,7 +75,9 @@ struct ColArgs {
     const int64_t* slab_off;       // four-step, optional: element offset of each s1 slab's 1D data
     const int64_t* slab_m;         // four-step, optional: logical length of each s1 slab
     uint32_t fsflags;              // 1 = reverse within m (input of kFsBwd / kPadBwd, output of kFsFwd /
-                                   // kPadFwd), 2 = conjugate the input (kFsBwd / kPadBwd)
+                                   // kPadFwd), 2 = conjugate the input (kFsBwd / kPadBwd), 4 = Hermitian
+                                   // adjoint on the k_last = 0 hyperplane (kCenBwd: load U_k + conj U_{-k};
+                                   // kCenFwd: zero the overwritten half, DC halved and real; needs sym)
     double scale;
     const void* tw;
     const void* tw3;
@@ -225,8 +227,16 @@ k_colpass(ColArgs a)
             mcol = (iym >= 0 && iym < a.sym_ny) ? int64_t(iym) * a.sym_nz : cc;
         }
         const C<T>* base = (const C<T>*)a.in[0] + s1 * a.in_bs + s2 * a.in_bs2;
+        const bool adj = a.fsflags & 4;
         auto ldk = [&](int k) -> C<T> {  // wavenumber k of this column (|k| < m)
             const bool in = cact && k > -a.m && k < a.m;
+            if (adj) {
+                // adjoint: U_k + conj U_{-k} on the hyperplane (both halves)
+                const int kk = in ? k : 0;
+                C<T> v = base[cc + int64_t(kk + a.off_in) * a.in_ld];
+                if (plane) v = v + conj(base[mcol + int64_t(-kk + a.off_in) * a.in_ld]);
+                return in ? v : zero<T>();
+            }
             // mirror: k < 0, or k = 0 with ky < 0 (3D); DC real
             const bool mir = plane && (k < 0 || (k == 0 && ky < 0));
             const int kk = in ? (mir ? -k : k) : 0;
@@ -295,11 +305,30 @@ k_colpass(ColArgs a)
             }
         });
         const T s = T(a.scale);
+        // adjoint: on the k_last = 0 hyperplane the entries the forward
+        // symmetrization overwrites (k < 0, or k = 0 with ky < 0) get zero,
+        // and the DC entry is halved and real
+        bool plane = false;
+        int ky = 0;
+        if (a.fsflags & 4) {
+            if (a.sym == 1) {
+                plane = c == 0;
+            } else if (a.sym == 2) {
+                const int64_t iy = cc / a.sym_nz, iz = cc - iy * a.sym_nz;
+                plane = iz == 0;
+                ky = int(iy) - a.sym_offy;
+            }
+        }
+        auto adj_edit = [&](int k, C<T> v) -> C<T> {
+            if (plane && (k < 0 || (k == 0 && ky < 0))) return zero<T>();
+            if (plane && k == 0 && ky == 0) return C<T>{T(0.5) * v.re, T(0)};
+            return v;
+        };
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = t + e * G;
-            if (k < a.m) strow(0, k + a.off_out, scale(ap[e], s));
-            if (k >= 1 && k - N > -a.m) strow(0, k - N + a.off_out, scale(an[e], s));
+            if (k < a.m) strow(0, k + a.off_out, adj_edit(k, scale(ap[e], s)));
+            if (k >= 1 && k - N > -a.m) strow(0, k - N + a.off_out, adj_edit(k - N, scale(an[e], s)));
         }
         // zero slots: rows whose wavenumber lies outside |k| < m
         for (int row = t; row < a.n_out; row += G) {

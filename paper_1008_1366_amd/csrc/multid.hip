@@ -194,8 +194,12 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
     if (!m || !n) return fail(IMPCONV_E_ARG, "m or n is NULL");
     if (batch < 0 || M < 1) return fail(IMPCONV_E_SIZE, "batch must be >= 0 and M >= 1");
     const uint32_t adj = IMPCONV_REV_F | IMPCONV_CONJ_G | IMPCONV_REV_OUT;
-    const uint32_t known = IMPCONV_NO_SYMMETRIZE | IMPCONV_EXPLICIT_PADDED | IMPCONV_EXPLICIT_PRUNED | adj;
+    const uint32_t known = IMPCONV_NO_SYMMETRIZE | IMPCONV_EXPLICIT_PADDED | IMPCONV_EXPLICIT_PRUNED | adj |
+                           IMPCONV_HERMITIAN_ADJOINT;
     if (flags & ~known) return fail(IMPCONV_E_ARG, "unsupported flag for an nD convolution");
+    if ((flags & IMPCONV_HERMITIAN_ADJOINT) &&
+        (kind != IMPCONV_HERMITIAN || (flags & (IMPCONV_EXPLICIT_PADDED | IMPCONV_NO_SYMMETRIZE))))
+        return fail(IMPCONV_E_ARG, "HERMITIAN_ADJOINT applies to implicit, symmetrized Hermitian nD convolutions");
     if ((flags & IMPCONV_EXPLICIT_PRUNED) && !(flags & IMPCONV_EXPLICIT_PADDED))
         return fail(IMPCONV_E_ARG, "EXPLICIT_PRUNED qualifies EXPLICIT_PADDED");
     if ((flags & adj) && (kind != IMPCONV_COMPLEX || (flags & IMPCONV_EXPLICIT_PADDED)))
@@ -296,10 +300,15 @@ impconv_status outer_bwd(const DevTables& tb, const PlanND& p, const void* src, 
 // Outer-axis forward pass: src[r]: [B][N0][ld=ldin] -> dst [B][n0][cols]
 impconv_status outer_fwd(const DevTables& tb, const PlanND& p, void* const* src, void* dst,
                          int64_t nslab, int64_t in_bs, int64_t in_ld, int64_t n0, int64_t m0,
-                         int64_t N0, int64_t cols, hipStream_t s, uint32_t fsflags = 0)
+                         int64_t N0, int64_t cols, hipStream_t s, uint32_t fsflags = 0, int sym = 0,
+                         int64_t sym_nz = 0, int sym_offy = 0, int sym_ny = 0)
 {
     ColArgs a = col_args(tb, p.dt);
     a.fsflags = fsflags;
+    a.sym = sym;
+    a.sym_nz = sym_nz;
+    a.sym_offy = sym_offy;
+    a.sym_ny = sym_ny;
     for (int r = 0; r < 3; ++r) a.in[r] = src[r];
     a.out[0] = dst;
     a.nslab = nslab;
@@ -643,6 +652,10 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
     const uint32_t fs_g = (flags & IMPCONV_CONJ_G) ? 2u : 0u;
     const uint32_t fs_o = (flags & IMPCONV_REV_OUT) ? 1u : 0u;
     const uint32_t rowfl = ((flags & IMPCONV_REV_F) ? kRevF : 0u) | ((flags & IMPCONV_REV_OUT) ? kRevOut : 0u);
+    // adjoint form (Hermitian): the k_last = 0 hyperplane of f enters as
+    // f_k + conj f_{-k} in the first outer pass, and the last outer pass
+    // edits that hyperplane of the output; the inner passes are unchanged
+    const uint32_t ha = (flags & IMPCONV_HERMITIAN_ADJOINT) ? 4u : 0u;
     if (nd == 2) {
         const int64_t N0 = p.Np[0], n0 = n[0], n1 = n[1], m0 = m[0], m1 = m[1];
         const size_t arr = size_t(batch) * M * N0 * n1 * cs;
@@ -652,12 +665,13 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
         // Hermitian: columns y < m1 carry data (slot m1 is a zero slot); k_y = 0 is column 0
         const int64_t mask_nz = herm ? n1 : 0;
         if ((st = outer_bwd(tb, p, f, Wf, batch, M * n0 * n1, n0, m0, N0, n1, sym ? 1 : 0, 0, 0, 0,
-                            mask_nz, 0, 1, int(m1), s, fs_f))) return st;
+                            mask_nz, 0, 1, int(m1), s, fs_f | ha))) return st;
         if ((st = outer_bwd(tb, p, g, Wg, batch, M * n0 * n1, n0, m0, N0, n1, sym ? 1 : 0, 0, 0, 0,
                             mask_nz, 0, 1, int(m1), s, fs_g))) return st;
         for (int r = 0; r < R; ++r)
             if ((st = inner_rows(tb, p, Wf[r], Wg[r], batch * N0, s, rowfl))) return st;
-        if ((st = outer_fwd(tb, p, Wf, h, batch, N0 * M * n1, M * n1, n0, m0, N0, n1, s, fs_o))) return st;
+        if ((st = outer_fwd(tb, p, Wf, h, batch, N0 * M * n1, M * n1, n0, m0, N0, n1, s, fs_o | ha,
+                            ha ? 1 : 0))) return st;
         return IMPCONV_OK;
     }
     // 3D
@@ -677,7 +691,7 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
     const int ylo = herm ? int(n1 - (2 * m1 - 1)) : 0;
     const int64_t mask_nz = herm ? n2 : 0;
     if ((st = outer_bwd(tb, p, f, Xf, batch, M * n0 * n1 * n2, n0, m0, N0, n1 * n2, sym ? 2 : 0, n2,
-                        int(n1 - m1), int(n1), mask_nz, ylo, int(n1), int(m2), s, fs_f))) return st;
+                        int(n1 - m1), int(n1), mask_nz, ylo, int(n1), int(m2), s, fs_f | ha))) return st;
     if ((st = outer_bwd(tb, p, g, Xg, batch, M * n0 * n1 * n2, n0, m0, N0, n1 * n2, sym ? 2 : 0, n2,
                         int(n1 - m1), int(n1), mask_nz, ylo, int(n1), int(m2), s, fs_g))) return st;
     void* Q[3];
@@ -746,7 +760,8 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
     // x forward: Q[rx] [b][x'][n1 n2] -> h [b][n0][n1 n2]
     PlanND px = p;
     px.M = 1;
-    if ((st = outer_fwd(tb, px, Q, h, batch, N0 * n1 * n2, n1 * n2, n0, m0, N0, n1 * n2, s, fs_o))) return st;
+    if ((st = outer_fwd(tb, px, Q, h, batch, N0 * n1 * n2, n1 * n2, n0, m0, N0, n1 * n2, s, fs_o | ha,
+                        ha ? 2 : 0, n2, int(n1 - m1), int(n1)))) return st;
     return IMPCONV_OK;
 }
 

@@ -93,6 +93,10 @@ def test_nd_workspace_and_errors(L):
     nb = (ctypes.c_int64 * 3)(512, 511, 258)
     assert L.impconv_convnd_workspace(1, 0, 3, mh, nb, 1, 3, 0, ctypes.byref(out)) == 2
     assert L.impconv_convnd_workspace(1, 0, 4, mh, nh, 1, 3, 0, ctypes.byref(out)) == 1
+    # HERMITIAN_ADJOINT: Hermitian kind only, not with NO_SYMMETRIZE
+    assert L.impconv_convnd_workspace(1, 0, 3, mh, nh, 1, 1, 1 << 5, ctypes.byref(out)) == 0
+    assert L.impconv_convnd_workspace(0, 0, 2, m, m, 8, 1, 1 << 5, ctypes.byref(out)) == 1
+    assert L.impconv_convnd_workspace(1, 0, 3, mh, nh, 1, 1, (1 << 5) | (1 << 4), ctypes.byref(out)) == 1
 
 
 def test_ragged_plan_validation(L):

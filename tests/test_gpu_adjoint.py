@@ -1,6 +1,7 @@
 """GPU checks of the hand-written adjoints beyond complex 1D: the centered
-Hermitian 1D convolution (the HERMITIAN_ADJOINT load/store edits) and the
-complex 2D/3D convolutions (REV_F / CONJ_G / REV_OUT along every axis):
+Hermitian 1D, 2D and 3D convolutions (the HERMITIAN_ADJOINT load/store
+edits) and the complex 2D/3D convolutions (REV_F / CONJ_G / REV_OUT along
+every axis):
 backward vs the oracle-evaluated adjoint formulas (pinned on the CPU by
 finite differences of the oracle) and vs torch.autograd.gradcheck."""
 import numpy as np
@@ -104,3 +105,76 @@ def test_complex_2d_gradcheck():
     f = to_dev(synth.unit_disk((1, 2, 5, 6), 372), np.complex128).requires_grad_(True)
     g = to_dev(synth.unit_disk((1, 2, 5, 6), 373), np.complex128).requires_grad_(True)
     assert torch.autograd.gradcheck(ic.conv2d_ad, (f, g), eps=1e-6, atol=1e-8)
+
+
+def herm_storage(m, n, seed):
+    u = synth.unit_disk(n, seed)
+    nd = len(m)
+    for d in range(nd - 1):
+        if n[d] == 2 * m[d]:
+            idx = [slice(None)] * nd
+            idx[d] = 0
+            u[tuple(idx)] = 0
+    if n[-1] == m[-1] + 1:
+        u[..., m[-1]] = 0
+    return u
+
+
+@pytest.mark.parametrize("dt", [np.complex128, np.complex64])
+@pytest.mark.parametrize("m,n", [((1, 1), (1, 1)), ((3, 4), (5, 4)), ((4, 3), (8, 4)), ((20, 17), (40, 18)),
+                                 ((3, 2, 3), (6, 3, 4)), ((5, 6, 4), (9, 12, 5))])
+def test_hermitian_nd_backward_vs_oracle(dt, m, n):
+    """Centered Hermitian 2D/3D backward (HERMITIAN_ADJOINT in the outer
+    passes) vs the adjoint formula evaluated with the oracle."""
+    from adjoint_ref import hermitian_nd_adjoint
+    ic = need_gpu()
+    import torch
+    say(f"hermitian nd adjoint m={m} n={n} {dt.__name__}")
+    B, M = 2, 2
+    f = np.stack([np.stack([herm_storage(m, n, 380 + 4 * b + i) for i in range(M)]) for b in range(B)])
+    g = np.stack([np.stack([herm_storage(m, n, 390 + 4 * b + i) for i in range(M)]) for b in range(B)])
+    w = synth.unit_disk((B, *n), 399)
+    F = to_dev(f, dt).requires_grad_(True)
+    G = to_dev(g, dt).requires_grad_(True)
+    fn = ic.conv2d_hermitian_ad if len(m) == 2 else ic.conv3d_hermitian_ad
+    h = fn(F, G, m)
+    torch.real(torch.sum(torch.conj(to_dev(w, dt)) * h)).backward()
+    for b in range(B):
+        wb = rounded(w[b], dt)
+        for i in range(M):
+            assert rel(F.grad[b, i].cpu().numpy(), hermitian_nd_adjoint(oracle, wb, rounded(g[b, i], dt), m)) < TOL[dt]
+            assert rel(G.grad[b, i].cpu().numpy(), hermitian_nd_adjoint(oracle, wb, rounded(f[b, i], dt), m)) < TOL[dt]
+
+
+def test_hermitian_2d_backward_sampled():
+    """m = (300, 200), storage (600, 201), complex64: sampled gradient entries
+    on and off the k_y = 0 line (authoritative, overwritten and origin)."""
+    from adjoint_ref import hermitian_gamma
+    ic = need_gpu()
+    import torch
+    m, n = (300, 200), (600, 201)
+    f, g = herm_storage(m, n, 401), herm_storage(m, n, 402)
+    w = synth.unit_disk(n, 403)
+    F = to_dev(f[None], np.complex64).requires_grad_(True)
+    G = to_dev(g[None], np.complex64).requires_grad_(True)
+    h = ic.conv2d_hermitian_ad(F, G, m)
+    torch.real(torch.sum(torch.conj(to_dev(w[None], np.complex64)) * h)).backward()
+    gf = F.grad[0].cpu().numpy()
+    pts = np.array([[0, 0], [17, 0], [-17, 0], [-299, 5], [250, 199], [-3, 120], [0, 77]])
+    gam = hermitian_gamma(rounded(w, np.complex64), m)
+    ref = oracle.convnd_hermitian_at(gam, rounded(g, np.complex64), m, pts)
+    ref[0] = ref[0].real / 2  # origin
+    ref[2] = 0                # overwritten half of the k_y = 0 line
+    got = gf[pts[:, 0] + n[0] - m[0], pts[:, 1]]
+    assert abs(got[2]) == 0
+    assert rel(got, ref) < TOL[np.complex64]
+
+
+@pytest.mark.parametrize("m,n", [((2, 3), (4, 4)), ((2, 2, 2), (3, 4, 3))])
+def test_hermitian_nd_gradcheck(m, n):
+    ic = need_gpu()
+    import torch
+    f = to_dev(herm_storage(m, n, 404)[None], np.complex128).requires_grad_(True)
+    g = to_dev(herm_storage(m, n, 405)[None], np.complex128).requires_grad_(True)
+    fn = ic.conv2d_hermitian_ad if len(m) == 2 else ic.conv3d_hermitian_ad
+    assert torch.autograd.gradcheck(lambda a, b: fn(a, b, m), (f, g), eps=1e-6, atol=1e-8)

@@ -532,3 +532,22 @@ def test_complex_nd_adjoint_formula(orc):
     fd = _fd_grad(L, f)
     an = orc.convnd_complex(w[::-1, ::-1].copy(), np.conj(g))[::-1, ::-1]
     assert rel(an, fd) < 1e-12
+
+
+@pytest.mark.parametrize("m,n", [((3, 4), (5, 4)), ((4, 3), (8, 4)), ((3, 2, 3), (6, 3, 4)),
+                                 ((2, 3, 2), (3, 6, 2))])
+def test_hermitian_nd_adjoint_formula(orc, m, n):
+    """Centered Hermitian 2D/3D: the gradient with respect to the stored half
+    is conv_herm(Gamma, g), Gamma = w off the k_last = 0 hyperplane and
+    w_k + conj(w_{-k}) on it, with the overwritten half of that hyperplane
+    zero and DC halved and real.  Finite differences see every stored entry,
+    zero slots and the ignored entries included."""
+    from adjoint_ref import hermitian_nd_adjoint
+    f, g = herm_storage(m, n, 137), herm_storage(m, n, 138)
+    w = rnd(n, 139)
+    L = lambda x: float(np.real(np.vdot(w, orc.convnd_hermitian(x, g, m))))
+    fd = _fd_grad(L, rnd(n, 140))
+    an = hermitian_nd_adjoint(orc, w, g, m)
+    assert rel(an, fd) < 1e-12
+    assert rel(hermitian_nd_adjoint(orc, w, f, m), _fd_grad(
+        lambda x: float(np.real(np.vdot(w, orc.convnd_hermitian(f, x, m)))), g)) < 1e-12
