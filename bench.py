@@ -73,11 +73,26 @@ def flops_row_hermitian(NC: int, M: int = 1) -> float:
     return 3 * (2 * M + 1) * 2.5 * m * np.log2(max(m, 2)) + 3 * (6.0 * 2 * M * NC + 2.0 * m * M) + 3 * 8.0 * NC
 
 
-def kernel_source_hash() -> str:
+# Sources a kernel's traffic depends on: the shared device headers and host
+# orchestration, plus its own family (column passes or row kernels).
+_SHARED_SOURCES = ("cx.hpp", "fft_wg.hpp", "launch.hpp", "runtime.hpp", "twiddle.hip", "abi.hip",
+                   "multid.hip", "multid.hpp", "ragged.hip", "plan.hip", "k_misc.hip")
+
+
+def kernel_source_hash(kernel: str = "") -> str:
+    """Hash of the sources that define `kernel` (all sources if unknown):
+    counter readings recorded under one hash are void once it changes."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1008_1366_amd", "csrc")
+    if kernel.startswith("colpass"):
+        own = lambda fn: fn == "colpass.hpp" or fn.startswith("k_col_")
+    elif kernel.startswith("k_conv1d"):
+        own = lambda fn: fn == "rowconv.hpp" or fn.startswith("k_row_")
+    else:
+        own = lambda fn: True
     for fn in sorted(os.listdir(csrc)):
-        if fn.endswith((".hpp", ".hip")):
+        if fn.endswith((".hpp", ".hip")) and (fn in _SHARED_SOURCES or own(fn)):
+            h.update(fn.encode())
             h.update(open(os.path.join(csrc, fn), "rb").read())
     return h.hexdigest()[:16]
 
@@ -652,9 +667,9 @@ def main():
         traffic = None
         tf = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{args.dtype}.json")
         if os.path.exists(tf):
-            t = json.load(open(tf))
-            if t.get("source_hash") == kernel_source_hash() and dom["name"] in t.get("kernels", {}):
-                traffic = t["kernels"][dom["name"]]
+            rec = json.load(open(tf)).get("kernels", {}).get(dom["name"])
+            if rec and rec.get("source_hash") == kernel_source_hash(dom["name"]):
+                traffic = rec["bytes"]
         hbm_frac = dom["gbs"] / HBM_PEAK_GBS if "gbs" in dom else None
         alu_frac = dom["tflops"] / VALU_PEAK_TFLOPS if "tflops" in dom else None
         if alu_frac is not None and (hbm_frac is None or alu_frac > hbm_frac):

@@ -106,10 +106,37 @@ impconv_status impconv_conv1d_workspace(int kind, int dtype, int64_t batch, int6
  * flags express the adjoint: dL/df = REV_OUT(conv(REV_F(dL/dh), CONJ_G(g))).
  * With IMPCONV_EXPLICIT_PADDED the same sum is computed by the conventional
  * method (inputs copied zero-padded to 2N in work, size-2N cyclic FFT
- * convolution, output cropped); REV/CONJ flags are not accepted with it. */
+ * convolution, output cropped); REV/CONJ flags are not accepted with it.
+ * The implicit method takes the general p/q rule of Sec. 2.4 where it needs
+ * clearly fewer transforms (see impconv_conv1d_complex_pq). */
 impconv_status impconv_conv1d_complex(int dtype, int64_t batch, int64_t M, int64_t m,
                                       const void* f, const void* g, void* h, void* work,
                                       size_t work_bytes, uint32_t flags, void* stream);
+
+/* Complex 1D convolution (the sum above) with the general p/q padding of
+ * Sec. 2.4: the inputs, zero beyond m, are taken as P = ceil(m / np) blocks
+ * of np values and implicitly padded to q np with q = ceil((2m - 1) / np),
+ * q np >= 2m - 1, so that no cyclic wrap-around reaches k < m; q residue
+ * transforms of size np per input replace the two of size 2^ceil(log2 m) of
+ * the 1/2 rule.  np: a power of two with P in {2, 3} and np <= 4096
+ * (complex64) or 2048 (complex128); np >= m (power of two <= 8192) runs the
+ * 1/2 rule at size np; np = 0 the automatic choice of impconv_conv1d_complex,
+ * which takes the p/q rule wherever its transform volume is clearly smaller
+ * (m up to 12288 / 6144 in one pass); np = 2^ceil(log2 m) above 8192 the
+ * multi-pass 1/2 rule.  Flags as for impconv_conv1d_complex (not
+ * IMPCONV_EXPLICIT_PADDED).  Workspace: impconv_conv1d_complex_pq_workspace
+ * (0 except for the multi-pass rule).  Other np: E_SIZE. */
+impconv_status impconv_conv1d_complex_pq(int dtype, int64_t batch, int64_t M, int64_t m, int64_t np,
+                                         const void* f, const void* g, void* h, void* work,
+                                         size_t work_bytes, uint32_t flags, void* stream);
+
+impconv_status impconv_conv1d_complex_pq_workspace(int dtype, int64_t batch, int64_t M, int64_t m, int64_t np,
+                                                   size_t* bytes);
+
+/* The rule impconv_conv1d_complex takes for length m: *np = 0 for the 1/2
+ * rule at N = 2^ceil(log2 m) (*p = 1, *q = 2), else the p/q block size,
+ * blocks and residues. */
+impconv_status impconv_conv1d_complex_rule(int dtype, int64_t m, int64_t* np, int* p, int* q);
 
 /* Centered Hermitian 1D convolution, Sec. 2.3 (2/3 rule, Fourier size 3N):
  * f, g hold the non-negative wavenumbers 0..m-1 of fields with

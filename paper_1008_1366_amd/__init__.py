@@ -79,6 +79,12 @@ def lib():
             "impconv_conv1d_workspace": ([ctypes.c_int, ctypes.c_int, _i64, _i64, _i64, _u32,
                                           ctypes.POINTER(_sz)], st),
             "impconv_conv1d_complex": ([ctypes.c_int, _i64, _i64, _i64, _p, _p, _p, _p, _sz, _u32, _p], st),
+            "impconv_conv1d_complex_pq": ([ctypes.c_int, _i64, _i64, _i64, _i64, _p, _p, _p, _p, _sz, _u32, _p],
+                                          st),
+            "impconv_conv1d_complex_pq_workspace": ([ctypes.c_int, _i64, _i64, _i64, _i64, ctypes.POINTER(_sz)],
+                                                    st),
+            "impconv_conv1d_complex_rule": ([ctypes.c_int, _i64, ctypes.POINTER(_i64),
+                                             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], st),
             "impconv_conv1d_hermitian": ([ctypes.c_int, _i64, _i64, _i64, _p, _p, _p, _p, _sz, _u32, _p], st),
             "impconv_conv1d_ternary": ([ctypes.c_int, _i64, _i64, _p, _p, _p, _p, _p, _sz, _u32, _p], st),
             "impconv_convnd_workspace": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, _p, _p, _i64, _i64,
@@ -196,6 +202,38 @@ def conv1d_complex(f, g, method: str = "implicit", flags: int = 0):
     """Complex 1D dealiased convolution (Sec. 2.1) of (m,), (B, m) or (B, M, m)
     inputs (M = dot-product width); returns (m,) or (B, m)."""
     return _conv1d(COMPLEX, f, g, method, flags)
+
+
+def conv1d_complex_pq(f, g, np: int, flags: int = 0):
+    """Complex 1D convolution with the general p/q padding of Sec. 2.4 at
+    block size np (a power of two): P = ceil(m / np) blocks, q =
+    ceil((2m - 1) / np) residues of size-np transforms; np >= m is the 1/2
+    rule at size np (np = 2^ceil(log2 m) above 8192: the multi-pass 1/2
+    rule), np = 0 the library's automatic choice."""
+    if f.shape != g.shape or f.dtype != g.dtype:
+        raise ValueError("f and g must have the same shape and dtype")
+    dev = _dev(f, g)
+    F, G = _as_bmm(f), _as_bmm(g)
+    B, M, m = F.shape
+    dt = _dtype_code(f)
+    h = torch.empty((B, m), dtype=f.dtype, device=dev)
+    wb = _sz()
+    _check(lib().impconv_conv1d_complex_pq_workspace(dt, B, M, m, int(np), ctypes.byref(wb)),
+           "conv1d_complex_pq_workspace")
+    w = _work(wb.value, dev)
+    _check(lib().impconv_conv1d_complex_pq(dt, B, M, m, int(np), _ptr(F), _ptr(G), _ptr(h), _ptr(w), wb.value,
+                                           flags, ctypes.c_void_p(_stream(dev))), "conv1d_complex_pq")
+    return h.view(m) if f.dim() == 1 else h
+
+
+def complex_rule(m: int, dtype=torch.complex64):
+    """(np, p, q) of the rule conv1d_complex uses for length m: np = 0 is the
+    1/2 rule at the power-of-two size (p = 1, q = 2)."""
+    np_, p, q = _i64(), ctypes.c_int(), ctypes.c_int()
+    dt = C128 if dtype == torch.complex128 else C64
+    _check(lib().impconv_conv1d_complex_rule(dt, int(m), ctypes.byref(np_), ctypes.byref(p), ctypes.byref(q)),
+           "conv1d_complex_rule")
+    return np_.value, p.value, q.value
 
 
 def conv1d_hermitian(f, g, method: str = "implicit", flags: int = 0):

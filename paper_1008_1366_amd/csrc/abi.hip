@@ -1,6 +1,7 @@
 // abi.cpp -- the extern "C" entry points of libimpconv: argument checks on
 // the host, workspace sizing, and the launch sequence of each convolution.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -67,9 +68,59 @@ struct Plan1D {
     bool explicit_;   // comparator path
     int64_t Ne;       // explicit: padded transform size
     size_t work;      // bytes
+    int64_t np;       // complex, general p/q rule: block size (0: the 1/2 rule at size N)
+    int pq_p, pq_q;   // blocks and residues of the p/q rule
 };
 
-impconv_status plan1d(int kind, int dt, int64_t batch, int64_t M, int64_t m, uint32_t flags, Plan1D* p)
+// ---------------------------------------------------- general p/q padding
+// Sec. 2.4 with the inputs zero-extended to P blocks of NP (P NP >= m) and
+// q = ceil((2m - 1) / NP) residues, so that q NP >= 2m - 1 and the cyclic
+// convolution of length q NP has no wrap-around onto k < m.
+bool pq_rule(int dt, int64_t m, int64_t np, int64_t* P, int64_t* q)
+{
+    if (np < 1 || (np & (np - 1)) || np > (dt ? kPqMax / 2 : kPqMax)) return false;
+    *P = (m + np - 1) / np;
+    *q = (2 * m - 1 + np - 1) / np;
+    return *P >= 2 && *P <= kPqMaxP;
+}
+
+// Relative cost per row, calibrated on MI355X: transform volume times
+// (log2 size + per-element work).  The p/q kernel re-reads its P blocks for
+// every residue and keeps P output blocks live (half the elements per
+// thread of the 1/2-rule kernel), which costs it ~1.5x (P = 2) / ~1.75x
+// (P = 3) per unit of volume; the 1/2 rule pays ~1.5x where it needs the
+// multi-pass path (N > kRowMax) or, in complex128, the register-bound
+// N = kRowMax kernel.
+double cost_half_rule(int dt, int64_t m)
+{
+    const int64_t N = next_pow2(m);
+    const double c = 2.0 * double(N) * (std::log2(double(N)) + 2.0);
+    return (N > kRowMax || (dt && N == kRowMax)) ? 1.5 * c : c;
+}
+double cost_pq_rule(int64_t np, int64_t P, int64_t q)
+{
+    return double(q) * double(np) * (std::log2(double(np)) + 2.0 + double(P)) * (1.0 + 0.25 * double(P));
+}
+
+// Block size of the cheapest p/q rule for m, or 0 if the 1/2 rule at the
+// power-of-two size is cheaper.
+int64_t pq_auto(int dt, int64_t m)
+{
+    int64_t best = 0;
+    double bc = cost_half_rule(dt, m);
+    for (int64_t np = 1; np <= kPqMax; np *= 2) {
+        int64_t P, q;
+        if (!pq_rule(dt, m, np, &P, &q)) continue;
+        const double c = cost_pq_rule(np, P, q);
+        if (c < bc) { bc = c; best = np; }
+    }
+    return best;
+}
+
+// np_req (complex only): -1 automatic, 0 the 1/2 rule at N = 2^ceil(log2 m),
+// > 0 the p/q rule with that block size (np >= m: the 1/2 rule at size np).
+impconv_status plan1d(int kind, int dt, int64_t batch, int64_t M, int64_t m, uint32_t flags, Plan1D* p,
+                      int64_t np_req = -1)
 {
     impconv_status st = check_dtype(dt);
     if (st) return st;
@@ -84,12 +135,31 @@ impconv_status plan1d(int kind, int dt, int64_t batch, int64_t M, int64_t m, uin
         return fail(IMPCONV_E_ARG, "REV/CONJ flags apply to complex convolutions only");
     if ((flags & IMPCONV_HERMITIAN_ADJOINT) && kind != IMPCONV_HERMITIAN)
         return fail(IMPCONV_E_ARG, "HERMITIAN_ADJOINT applies to Hermitian convolutions only");
-    *p = Plan1D{kind, dt, batch, M, m, flags, 0, bool(flags & IMPCONV_EXPLICIT_PADDED), 0, 0};
+    *p = Plan1D{kind, dt, batch, M, m, flags, 0, bool(flags & IMPCONV_EXPLICIT_PADDED), 0, 0, 0, 0, 0};
     if (p->explicit_ && adj) return fail(IMPCONV_E_ARG, "REV/CONJ flags are not accepted with EXPLICIT_PADDED");
     const size_t cs = csize(dt);
     if (kind == IMPCONV_COMPLEX) {
         p->N = next_pow2(m);
         if (!p->explicit_) {
+            if (np_req < 0) np_req = pq_auto(dt, m);
+            if (np_req > 0) {
+                if (np_req >= m && np_req <= kRowMax && (np_req & (np_req - 1)) == 0) {
+                    p->N = np_req;  // P = 1: the 1/2 rule at size np
+                    return IMPCONV_OK;
+                }
+                if (np_req == p->N) np_req = 0;  // the 1/2 rule at N, multi-pass above kRowMax
+            }
+            if (np_req > 0) {
+                int64_t P, q;
+                if (!pq_rule(dt, m, np_req, &P, &q))
+                    return fail(IMPCONV_E_SIZE, "p/q rule: np must be a power of two <= " +
+                                                    std::to_string(dt ? kPqMax / 2 : kPqMax) +
+                                                    " with ceil(m / np) <= " + std::to_string(kPqMaxP));
+                p->np = np_req;
+                p->pq_p = int(P);
+                p->pq_q = int(q);
+                return IMPCONV_OK;
+            }
             if (p->N > kRowMax) return large1d_plan(p->dt, batch, M, m, &p->work) ;
         } else {
             p->Ne = 2 * p->N;
@@ -179,10 +249,10 @@ impconv_status impconv_conv1d_workspace(int kind, int dtype, int64_t batch, int6
 
 static impconv_status run1d(int kind, int dtype, int64_t batch, int64_t M, int64_t m, const void* f,
                             const void* g, const void* e, void* h, void* work, size_t wb,
-                            uint32_t flags, void* stream)
+                            uint32_t flags, void* stream, int64_t np_req = -1)
 {
     Plan1D p;
-    impconv_status st = plan1d(kind, dtype, batch, M, m, flags, &p);
+    impconv_status st = plan1d(kind, dtype, batch, M, m, flags, &p, np_req);
     if (st) return st;
     if (batch == 0) return IMPCONV_OK;
     const int dt = dtype;
@@ -200,7 +270,7 @@ static impconv_status run1d(int kind, int dtype, int64_t batch, int64_t M, int64
     hipStream_t s = S(stream);
     hipError_t err = hipSuccess;
 
-    if (kind == IMPCONV_COMPLEX && !p.explicit_ && p.N > kRowMax)
+    if (kind == IMPCONV_COMPLEX && !p.explicit_ && p.np == 0 && p.N > kRowMax)
         return large1d_run(*tb, dt, batch, M, m, f, g, h, work, flags, s);
 
     RowArgs a = row_args(tb, dt);
@@ -217,8 +287,16 @@ static impconv_status run1d(int kind, int dtype, int64_t batch, int64_t M, int64
             a.f_row = a.g_row = M * m;
             a.f_i = a.g_i = m;
             a.h_row = m;
-            err = kind == IMPCONV_COMPLEX ? launch_row_complex(dt, int(p.N), a, s)
-                                          : launch_row_hermitian(dt, int(p.N), a, s);
+            if (kind == IMPCONV_COMPLEX && p.np > 0) {
+                const int64_t Nq = p.pq_q * p.np;
+                a.q = p.pq_q;
+                a.twq = (Nq & (Nq - 1)) == 0 ? static_cast<const void*>(static_cast<const char*>(tb->tw[dt]) + tw_off(Nq) * cs)
+                                             : static_cast<const void*>(static_cast<const char*>(tb->twq[dt]) + twq_off(p.pq_q, p.np) * cs);
+                err = launch_row_pq(dt, int(p.np), p.pq_p, a, s);
+            } else {
+                err = kind == IMPCONV_COMPLEX ? launch_row_complex(dt, int(p.N), a, s)
+                                              : launch_row_hermitian(dt, int(p.N), a, s);
+            }
         }
         if (err != hipSuccess) return hip_fail(err, "row kernel launch");
         return IMPCONV_OK;
@@ -264,6 +342,40 @@ impconv_status impconv_conv1d_complex(int dtype, int64_t batch, int64_t M, int64
                                       uint32_t flags, void* stream)
 {
     return run1d(IMPCONV_COMPLEX, dtype, batch, M, m, f, g, nullptr, h, work, work_bytes, flags, stream);
+}
+
+impconv_status impconv_conv1d_complex_pq(int dtype, int64_t batch, int64_t M, int64_t m, int64_t np,
+                                         const void* f, const void* g, void* h, void* work,
+                                         size_t work_bytes, uint32_t flags, void* stream)
+{
+    if (np < 0) return fail(IMPCONV_E_SIZE, "np must be >= 0");
+    if (flags & IMPCONV_EXPLICIT_PADDED) return fail(IMPCONV_E_ARG, "the p/q rule is an implicit method");
+    return run1d(IMPCONV_COMPLEX, dtype, batch, M, m, f, g, nullptr, h, work, work_bytes, flags, stream,
+                 np == 0 ? -1 : np);
+}
+
+impconv_status impconv_conv1d_complex_pq_workspace(int dtype, int64_t batch, int64_t M, int64_t m, int64_t np,
+                                                   size_t* bytes)
+{
+    if (!bytes) return fail(IMPCONV_E_ARG, "bytes is NULL");
+    if (np < 0) return fail(IMPCONV_E_SIZE, "np must be >= 0");
+    Plan1D p;
+    impconv_status st = plan1d(IMPCONV_COMPLEX, dtype, batch, M, m, 0, &p, np == 0 ? -1 : np);
+    if (st) return st;
+    *bytes = p.work;
+    return IMPCONV_OK;
+}
+
+impconv_status impconv_conv1d_complex_rule(int dtype, int64_t m, int64_t* np, int* p, int* q)
+{
+    if (!np || !p || !q) return fail(IMPCONV_E_ARG, "null output pointer");
+    Plan1D pl;
+    impconv_status st = plan1d(IMPCONV_COMPLEX, dtype, 1, 1, m, 0, &pl);
+    if (st) return st;
+    *np = pl.np;
+    *p = pl.np ? pl.pq_p : 1;
+    *q = pl.np ? pl.pq_q : 2;
+    return IMPCONV_OK;
 }
 
 impconv_status impconv_conv1d_hermitian(int dtype, int64_t batch, int64_t M, int64_t m, const void* f,

@@ -17,6 +17,11 @@ hipError_t launch_row_cyclic(int dt, int N, const RowArgs& a, hipStream_t s);
 hipError_t launch_row_hermitian(int dt, int NC, const RowArgs& a, hipStream_t s);
 hipError_t launch_row_ternary(int dt, int NN, const RowArgs& a, hipStream_t s);
 hipError_t launch_row_realcyclic(int dt, int NC, const RowArgs& a, hipStream_t s);
+// General p/q rule: block size NP <= kPqMax (power of two), P in {2, 3};
+// a.q residues, a.twq = zeta_{q NP} table.
+constexpr int kPqMax = 4096;  // complex64; complex128: kPqMax / 2 (register budget)
+constexpr int kPqMaxP = 3;
+hipError_t launch_row_pq(int dt, int NP, int P, const RowArgs& a, hipStream_t s);
 
 // dst[r][j] = j < copy ? src[r][j] : 0, j < dst_ld
 hipError_t launch_pad_rows(int dt, const void* src, void* dst, int64_t nrows, int64_t src_ld,

@@ -38,6 +38,8 @@ struct RowArgs {
     const void* tw;          // concatenated zeta_N^j tables, N = 1, 2, 4, ...
     const void* tw3;         // concatenated zeta_{3N}^j tables (j < N)
     int64_t h_pad;           // Hermitian rows: stored output length; entries m..h_pad-1 are zeroed
+    const void* twq;         // general p/q rule: zeta_{q NP}^j, j < q NP
+    int q;                   // general p/q rule: residues
 };
 
 // Elements per thread of the row kernels: family 0 (complex, cyclic) keeps
@@ -273,6 +275,121 @@ k_conv1d_complex(RowArgs a)
         for (int e = 0; e < E; ++e) {
             const int k = t + e * G;
             if (k < c.m) H[revo ? c.m - 1 - k : k] = scale(acc[e], s);
+        }
+    }
+}
+
+// ======================================================================
+// Complex 1D convolution with general p/q padding (Sec. 2.4).  The inputs
+// (zero beyond m) are taken as P blocks of NP values, P NP >= m, and padded
+// implicitly to Nq = q NP with Nq >= 2m - 1, so that the cyclic convolution
+// of length Nq is the linear one on k < m.  For each residue r < q
+//   x_r[s] = zeta_Nq^{rs} sum_{t<P} zeta_q^{rt} f_{t NP + s},  s < NP,
+// is transformed backward at size NP (likewise g), the products, summed over
+// the M terms, are transformed forward, and
+//   Nq h_{t NP + s} = sum_{r<q} zeta_q^{-rt} zeta_Nq^{-rs} V_r[s].
+// q NP transforms of size NP replace the 2N of size N = 2^ceil(log2 m) of
+// the 1/2 rule.  The inputs are re-read for each residue (from cache); the
+// P output blocks accumulate in registers.
+// ======================================================================
+template <typename T, int NP, int P>
+__global__ void __launch_bounds__((row_block<T, 1>(NP)), row_waves<T>(NP))
+k_conv1d_pq(RowArgs a)
+{
+    constexpr int E = row_E<T, 1>(NP), G = NP / E, GPB = row_GPB<T, 1>(NP), LDSN = row_lds<T, 1>(NP);
+    constexpr bool DUAL = 2 * GPB * LDSN * int(sizeof(C<T>)) <= 160 * 1024;
+    __shared__ C<T> sh[(DUAL ? 2 : 1) * GPB * LDSN];
+    static_assert(sizeof(sh) <= 160 * 1024, "LDS footprint exceeds 160 KB");
+    const int grp = threadIdx.x / G, t = threadIdx.x % G;
+    const RowCtx c = row_ctx(a, (int64_t)blockIdx.x * GPB + grp);
+    C<T>* lds = sh + grp * LDSN;
+    C<T>* lds1 = DUAL ? sh + (GPB + grp) * LDSN : lds;
+    const C<T>* twN = (const C<T>*)a.tw + tw_off(NP);
+    const C<T>* twq = (const C<T>*)a.twq;
+    const int q = a.q, m = c.m;
+    const C<T>* F = (const C<T>*)a.f + c.of;
+    const C<T>* Gp = (const C<T>*)a.g + c.og;
+    C<T>* H = (C<T>*)a.h + c.oh;
+    const bool revf = a.flags & kRevF, cjg = a.flags & kConjG, revo = a.flags & kRevOut;
+
+    C<T> acc[P][E];
+    for (int r = 0; r < q; ++r) {
+        // zeta_q^{rt} = zeta_Nq^{(rt mod q) NP} for the P blocks (wave uniform)
+        C<T> zq[P];
+        {
+            int j = 0;
+#pragma unroll
+            for (int b = 0; b < P; ++b) {
+                zq[b] = twq[j * NP];
+                j += r;
+                if (j >= q) j -= q;
+            }
+        }
+        C<T> w[E];  // zeta_Nq^{rs}, s = t + eG
+        {
+            const int z = opaque_zero();
+#pragma unroll
+            for (int e = 0; e < E; ++e) w[e] = twq[r * (t + e * G) + z];
+        }
+        C<T> Pr[E];
+        for (int64_t i = 0; i < a.M; ++i) {
+            C<T> x[E], y[E];
+            const int z = opaque_zero();
+            const C<T>* Fi = F + i * a.f_i + z;
+            const C<T>* Gi = Gp + i * a.g_i + z;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int s = t + e * G;
+                C<T> sf = ldz(Fi, revf ? m - 1 - s : s, m);
+#pragma unroll
+                for (int b = 1; b < P; ++b) {
+                    const int k = b * NP + s;
+                    sf = sf + zq[b] * ldz(Fi, revf ? m - 1 - k : k, m);
+                }
+                x[e] = sf * w[e];
+            }
+            // keep the two inputs' loads apart: the P E values of one input
+            // in flight at a time
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int s = t + e * G;
+                auto gld = [&](int k) {  // g_k, conjugated before the block weights
+                    const C<T> v = ldz(Gi, k, m);
+                    return cjg ? conj(v) : v;
+                };
+                C<T> sg = gld(s);
+#pragma unroll
+                for (int b = 1; b < P; ++b) sg = sg + zq[b] * gld(b * NP + s);
+                y[e] = sg * w[e];
+            }
+            if constexpr (DUAL) {
+                fft2<T, NP, E, +1>(x, y, t, lds, lds1, 1, twN);
+            } else {
+                fft<T, NP, E, +1>(x, t, lds, 1, twN);
+                fft<T, NP, E, +1>(y, t, lds, 1, twN);
+            }
+#pragma unroll
+            for (int e = 0; e < E; ++e) Pr[e] = i > 0 ? Pr[e] + x[e] * y[e] : x[e] * y[e];
+        }
+        fft<T, NP, E, -1>(Pr, t, lds, 1, twN);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const C<T> v = mulc(Pr[e], w[e]);  // zeta_Nq^{-rs} V_r[s]
+#pragma unroll
+            for (int b = 0; b < P; ++b) {
+                const C<T> u = mulc(v, zq[b]);  // zeta_q^{-rb}
+                acc[b][e] = r > 0 ? acc[b][e] + u : u;
+            }
+        }
+    }
+    const T sc = T(1) / T(q * NP);
+#pragma unroll
+    for (int b = 0; b < P; ++b) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = b * NP + t + e * G;
+            if (k < m) H[revo ? m - 1 - k : k] = scale(acc[b][e], sc);
         }
     }
 }

@@ -13,10 +13,18 @@ namespace impconv {
 // the zeta_{3N}^j tables.
 constexpr int kTwLog = 18;
 constexpr int kTw3Log = 16;
+// General p/q padding (Sec. 2.4): transform sizes NP = 2^l <= 2^kTwqLog,
+// residue counts q with a table zeta_{q NP}^j (j < q NP) of their own (the
+// power-of-two q use the zeta_N tables).
+constexpr int kTwqLog = 12;
+constexpr int kTwqList[4] = {3, 5, 6, 7};
+// Element offset of zeta_{q NP}^j in the concatenated q tables, or -1.
+int64_t twq_off(int q, int64_t NP);
 
 struct DevTables {
     const void* tw[2];   // [0] complex64, [1] complex128: concatenated zeta_N^j, offset N - 1
     const void* tw3[2];  // concatenated zeta_{3N}^j (j < N), offset N - 1
+    const void* twq[2];  // concatenated zeta_{q NP}^j (j < q NP), offset twq_off(q, NP)
     int ncu;             // compute units
 };
 

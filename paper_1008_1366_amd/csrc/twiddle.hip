@@ -1,12 +1,13 @@
-// twiddle.cpp -- FP64 roots of unity for the FFT stages and the residue
+// twiddle.hip -- FP64 roots of unity for the FFT stages and the residue
 // shifts (Sec. 2.1 discussion of the zeta_N^k factors).  The paper builds
 // them from two short tables with one complex multiply; on the GPU the full
-// per-size tables cost only ~12 MB of HBM and one cached load per use, so
+// per-size tables cost only ~16 MB of HBM and one cached load per use, so
 // they are stored directly: tw_N[j] = zeta_N^j for every power-of-two N up to
-// 2^18 (concatenated, tw_N at offset N - 1) and zeta_{3N}^j, j < N, for the
-// 2/3-rule shifts.  Each value is computed in long double with the argument
-// reduced exactly (integer j mod denom, folded into the first octant) and
-// rounded once to double; the complex64 tables round those doubles to float.
+// 2^18 (concatenated, tw_N at offset N - 1), zeta_{3N}^j, j < N, for the
+// 2/3-rule shifts, and zeta_{q NP}^j, j < q NP, for the general p/q rule.
+// Each value is computed in long double with the argument reduced exactly
+// (integer j mod denom, folded into the first octant) and rounded once to
+// double; the complex64 tables round those doubles to float.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -53,6 +54,19 @@ void gen_roots(int64_t denom, int64_t count, double* out)
     }
 }
 
+int64_t twq_off(int q, int64_t NP)
+{
+    int64_t off = 0;
+    for (int qq : kTwqList) {
+        for (int l = 0; l <= kTwqLog; ++l) {
+            const int64_t n = int64_t(1) << l;
+            if (qq == q && n == NP) return off;
+            off += qq * n;
+        }
+    }
+    return -1;
+}
+
 namespace {
 
 std::mutex g_mu;
@@ -97,6 +111,15 @@ const DevTables* tables()
         const int64_t N = int64_t(1) << l;
         gen_roots(3 * N, N, tw3.data() + 2 * (N - 1));
     }
+    std::vector<double> twq;
+    for (int q : kTwqList) {
+        for (int l = 0; l <= kTwqLog; ++l) {
+            const int64_t NP = int64_t(1) << l;
+            const size_t at = twq.size();
+            twq.resize(at + 2 * q * NP);
+            gen_roots(q * NP, q * NP, twq.data() + at);
+        }
+    }
     DevTables t{};
     if ((e = hipDeviceGetAttribute(&t.ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) {
         hip_fail(e, "hipDeviceGetAttribute");
@@ -105,7 +128,9 @@ const DevTables* tables()
     if ((e = upload<float>(tw, &t.tw[0])) != hipSuccess ||
         (e = upload<double>(tw, &t.tw[1])) != hipSuccess ||
         (e = upload<float>(tw3, &t.tw3[0])) != hipSuccess ||
-        (e = upload<double>(tw3, &t.tw3[1])) != hipSuccess) {
+        (e = upload<double>(tw3, &t.tw3[1])) != hipSuccess ||
+        (e = upload<float>(twq, &t.twq[0])) != hipSuccess ||
+        (e = upload<double>(twq, &t.twq[1])) != hipSuccess) {
         hip_fail(e, "twiddle table upload");
         return nullptr;
     }

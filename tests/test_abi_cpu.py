@@ -149,3 +149,28 @@ def test_plan_create_validation(L):
     assert L.impconv_plan_destroy(None) == 0
     assert L.impconv_conv1d_complex_ragged(0, -1, None, None, None, None, None, None, 0, 0, None) == 2
     assert L.impconv_conv1d_complex_ragged(0, 2, None, None, None, None, None, None, 0, 0, None) == 1
+
+
+def test_pq_rule_and_validation(L):
+    """General p/q rule (host logic only): the automatic choice and the
+    block-size checks, which return before any pointer is used."""
+    np_, p, q = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int()
+    # one pass above the largest row transform (complex64): P = 3 blocks of 4096, q = 5
+    assert L.impconv_conv1d_complex_rule(0, 10000, ctypes.byref(np_), ctypes.byref(p), ctypes.byref(q)) == 0
+    assert (np_.value, p.value, q.value) == (4096, 3, 5)
+    # complex128 at 5000: three blocks of 2048 instead of the 8192-point 1/2 rule
+    assert L.impconv_conv1d_complex_rule(1, 5000, ctypes.byref(np_), ctypes.byref(p), ctypes.byref(q)) == 0
+    assert (np_.value, p.value, q.value) == (2048, 3, 5)
+    for m in (1024, 1100, 3000, 16384):
+        assert L.impconv_conv1d_complex_rule(0, m, ctypes.byref(np_), ctypes.byref(p), ctypes.byref(q)) == 0
+        assert (np_.value, p.value, q.value) == (0, 1, 2), m
+    fn = L.impconv_conv1d_complex_pq
+    fn.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64] + \
+        [ctypes.c_void_p] * 4 + [ctypes.c_size_t, ctypes.c_uint32, ctypes.c_void_p]
+    fn.restype = ctypes.c_int
+    assert fn(0, 1, 1, 1000, 300, None, None, None, None, 0, 0, None) == 2    # not a power of two
+    assert fn(0, 1, 1, 1000, 128, None, None, None, None, 0, 0, None) == 2    # P = 8
+    assert fn(0, 1, 1, 12000, 8192, None, None, None, None, 0, 0, None) == 2  # block above 4096
+    assert fn(1, 1, 1, 5000, 4096, None, None, None, None, 0, 0, None) == 2   # complex128: 2048 at most
+    assert fn(0, 1, 1, 1000, 512, None, None, None, None, 0, 0, None) == 1    # valid rule, null pointers
+    assert fn(0, 1, 1, 1000, 512, None, None, None, None, 0, 1, None) == 1    # EXPLICIT_PADDED
