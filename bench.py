@@ -668,7 +668,7 @@ def main():
         tf = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{args.dtype}.json")
         if os.path.exists(tf):
             rec = json.load(open(tf)).get("kernels", {}).get(dom["name"])
-            if rec and rec.get("source_hash") == kernel_source_hash(dom["name"]):
+            if isinstance(rec, dict) and rec.get("source_hash") == kernel_source_hash(dom["name"]):
                 traffic = rec["bytes"]
         hbm_frac = dom["gbs"] / HBM_PEAK_GBS if "gbs" in dom else None
         alu_frac = dom["tflops"] / VALU_PEAK_TFLOPS if "tflops" in dom else None

@@ -227,16 +227,9 @@ k_colpass(ColArgs a)
             mcol = (iym >= 0 && iym < a.sym_ny) ? int64_t(iym) * a.sym_nz : cc;
         }
         const C<T>* base = (const C<T>*)a.in[0] + s1 * a.in_bs + s2 * a.in_bs2;
-        const bool adj = a.fsflags & 4;
-        auto ldk = [&](int k) -> C<T> {  // wavenumber k of this column (|k| < m)
+        // wavenumber k of this column (|k| < m)
+        auto ldk = [&](int k) -> C<T> {
             const bool in = cact && k > -a.m && k < a.m;
-            if (adj) {
-                // adjoint: U_k + conj U_{-k} on the hyperplane (both halves)
-                const int kk = in ? k : 0;
-                C<T> v = base[cc + int64_t(kk + a.off_in) * a.in_ld];
-                if (plane) v = v + conj(base[mcol + int64_t(-kk + a.off_in) * a.in_ld]);
-                return in ? v : zero<T>();
-            }
             // mirror: k < 0, or k = 0 with ky < 0 (3D); DC real
             const bool mir = plane && (k < 0 || (k == 0 && ky < 0));
             const int kk = in ? (mir ? -k : k) : 0;
@@ -246,18 +239,39 @@ k_colpass(ColArgs a)
             if (plane && k == 0 && ky == 0) v.im = T(0);
             return in ? v : zero<T>();
         };
+        // adjoint: U_k + conj U_{-k} on the hyperplane (both halves); off it
+        // the second load repeats the first address (a cache hit)
+        auto ldk_adj = [&](int k) -> C<T> {
+            const bool in = cact && k > -a.m && k < a.m;
+            const int kk = in ? k : 0;
+            const C<T> v = base[cc + int64_t(kk + a.off_in) * a.in_ld];
+            const C<T> u = base[(plane ? mcol : cc) + int64_t((plane ? -kk : kk) + a.off_in) * a.in_ld];
+            const C<T> s = plane ? v + conj(u) : v;
+            return in ? s : zero<T>();
+        };
         // The thread index goes through an empty asm so the per-element
         // mirror selection below stays a run-time computation.  With one
         // thread per column (G = 1) it is otherwise fully constant-folded,
         // and that folded form was observed to load wrong mirrored values
-        // (caught by the G = 1 symmetrized parity cases).
+        // (caught by the G = 1 symmetrized parity cases).  The adjoint test
+        // is taken once, outside the element loops, so that each loop stays
+        // free of branches and its loads issue back to back.
         int tl = t;
         asm volatile("" : "+v"(tl));
+        if (a.fsflags & 4) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int k = tl + e * G;
-            up[e] = ldk(k);
-            un[e] = ldk(k - N);
+            for (int e = 0; e < E; ++e) {
+                const int k = tl + e * G;
+                up[e] = ldk_adj(k);
+                un[e] = ldk_adj(k - N);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int k = tl + e * G;
+                up[e] = ldk(k);
+                un[e] = ldk(k - N);
+            }
         }
         const T h3 = T(0.86602540378443864676);
         static_for<3>([&](auto ri) {

@@ -251,6 +251,83 @@ __device__ __forceinline__ void fft2(C<T> (&v0)[E], C<T> (&v1)[E], int t, C<T>* 
     if constexpr (N > 1) fft2_stage<T, N, E, DIR, 1, TW>(v0, v1, t, lds0, lds1, LS, tw);
 }
 
+// Three independent FFTs advanced together (as fft2_stage, three exchange
+// buffers): the three residues of the 2/3 rule share every barrier and
+// twiddle load.
+template <typename T, int N, int E, int DIR, int NS, typename TW>
+__device__ __forceinline__ void fft3_stage(C<T> (&v0)[E], C<T> (&v1)[E], C<T> (&v2)[E], int t, C<T>* lds0,
+                                           C<T>* lds1, C<T>* lds2, int LS, TW tw)
+{
+    constexpr int R = (N / NS < E) ? (N / NS) : E;
+    constexpr bool LAST = (NS * R == N);
+    constexpr int G = N / E;
+    constexpr int Q = E / R;
+    int zoff = 0;
+    asm volatile("" : "+s"(zoff));
+    asm volatile("" : "+v"(t));
+    const TW tws = tw + zoff;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int b = t + q * G;
+        const int k = b & (NS - 1);
+        C<T> u0[R], u1[R], u2[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            u0[r] = v0[q + r * Q];
+            u1[r] = v1[q + r * Q];
+            u2[r] = v2[q + r * Q];
+        }
+        if constexpr (NS > 1) {
+            const int ks = k * (N / (NS * R));
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const C<T> w = tws[r * ks];
+                u0[r] = mulw<DIR>(u0[r], w);
+                u1[r] = mulw<DIR>(u1[r], w);
+                u2[r] = mulw<DIR>(u2[r], w);
+            }
+        }
+        DFT<R, DIR, T>::run(u0);
+        DFT<R, DIR, T>::run(u1);
+        DFT<R, DIR, T>::run(u2);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                v0[q + r * Q] = u0[r];
+                v1[q + r * Q] = u1[r];
+                v2[q + r * Q] = u2[r];
+            }
+        } else {
+            const int wb = lpad((b - k) * R + k) * LS;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                lds0[wb + (r * NS + ((r * NS) >> 4)) * LS] = u0[r];
+                lds1[wb + (r * NS + ((r * NS) >> 4)) * LS] = u1[r];
+                lds2[wb + (r * NS + ((r * NS) >> 4)) * LS] = u2[r];
+            }
+        }
+    }
+    if constexpr (!LAST) {
+        __syncthreads();
+        const int rb = lpad(t) * LS;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            v0[i] = lds0[rb + (i * G + ((i * G) >> 4)) * LS];
+            v1[i] = lds1[rb + (i * G + ((i * G) >> 4)) * LS];
+            v2[i] = lds2[rb + (i * G + ((i * G) >> 4)) * LS];
+        }
+        __syncthreads();
+        fft3_stage<T, N, E, DIR, NS * R, TW>(v0, v1, v2, t, lds0, lds1, lds2, LS, tw);
+    }
+}
+
+template <typename T, int N, int E, int DIR, typename TW>
+__device__ __forceinline__ void fft3(C<T> (&v0)[E], C<T> (&v1)[E], C<T> (&v2)[E], int t, C<T>* lds0,
+                                     C<T>* lds1, C<T>* lds2, int LS, TW tw)
+{
+    if constexpr (N > 1) fft3_stage<T, N, E, DIR, 1, TW>(v0, v1, v2, t, lds0, lds1, lds2, LS, tw);
+}
+
 // Full FFT.  All threads of the workgroup must call this together (it
 // contains workgroup barriers whenever N > E).  tw is the twiddle source
 // zeta_N^j: a pointer to tw_N in global memory, or any type with the same

@@ -459,6 +459,61 @@ __device__ __forceinline__ void mirror(const C<T> (&P)[E], C<T> (&Pm)[E], int t,
     }
 }
 
+// mirror of two or three sequences through as many disjoint LDS buffers,
+// with one pair of barriers
+template <typename T, int NC, int E>
+__device__ __forceinline__ void mirror2(const C<T> (&A)[E], C<T> (&Am)[E], const C<T> (&B)[E], C<T> (&Bm)[E],
+                                        int t, C<T>* lds0, C<T>* lds1)
+{
+    constexpr int G = NC / E;
+    if constexpr (G == 1) {
+        mirror<T, NC, E>(A, Am, t, lds0);
+        mirror<T, NC, E>(B, Bm, t, lds1);
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            lds0[lpad(t + e * G)] = A[e];
+            lds1[lpad(t + e * G)] = B[e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int j = lpad((NC - (t + e * G)) & (NC - 1));
+            Am[e] = lds0[j];
+            Bm[e] = lds1[j];
+        }
+        __syncthreads();
+    }
+}
+template <typename T, int NC, int E>
+__device__ __forceinline__ void mirror3(const C<T> (&A)[E], C<T> (&Am)[E], const C<T> (&B)[E], C<T> (&Bm)[E],
+                                        const C<T> (&D)[E], C<T> (&Dm)[E], int t, C<T>* lds0, C<T>* lds1,
+                                        C<T>* lds2)
+{
+    constexpr int G = NC / E;
+    if constexpr (G == 1) {
+        mirror<T, NC, E>(A, Am, t, lds0);
+        mirror<T, NC, E>(B, Bm, t, lds1);
+        mirror<T, NC, E>(D, Dm, t, lds2);
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            lds0[lpad(t + e * G)] = A[e];
+            lds1[lpad(t + e * G)] = B[e];
+            lds2[lpad(t + e * G)] = D[e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int j = lpad((NC - (t + e * G)) & (NC - 1));
+            Am[e] = lds0[j];
+            Bm[e] = lds1[j];
+            Dm[e] = lds2[j];
+        }
+        __syncthreads();
+    }
+}
+
 // Spectrum V_k (k = 0..NC) of a real sequence v of length 2 NC from the
 // size-NC forward FFT P of its packing z_l = v_{2l} + i v_{2l+1}:
 // V_k = (P_k + conj P_{NC-k}) / 2 - i zeta_{2NC}^{-k} (P_k - conj P_{NC-k}) / 2.
@@ -518,10 +573,10 @@ __device__ __forceinline__ C<T> zeta3N(const C<T>* tw3N, int k)
 // values U_{NC-k} and U_{N-k} come from the thread holding NC - k through the
 // exchange buffer.  With w_{k,r} = zeta_{3N}^{rk} (U_k + zeta_3^{-r} conj U_{N-k}),
 // w_{0,r} = Re U_0 and the real w_{NC,r}, Z_{k,r} = c2r_pre(w_{k,r}, w_{NC-k,r}).
-template <typename T, int NC, int E>
+template <typename T, int NC, int E, bool PAIRED = false>
 __device__ __forceinline__ void herm_build3(const C<T>* U, int m, int t, C<T>* lds, const C<T>* tw3N,
                                             const C<T>* twN, C<T> (&z0)[E], C<T> (&z1)[E], C<T> (&z2)[E],
-                                            T dc = T(1))
+                                            T dc = T(1), C<T>* lds1 = nullptr)
 {
     constexpr int N = 2 * NC, G = NC / E;
     const T h3 = T(0.86602540378443864676), sq3 = T(1.73205080756887729353);
@@ -536,8 +591,13 @@ __device__ __forceinline__ void herm_build3(const C<T>* U, int m, int t, C<T>* l
         // U_0 scaled by dc (the adjoint's doubled mean; only its real part is read)
         if (t == 0) lo[0] = scale(lo[0], dc);
     }
-    mirror<T, NC, E>(lo, lom, t, lds);  // lom[e] = U_{(NC - k) mod NC}
-    mirror<T, NC, E>(hi, him, t, lds);  // him[e] = U_{NC + (NC - k) mod NC}
+    // lom[e] = U_{(NC - k) mod NC}, him[e] = U_{NC + (NC - k) mod NC}
+    if constexpr (PAIRED) {
+        mirror2<T, NC, E>(lo, lom, hi, him, t, lds, lds1);
+    } else {
+        mirror<T, NC, E>(lo, lom, t, lds);
+        mirror<T, NC, E>(hi, him, t, lds);
+    }
     const int z = opaque_zero();
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -582,30 +642,42 @@ k_conv1d_hermitian(RowArgs a)
 {
     constexpr int N = 2 * NC;
     constexpr int E = row_E<T, 1>(NC), G = NC / E, GPB = row_GPB<T, 1>(NC), LDSN = row_lds<T, 1>(NC);
-    __shared__ C<T> sh[GPB * LDSN];
+    // three exchange buffers per row (the three residues transformed
+    // together) where they fit in LDS
+    constexpr bool TRI = 3 * GPB * LDSN * int(sizeof(C<T>)) <= 160 * 1024;
+    __shared__ C<T> sh[(TRI ? 3 : 1) * GPB * LDSN];
     static_assert(sizeof(sh) <= 160 * 1024, "LDS footprint exceeds 160 KB");
     const int grp = threadIdx.x / G, t = threadIdx.x % G;
     const RowCtx c = row_ctx(a, (int64_t)blockIdx.x * GPB + grp);
     C<T>* lds = sh + grp * LDSN;
+    C<T>* lds1 = TRI ? sh + (GPB + grp) * LDSN : lds;
+    C<T>* lds2 = TRI ? sh + (2 * GPB + grp) * LDSN : lds;
     const C<T>* twb = (const C<T>*)a.tw;
     const C<T>* twNC = twb + tw_off(NC);
     const C<T>* twN = twb + tw_off(N);
     const C<T>* tw3N = (const C<T>*)a.tw3 + tw_off(N);
     const int m = c.m;
+    auto fft3x = [&](C<T> (&v0)[E], C<T> (&v1)[E], C<T> (&v2)[E], auto dir) {
+        constexpr int D = decltype(dir)::value;
+        if constexpr (TRI) {
+            fft3<T, NC, E, D>(v0, v1, v2, t, lds, lds1, lds2, 1, twNC);
+        } else {
+            fft<T, NC, E, D>(v0, t, lds, 1, twNC);
+            fft<T, NC, E, D>(v1, t, lds, 1, twNC);
+            fft<T, NC, E, D>(v2, t, lds, 1, twNC);
+        }
+    };
     C<T> P0[E], P1[E], P2[E];
     const int64_t nM = MD ? a.M : 1;
     for (int64_t i = 0; i < nM; ++i) {
         C<T> x0[E], x1[E], x2[E];
-        herm_build3<T, NC, E>((const C<T>*)a.f + c.of + i * a.f_i, m, t, lds, tw3N, twN, x0, x1, x2,
-                              (a.flags & kHermAdj) ? T(2) : T(1));
-        fft<T, NC, E, +1>(x0, t, lds, 1, twNC);
-        fft<T, NC, E, +1>(x1, t, lds, 1, twNC);
-        fft<T, NC, E, +1>(x2, t, lds, 1, twNC);
+        herm_build3<T, NC, E, TRI>((const C<T>*)a.f + c.of + i * a.f_i, m, t, lds, tw3N, twN, x0, x1, x2,
+                                   (a.flags & kHermAdj) ? T(2) : T(1), lds1);
+        fft3x(x0, x1, x2, std::integral_constant<int, +1>{});
         C<T> y0[E], y1[E], y2[E];
-        herm_build3<T, NC, E>((const C<T>*)a.g + c.og + i * a.g_i, m, t, lds, tw3N, twN, y0, y1, y2);
-        fft<T, NC, E, +1>(y0, t, lds, 1, twNC);
-        fft<T, NC, E, +1>(y1, t, lds, 1, twNC);
-        fft<T, NC, E, +1>(y2, t, lds, 1, twNC);
+        herm_build3<T, NC, E, TRI>((const C<T>*)a.g + c.og + i * a.g_i, m, t, lds, tw3N, twN, y0, y1, y2,
+                                   T(1), lds1);
+        fft3x(y0, y1, y2, std::integral_constant<int, +1>{});
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const C<T> p0{x0[e].re * y0[e].re, x0[e].im * y0[e].im};
@@ -616,17 +688,17 @@ k_conv1d_hermitian(RowArgs a)
             P2[e] = (MD && i > 0) ? P2[e] + p2 : p2;
         }
     }
-    fft<T, NC, E, -1>(P0, t, lds, 1, twNC);
-    fft<T, NC, E, -1>(P1, t, lds, 1, twNC);
-    fft<T, NC, E, -1>(P2, t, lds, 1, twNC);
+    fft3x(P0, P1, P2, std::integral_constant<int, -1>{});
     // recombination: V_r(k) from P_r(k), P_r(NC-k); H_k, H_{N-k}, H_NC
     C<T> olo[E], ohi[E], ocen = zero<T>();
     const T h3 = T(0.86602540378443864676);
+    C<T> Pm0[E], Pm1[E], Pm2[E];
+    if constexpr (TRI) mirror3<T, NC, E>(P0, Pm0, P1, Pm1, P2, Pm2, t, lds, lds1, lds2);
     static_for<3>([&](auto ri) {
         constexpr int R = decltype(ri)::value == 0 ? 0 : (decltype(ri)::value == 1 ? 1 : -1);
         C<T>(&P)[E] = R == 0 ? P0 : (R > 0 ? P1 : P2);
-        C<T> Pm[E];
-        mirror<T, NC, E>(P, Pm, t, lds);
+        C<T>(&Pm)[E] = R == 0 ? Pm0 : (R > 0 ? Pm1 : Pm2);
+        if constexpr (!TRI) mirror<T, NC, E>(P, Pm, t, lds);
         const C<T> z3 = R == 0 ? C<T>{T(1), T(0)} : (R > 0 ? C<T>{T(-0.5), -h3} : C<T>{T(-0.5), h3});
         const int zo = opaque_zero();
 #pragma unroll
