@@ -169,13 +169,14 @@ def wl_c3(args):
     run = lambda: ic.conv2d(F, G)
     expl = lambda: ic.conv2d(F, G, method="explicit")
     pruned = lambda: ic.conv2d(F, G, method="pruned")
+    comp = (lambda: ic.conv2d(F, G, flags=ic.COMPENSATED)) if cdt == torch.complex64 else None
     # algorithmic bytes per launch: every pass moves 3 S (Sec. 3.1 schedule)
     kbytes = {"colpass_pad_bwd": 3 * S, "k_conv1d_complex": 3 * S, "colpass_pad_fwd": 3 * S}
     # the row kernel convolves 2 m_x rows per pair (one launch per x residue)
     kflops = {"k_conv1d_complex": B * mx * flops_row_complex(my)}
     step_bytes = 15 * S
 
-    def cpu_baseline(h_gpu, h_expl=None):
+    def cpu_baseline(h_gpu, h_expl=None, h_comp=None):
         """Oracle at stratified sample points of every pair: the whole
         low-wavenumber block [0,L)^2 (where the energy of the (1+|k|^2)^-1
         spectra concentrates) plus uniform random points elsewhere.  The
@@ -191,7 +192,7 @@ def wl_c3(args):
         dt_np = np.complex64 if cdt == torch.complex64 else np.complex128
         macs = 0.0
         t_oracle = 0.0
-        res = {"implicit": [], "explicit": [], "uniform_random_points": []}
+        res = {"implicit": [], "explicit": [], "compensated": [], "uniform_random_points": []}
         for b in range(B):
             rp = rng.integers(0, mx, (4 * nrand, 2))
             rp = rp[(rp[:, 0] >= L) | (rp[:, 1] >= L)][:nrand]
@@ -204,7 +205,7 @@ def wl_c3(args):
             macs += float(np.sum((pts[:, 0] + 1.0) * (pts[:, 1] + 1.0)))
             r2 = np.abs(ref) ** 2
             wb = (mx * my - L * L) / len(rp)
-            for key, h in (("implicit", h_gpu), ("explicit", h_expl)):
+            for key, h in (("implicit", h_gpu), ("explicit", h_expl), ("compensated", h_comp)):
                 if h is None:
                     continue
                 e2 = np.abs(h[b][pts[:, 0], pts[:, 1]] - ref) ** 2
@@ -225,8 +226,8 @@ def wl_c3(args):
     cfg = {"workload": f"2D complex implicit dealiased convolution {mx}x{my}, batch {B} pairs per step, "
                        f"{'complex64' if cdt == torch.complex64 else 'complex128'}",
            "m": [mx, my], "batch": B, "M": 1, "dtype": args.dtype}
-    return dict(run=run, explicit=expl, pruned=pruned, convs=B, step_bytes=step_bytes, kbytes=kbytes,
-                kflops=kflops, cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy())
+    return dict(run=run, explicit=expl, pruned=pruned, compensated=comp, convs=B, step_bytes=step_bytes,
+                kbytes=kbytes, kflops=kflops, cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy())
 
 
 def wl_c2(args):
@@ -279,10 +280,11 @@ def wl_c1(args):
     cs = 8 if cdt == torch.complex64 else 16
     run = lambda: ic.conv1d_complex(F, G)
     expl = lambda: ic.conv1d_complex(F, G, method="explicit")
+    comp = (lambda: ic.conv1d_complex(F, G, flags=ic.COMPENSATED)) if cdt == torch.complex64 else None
     kbytes = {"k_conv1d_complex": 3 * B * m * cs}
     kflops = {"k_conv1d_complex": B * flops_row_complex(m)}
 
-    def cpu_baseline(h_gpu, h_expl=None):
+    def cpu_baseline(h_gpu, h_expl=None, h_comp=None):
         import oracle
         nb = min(B, args.cpu_rows or 8192)
         t0 = time.perf_counter()
@@ -290,7 +292,7 @@ def wl_c1(args):
                                     np.asarray(g[:nb].astype(np.complex64 if cdt == torch.complex64 else np.complex128), np.complex128)[:, None])
         dt = time.perf_counter() - t0
         err = {}
-        for key, h in (("implicit", h_gpu), ("explicit", h_expl)):
+        for key, h in (("implicit", h_gpu), ("explicit", h_expl), ("compensated", h_comp)):
             if h is not None:
                 e = [float(np.linalg.norm(h[i] - ref[i]) / np.linalg.norm(ref[i])) for i in range(nb)]
                 err[key] = {"max": max(e), "median": float(np.median(e)), "pairs": nb}
@@ -300,8 +302,8 @@ def wl_c1(args):
     cfg = {"workload": f"1D complex implicit dealiased convolution m={m}, batch {B}, "
                        f"{'complex64' if cdt == torch.complex64 else 'complex128'}", "m": m, "batch": B,
            "dtype": args.dtype}
-    return dict(run=run, explicit=expl, convs=B, step_bytes=3 * B * m * cs, kbytes=kbytes, kflops=kflops,
-                cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy())
+    return dict(run=run, explicit=expl, compensated=comp, convs=B, step_bytes=3 * B * m * cs, kbytes=kbytes,
+                kflops=kflops, cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy())
 
 
 def wl_c4(args):
@@ -709,6 +711,12 @@ def main():
                                   "unit": "convs/s"}
         out["speedup_vs_pruned"] = round(ms_p / ms_clean, 3)
 
+    if W.get("compensated") is not None and not args.no_explicit:
+        ms_c = timed(W["compensated"], max(3, args.steps // 2), 1)
+        out["compensated"] = {"ms_per_step": round(ms_c, 5), "value": round(W["convs"] * 1000.0 / ms_c, 2),
+                              "unit": "convs/s", "note": "IMPCONV_COMPENSATED: twiddle products from FP32 "
+                              "high and low parts; errors under rel_err_vs_oracle.compensated"}
+
     if args.profile_copy:
         n = args.profile_copy * (1 << 20) // 4
         x = torch.empty(n, dtype=torch.float32, device="cuda")
@@ -721,7 +729,10 @@ def main():
     if not args.no_cpu:
         h = W["out"]()
         if W.get("explicit") is not None and not args.no_explicit:
-            cpu, err = W["cpu"](h, W["explicit"]().cpu().numpy())
+            extra = {}
+            if W.get("compensated") is not None:
+                extra["h_comp"] = W["compensated"]().cpu().numpy()
+            cpu, err = W["cpu"](h, W["explicit"]().cpu().numpy(), **extra)
         else:
             cpu, err = W["cpu"](h)
         out["cpu_baseline"] = {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in cpu.items()}

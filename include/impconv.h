@@ -75,6 +75,7 @@ typedef enum impconv_kind {
 #define IMPCONV_NO_SYMMETRIZE (1u << 4)   /* Hermitian nD: trust the k_last = 0 plane (see conv2d) */
 #define IMPCONV_HERMITIAN_ADJOINT (1u << 5) /* Hermitian 1D/nD: vector-Jacobian product edits (see below) */
 #define IMPCONV_EXPLICIT_PRUNED (1u << 6) /* with EXPLICIT_PADDED (2D): skip all-zero transforms, fuse padding */
+#define IMPCONV_COMPENSATED (1u << 7)     /* complex64 complex convolutions: compensated twiddle products */
 
 /* Version as 10000*major + 100*minor + patch. */
 int impconv_version(void);
@@ -108,7 +109,13 @@ impconv_status impconv_conv1d_workspace(int kind, int dtype, int64_t batch, int6
  * method (inputs copied zero-padded to 2N in work, size-2N cyclic FFT
  * convolution, output cropped); REV/CONJ flags are not accepted with it.
  * The implicit method takes the general p/q rule of Sec. 2.4 where it needs
- * clearly fewer transforms (see impconv_conv1d_complex_pq). */
+ * clearly fewer transforms (see impconv_conv1d_complex_pq).
+ * IMPCONV_COMPENSATED (implicit method, m <= 8192): in complex64 every
+ * product by a root of unity -- residue shifts, FFT stage twiddles,
+ * recombination -- is formed from the FP32 rounding h of the FP64 value and
+ * the FP32 rounding l of the remainder, a h + a l, which removes the
+ * twiddles' own representation error (at about twice the cost of each
+ * twiddle product); the 1/2 rule is used.  No effect in complex128. */
 impconv_status impconv_conv1d_complex(int dtype, int64_t batch, int64_t M, int64_t m,
                                       const void* f, const void* g, void* h, void* work,
                                       size_t work_bytes, uint32_t flags, void* stream);
@@ -208,6 +215,9 @@ size_t impconv_timing_report(char* buf, size_t cap);
  * hyperplane by zero for the entries the symmetrization overwrites and the
  * origin halved and real.  The flag makes the first outer pass load f as
  * Gamma and the last outer pass apply the edits; pass gh as f.
+ * IMPCONV_COMPLEX also accepts IMPCONV_COMPENSATED (implicit method; as in
+ * 1D: compensated twiddle products in the complex64 column passes and rows;
+ * the column passes then run one workgroup per tile).
  * IMPCONV_EXPLICIT_PADDED (2D complex only): the conventional comparator --
  * inputs copied into zero-padded 2N0 x 2N1 work arrays, full-size FFTs along
  * both axes, product, inverse, crop (m[d] <= 2048).  With

@@ -34,6 +34,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libimpconv.so")
 
 EXPLICIT_PADDED, REV_F, CONJ_G, REV_OUT, NO_SYMMETRIZE, HERMITIAN_ADJOINT, EXPLICIT_PRUNED = 1, 2, 4, 8, 16, 32, 64
+COMPENSATED = 128  # complex64: compensated twiddle products (complex convolutions)
 COMPLEX, HERMITIAN, TERNARY = 0, 1, 2
 C64, C128 = 0, 1
 
@@ -296,12 +297,13 @@ def _convnd(nd: int, f, g, kind: str, m, flags: int):
     return h.view(*n) if len(lead) == 0 else h
 
 
-def conv2d(f, g, kind: str = "complex", m=None, symmetrize: bool = True, method: str = "implicit"):
+def conv2d(f, g, kind: str = "complex", m=None, symmetrize: bool = True, method: str = "implicit",
+           flags: int = 0):
     """2D convolution (Secs. 3.1 / 3.2); inputs (n0, n1), (B, n0, n1) or
     (B, M, n0, n1); Hermitian needs m = (m0, m1).  method="explicit" runs the
     explicitly zero-padded comparator, "pruned" its pruned form (complex
-    only)."""
-    flags = 0 if symmetrize else NO_SYMMETRIZE
+    only); flags adds ABI flags (e.g. COMPENSATED)."""
+    flags |= 0 if symmetrize else NO_SYMMETRIZE
     flags |= {"implicit": 0, "explicit": EXPLICIT_PADDED, "pruned": EXPLICIT_PADDED | EXPLICIT_PRUNED}[method]
     return _convnd(2, f, g, kind, m, flags)
 
@@ -332,9 +334,9 @@ def conv2d_ternary(f, g, e, m, symmetrize: bool = True, method: str = "implicit"
     return h.view(*n) if f.dim() == 2 else h
 
 
-def conv3d(f, g, kind: str = "complex", m=None, symmetrize: bool = True):
+def conv3d(f, g, kind: str = "complex", m=None, symmetrize: bool = True, flags: int = 0):
     """3D convolution (Sec. 3.4); inputs (n0, n1, n2), (B, ...) or (B, M, ...)."""
-    return _convnd(3, f, g, kind, m, 0 if symmetrize else NO_SYMMETRIZE)
+    return _convnd(3, f, g, kind, m, flags | (0 if symmetrize else NO_SYMMETRIZE))
 
 
 def timing_enable(on: bool = True) -> None:

@@ -128,8 +128,10 @@ impconv_status plan1d(int kind, int dt, int64_t batch, int64_t M, int64_t m, uin
     if (batch < 0) return fail(IMPCONV_E_SIZE, "batch must be >= 0");
     if (M < 1) return fail(IMPCONV_E_SIZE, "M must be >= 1");
     const uint32_t known = IMPCONV_EXPLICIT_PADDED | IMPCONV_REV_F | IMPCONV_CONJ_G | IMPCONV_REV_OUT |
-                           IMPCONV_HERMITIAN_ADJOINT;
+                           IMPCONV_HERMITIAN_ADJOINT | IMPCONV_COMPENSATED;
     if (flags & ~known) return fail(IMPCONV_E_ARG, "unknown flag bits for a 1D convolution");
+    if ((flags & IMPCONV_COMPENSATED) && (kind != IMPCONV_COMPLEX || (flags & IMPCONV_EXPLICIT_PADDED)))
+        return fail(IMPCONV_E_ARG, "COMPENSATED applies to the implicit complex convolution");
     const bool adj = flags & (IMPCONV_REV_F | IMPCONV_CONJ_G | IMPCONV_REV_OUT | IMPCONV_HERMITIAN_ADJOINT);
     if ((flags & (IMPCONV_REV_F | IMPCONV_CONJ_G | IMPCONV_REV_OUT)) && kind != IMPCONV_COMPLEX)
         return fail(IMPCONV_E_ARG, "REV/CONJ flags apply to complex convolutions only");
@@ -141,6 +143,12 @@ impconv_status plan1d(int kind, int dt, int64_t batch, int64_t M, int64_t m, uin
     if (kind == IMPCONV_COMPLEX) {
         p->N = next_pow2(m);
         if (!p->explicit_) {
+            if (flags & IMPCONV_COMPENSATED) {
+                // compensated products: the 1/2-rule row kernel only
+                if (np_req > 0 && np_req != p->N) return fail(IMPCONV_E_ARG, "COMPENSATED takes the 1/2 rule");
+                if (p->N > kRowMax) return fail(IMPCONV_E_UNSUPPORTED, "COMPENSATED supports m <= 8192");
+                return IMPCONV_OK;
+            }
             if (np_req < 0) np_req = pq_auto(dt, m);
             if (np_req > 0) {
                 if (np_req >= m && np_req <= kRowMax && (np_req & (np_req - 1)) == 0) {
@@ -203,6 +211,7 @@ RowArgs row_args(const DevTables* tb, int dt)
     std::memset(&a, 0, sizeof(a));
     a.tw = tb->tw[dt];
     a.tw3 = tb->tw3[dt];
+    a.twlo = tb->twlo;
     return a;
 }
 
@@ -277,7 +286,7 @@ static impconv_status run1d(int kind, int dtype, int64_t batch, int64_t M, int64
     a.nrows = batch;
     a.m = m;
     a.M = M;
-    a.flags = flags & (kRevF | kConjG | kRevOut | kHermAdj);
+    a.flags = flags & (kRevF | kConjG | kRevOut | kHermAdj | kComp);
     if (!p.explicit_) {
         a.f = f; a.g = g; a.e = e; a.h = h;
         if (kind == IMPCONV_TERNARY) {

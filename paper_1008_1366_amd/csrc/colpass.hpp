@@ -77,11 +77,14 @@ struct ColArgs {
     uint32_t fsflags;              // 1 = reverse within m (input of kFsBwd / kPadBwd, output of kFsFwd /
                                    // kPadFwd), 2 = conjugate the input (kFsBwd / kPadBwd), 4 = Hermitian
                                    // adjoint on the k_last = 0 hyperplane (kCenBwd: load U_k + conj U_{-k};
-                                   // kCenFwd: zero the overwritten half, DC halved and real; needs sym)
+                                   // kCenFwd: zero the overwritten half, DC halved and real; needs sym),
+                                   // 8 = compensated twiddle products (complex64 kPadBwd / kPadFwd,
+                                   // selects the COMP instantiation)
     double scale;
     const void* tw;
     const void* tw3;
     int ncu;                       // compute units of the device (persistent grids)
+    const void* twlo;              // complex64 low parts of tw (fsflags 8: compensated products)
 };
 
 // Elements per thread of a column pass.  The centered passes keep three
@@ -132,7 +135,7 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t nblocks)
     return lg < nblocks ? lg : -1;
 }
 
-template <typename T, int N, int MODE, int DIR>
+template <typename T, int N, int MODE, int DIR, bool COMP = false>
 __global__ void __launch_bounds__((col_block<T, MODE>(N)))
 k_colpass(ColArgs a)
 {
@@ -156,8 +159,14 @@ k_colpass(ColArgs a)
     }
     C<T>* lds = sh + col;
     const C<T>* twb = (const C<T>*)a.tw;
-    const C<T>* twN = twb + tw_off(N);
-    const C<T>* tw2N = twb + tw_off(2 * N);
+    // twiddle sources: plain tables, or (COMP) the high/low pairs
+    using TWT = std::conditional_t<COMP, CompTw<T>, const C<T>*>;
+    auto twsrc = [&](int64_t off) -> TWT {
+        if constexpr (COMP) return CompTw<T>{twb + off, (const C<T>*)a.twlo + off};
+        else return twb + off;
+    };
+    const TWT twN = twsrc(tw_off(N));
+    const TWT tw2N = twsrc(tw_off(2 * N));
     const C<T>* tw3N = (const C<T>*)a.tw3 + tw_off(N);
     const int64_t ib = s1 * a.in_bs + s2 * a.in_bs2 + cc, ob = s1 * a.out_bs + s2 * a.out_bs2 + cc;
     auto ldrow = [&](int q, int row, int nrows) -> C<T> {  // in[q] at (row, c), zero outside
@@ -188,7 +197,7 @@ k_colpass(ColArgs a)
         for (int e = 0; e < E; ++e) strow(0, t + e * G, y[e]);
         const int z = opaque_zero();
 #pragma unroll
-        for (int e = 0; e < E; ++e) x[e] = x[e] * tw2N[t + e * G + z];
+        for (int e = 0; e < E; ++e) x[e] = mulw<+1>(x[e], tw2N[t + e * G + z]);
         fft<T, N, E, +1>(x, t, lds, TC, twN);
 #pragma unroll
         for (int e = 0; e < E; ++e) strow(1, t + e * G, x[e]);
@@ -208,7 +217,7 @@ k_colpass(ColArgs a)
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = t + e * G;
-            if (k < a.m) strow(0, rev ? a.m - 1 - k : k, scale(x[e] + mulc(y[e], tw2N[k]), s));
+            if (k < a.m) strow(0, rev ? a.m - 1 - k : k, scale(x[e] + mulw<-1>(y[e], tw2N[k]), s));
         }
     } else if constexpr (MODE == kCenBwd) {
         // U_k and U_{k-N} of this thread's frequencies, with the optional

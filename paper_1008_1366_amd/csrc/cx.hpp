@@ -41,4 +41,35 @@ template <int DIR, typename T> __host__ __device__ __forceinline__ C<T> mulw(C<T
     else return mulc(a, w);
 }
 
+// Compensated root of unity: w = h + l with h the rounding of the FP64 value
+// to T and l the rounding of the remainder.  a * w is formed as a h + a l
+// with the small product added first, so the representation error of the
+// twiddle (about 2^-24 |w| in FP32) drops to second order.
+template <typename T>
+struct TwHL {
+    C<T> h, l;
+};
+template <typename T> __host__ __device__ __forceinline__ T fmat(T a, T b, T c)
+{
+    if constexpr (sizeof(T) == 4) return __builtin_fmaf(a, b, c);
+    else return __builtin_fma(a, b, c);
+}
+template <int DIR, typename T> __host__ __device__ __forceinline__ C<T> mulw(C<T> a, TwHL<T> w)
+{
+    const C<T> s = mulw<DIR>(a, w.l);
+    if constexpr (DIR > 0)
+        return {fmat(a.re, w.h.re, fmat(-a.im, w.h.im, s.re)), fmat(a.re, w.h.im, fmat(a.im, w.h.re, s.im))};
+    else
+        return {fmat(a.re, w.h.re, fmat(a.im, w.h.im, s.re)), fmat(a.im, w.h.re, fmat(-a.re, w.h.im, s.im))};
+}
+// Twiddle source over a pair of tables (high and low parts, same indexing):
+// usable wherever the FFT takes a twiddle pointer.
+template <typename T>
+struct CompTw {
+    const C<T>* h;
+    const C<T>* l;
+    __host__ __device__ __forceinline__ CompTw operator+(int64_t z) const { return CompTw{h + z, l + z}; }
+    __host__ __device__ __forceinline__ TwHL<T> operator[](int64_t j) const { return TwHL<T>{h[j], l[j]}; }
+};
+
 }  // namespace impconv

@@ -209,7 +209,7 @@ __device__ __forceinline__ void fft2_stage(C<T> (&v0)[E], C<T> (&v1)[E], int t, 
             const int ks = k * (N / (NS * R));
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                const C<T> w = tws[r * ks];
+                const auto w = tws[r * ks];
                 u0[r] = mulw<DIR>(u0[r], w);
                 u1[r] = mulw<DIR>(u1[r], w);
             }
@@ -281,7 +281,7 @@ __device__ __forceinline__ void fft3_stage(C<T> (&v0)[E], C<T> (&v1)[E], C<T> (&
             const int ks = k * (N / (NS * R));
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                const C<T> w = tws[r * ks];
+                const auto w = tws[r * ks];
                 u0[r] = mulw<DIR>(u0[r], w);
                 u1[r] = mulw<DIR>(u1[r], w);
                 u2[r] = mulw<DIR>(u2[r], w);

@@ -38,6 +38,7 @@ static hipError_t go(const ColArgs& a, hipStream_t s)
 
 hipError_t launch_col_pad(int dt, int N, int mode, const ColArgs& a, hipStream_t s)
 {
+    if (dt == 0 && (a.fsflags & 8)) return launch_col_pad_comp(N, mode, a, s);
     switch (N) {
 #define X(n) case n: return mode == kPadBwd ? (dt ? go<double, n, kPadBwd>(a, s) : go<float, n, kPadBwd>(a, s)) \
                                         : (dt ? go<double, n, kPadFwd>(a, s) : go<float, n, kPadFwd>(a, s));

@@ -37,6 +37,7 @@ static hipError_t go_cyclic(const RowArgs& a, hipStream_t s)
 
 hipError_t launch_row_complex(int dt, int N, const RowArgs& a, hipStream_t s)
 {
+    if (dt == 0 && (a.flags & kComp)) return launch_row_complex_comp(N, a, s);
     switch (N) {
 #define X(n) case n: return dt ? go_complex<double, n>(a, s) : go_complex<float, n>(a, s);
         IMPCONV_POW2_CASES(X)

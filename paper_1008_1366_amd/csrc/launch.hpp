@@ -14,6 +14,8 @@ constexpr int kRowMax = 8192;
 // dt: 0 = complex64, 1 = complex128.  N / NC / NN: FFT size (power of two).
 hipError_t launch_row_complex(int dt, int N, const RowArgs& a, hipStream_t s);
 hipError_t launch_row_cyclic(int dt, int N, const RowArgs& a, hipStream_t s);
+// complex64 with compensated twiddle products (a.flags & kComp, a.twlo set)
+hipError_t launch_row_complex_comp(int N, const RowArgs& a, hipStream_t s);
 hipError_t launch_row_hermitian(int dt, int NC, const RowArgs& a, hipStream_t s);
 hipError_t launch_row_ternary(int dt, int NN, const RowArgs& a, hipStream_t s);
 hipError_t launch_row_realcyclic(int dt, int NC, const RowArgs& a, hipStream_t s);
@@ -37,6 +39,8 @@ constexpr int kColMax = 4096;
 struct ColArgs;
 hipError_t launch_col(int dt, int N, int mode, int dir, const ColArgs& a, hipStream_t s);
 hipError_t launch_col_pad(int dt, int N, int mode, const ColArgs& a, hipStream_t s);
+// complex64 kPadBwd / kPadFwd with compensated twiddle products (a.twlo set)
+hipError_t launch_col_pad_comp(int N, int mode, const ColArgs& a, hipStream_t s);
 hipError_t launch_col_cen(int dt, int N, int mode, const ColArgs& a, hipStream_t s);
 hipError_t launch_col_ter(int dt, int N, int mode, const ColArgs& a, hipStream_t s);
 hipError_t launch_col_fft(int dt, int N, int dir, const ColArgs& a, hipStream_t s);

@@ -33,6 +33,7 @@ ColArgs col_args(const DevTables& tb, int dt)
     a.nsub = 1;
     a.tw = tb.tw[dt];
     a.tw3 = tb.tw3[dt];
+    a.twlo = tb.twlo;
     a.ncu = tb.ncu;
     a.scale = 1.0;
     return a;
@@ -44,6 +45,7 @@ RowArgs row_args(const DevTables& tb, int dt)
     std::memset(&a, 0, sizeof(a));
     a.tw = tb.tw[dt];
     a.tw3 = tb.tw3[dt];
+    a.twlo = tb.twlo;
     a.scale = 1.0;
     return a;
 }
@@ -195,8 +197,10 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
     if (batch < 0 || M < 1) return fail(IMPCONV_E_SIZE, "batch must be >= 0 and M >= 1");
     const uint32_t adj = IMPCONV_REV_F | IMPCONV_CONJ_G | IMPCONV_REV_OUT;
     const uint32_t known = IMPCONV_NO_SYMMETRIZE | IMPCONV_EXPLICIT_PADDED | IMPCONV_EXPLICIT_PRUNED | adj |
-                           IMPCONV_HERMITIAN_ADJOINT;
+                           IMPCONV_HERMITIAN_ADJOINT | IMPCONV_COMPENSATED;
     if (flags & ~known) return fail(IMPCONV_E_ARG, "unsupported flag for an nD convolution");
+    if ((flags & IMPCONV_COMPENSATED) && (kind != IMPCONV_COMPLEX || (flags & IMPCONV_EXPLICIT_PADDED)))
+        return fail(IMPCONV_E_ARG, "COMPENSATED applies to implicit complex nD convolutions");
     if ((flags & IMPCONV_HERMITIAN_ADJOINT) &&
         (kind != IMPCONV_HERMITIAN || (flags & (IMPCONV_EXPLICIT_PADDED | IMPCONV_NO_SYMMETRIZE))))
         return fail(IMPCONV_E_ARG, "HERMITIAN_ADJOINT applies to implicit, symmetrized Hermitian nD convolutions");
@@ -648,10 +652,14 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
     // each outer axis and the row loads), g conjugated once (in the x pass),
     // the output reversed along every axis (row stores and the forward
     // passes of the outer axes)
-    const uint32_t fs_f = (flags & IMPCONV_REV_F) ? 1u : 0u;
-    const uint32_t fs_g = (flags & IMPCONV_CONJ_G) ? 2u : 0u;
-    const uint32_t fs_o = (flags & IMPCONV_REV_OUT) ? 1u : 0u;
-    const uint32_t rowfl = ((flags & IMPCONV_REV_F) ? kRevF : 0u) | ((flags & IMPCONV_REV_OUT) ? kRevOut : 0u);
+    // compensated twiddle products (complex): bit 8 of every column pass,
+    // kComp in the rows
+    const uint32_t cb = (flags & IMPCONV_COMPENSATED) ? 8u : 0u;
+    const uint32_t fs_f = ((flags & IMPCONV_REV_F) ? 1u : 0u) | cb;
+    const uint32_t fs_g = ((flags & IMPCONV_CONJ_G) ? 2u : 0u) | cb;
+    const uint32_t fs_o = ((flags & IMPCONV_REV_OUT) ? 1u : 0u) | cb;
+    const uint32_t rowfl = ((flags & IMPCONV_REV_F) ? kRevF : 0u) | ((flags & IMPCONV_REV_OUT) ? kRevOut : 0u) |
+                           ((flags & IMPCONV_COMPENSATED) ? kComp : 0u);
     // adjoint form (Hermitian): the k_last = 0 hyperplane of f enters as
     // f_k + conj f_{-k} in the first outer pass, and the last outer pass
     // edits that hyperplane of the output; the inner passes are unchanged
@@ -731,7 +739,7 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
             return IMPCONV_OK;
         };
         if ((st = ypass(Xf[rx], Yf, fs_f))) return st;
-        if ((st = ypass(Xg[rx], Yg, 0))) return st;
+        if ((st = ypass(Xg[rx], Yg, cb))) return st;
         for (int ry = 0; ry < R; ++ry)
             if ((st = inner_rows(tb, p, Yf[ry], Yg[ry], nplanes * N1, s, rowfl))) return st;
         // y forward: [plane][y'][M][n2] (3 residues) -> Q[rx] [plane][n1][n2]

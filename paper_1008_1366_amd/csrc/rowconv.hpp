@@ -19,6 +19,7 @@ enum : uint32_t {
     kConjG = 1u << 2,   // read g conjugated
     kRevOut = 1u << 3,  // write h reversed within its logical length
     kHermAdj = 1u << 5, // Hermitian adjoint: f_0 read as 2 Re f_0, h_0 stored halved (real)
+    kComp = 1u << 7,    // complex64: compensated twiddle products (tables tw + twlo)
 };
 
 struct RowArgs {
@@ -39,6 +40,7 @@ struct RowArgs {
     const void* tw3;         // concatenated zeta_{3N}^j tables (j < N)
     int64_t h_pad;           // Hermitian rows: stored output length; entries m..h_pad-1 are zeroed
     const void* twq;         // general p/q rule: zeta_{q NP}^j, j < q NP
+    const void* twlo;        // complex64 low parts of the tw tables (compensated products)
     int q;                   // general p/q rule: residues
 };
 
@@ -98,6 +100,17 @@ struct RowCtx {
     bool act;
 };
 
+// Twiddle source of the tw tables at offset off: a plain pointer, or with
+// COMP the (high, low) pair of tables for compensated products.
+template <typename T, bool COMP>
+using TwSrc = std::conditional_t<COMP, CompTw<T>, const C<T>*>;
+template <typename T, bool COMP>
+__device__ __forceinline__ TwSrc<T, COMP> tw_src(const RowArgs& a, int64_t off)
+{
+    if constexpr (COMP) return CompTw<T>{(const C<T>*)a.tw + off, (const C<T>*)a.twlo + off};
+    else return (const C<T>*)a.tw + off;
+}
+
 // Rows past nrows (the idle groups of the last block) read row 0 with
 // length 0, so every load below stays in bounds and yields zero.
 __device__ __forceinline__ RowCtx row_ctx(const RowArgs& a, int64_t row)
@@ -138,14 +151,13 @@ __device__ __forceinline__ C<T> ldz(const C<T>* U, int j, int m)
 // are formed from the same registers (x0 = f, x1 = zeta_{2N}^k f, likewise
 // g) and transformed together, through two exchange buffers (fft2, DUAL) or
 // one after the other through one.
-template <typename T, int N, bool DUAL>
+template <typename T, int N, bool DUAL, bool COMP>
 __device__ __forceinline__ void conv_complex_row(const RowArgs& a, const RowCtx& c, int t, C<T>* lds,
                                                  C<T>* lds1)
 {
     constexpr int E = fft_E<T>(N), G = N / E;
-    const C<T>* twb = (const C<T>*)a.tw;
-    const C<T>* twN = twb + tw_off(N);
-    const C<T>* tw2N = twb + tw_off(2 * N);
+    const TwSrc<T, COMP> twN = tw_src<T, COMP>(a, tw_off(N));
+    const TwSrc<T, COMP> tw2N = tw_src<T, COMP>(a, tw_off(2 * N));
     const C<T>* F = (const C<T>*)a.f + c.of;
     const C<T>* Gp = (const C<T>*)a.g + c.og;
     C<T>* H = (C<T>*)a.h + c.oh;
@@ -167,7 +179,7 @@ __device__ __forceinline__ void conv_complex_row(const RowArgs& a, const RowCtx&
         for (int e = 0; e < E; ++e) {
             const int k = t + e * G;
             x0[e] = ldz(F + z, revf ? c.m - 1 - k : k, c.m);
-            x1[e] = x0[e] * tw2N[k + z];
+            x1[e] = mulw<+1>(x0[e], tw2N[k + z]);
         }
     }
     pair(x0, x1, std::integral_constant<int, +1>{});
@@ -181,7 +193,7 @@ __device__ __forceinline__ void conv_complex_row(const RowArgs& a, const RowCtx&
         }
         C<T> y1[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) y1[e] = y[e] * tw2N[t + e * G + z];
+        for (int e = 0; e < E; ++e) y1[e] = mulw<+1>(y[e], tw2N[t + e * G + z]);
         pair(y, y1, std::integral_constant<int, +1>{});
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -194,11 +206,11 @@ __device__ __forceinline__ void conv_complex_row(const RowArgs& a, const RowCtx&
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = t + e * G;
-        if (k < c.m) H[revo ? c.m - 1 - k : k] = scale(x0[e] + mulc(x1[e], tw2N[k + z]), s);
+        if (k < c.m) H[revo ? c.m - 1 - k : k] = scale(x0[e] + mulw<-1>(x1[e], tw2N[k + z]), s);
     }
 }
 
-template <typename T, int N, bool ACCG, bool MD>
+template <typename T, int N, bool ACCG, bool MD, bool COMP = false>
 __global__ void __launch_bounds__(row_block<T>(N), row_waves<T>(N))
 k_conv1d_complex(RowArgs a)
 {
@@ -212,13 +224,12 @@ k_conv1d_complex(RowArgs a)
     C<T>* lds = sh + grp * LDSN;
 
     if constexpr (!MD) {
-        conv_complex_row<T, N, DUAL>(a, c, t, lds, DUAL ? sh + (GPB + grp) * LDSN : lds);
+        conv_complex_row<T, N, DUAL, COMP>(a, c, t, lds, DUAL ? sh + (GPB + grp) * LDSN : lds);
         return;
     }
 
-    const C<T>* twb = (const C<T>*)a.tw;
-    const C<T>* twN = twb + tw_off(N);
-    const C<T>* tw2N = twb + tw_off(2 * N);
+    const TwSrc<T, COMP> twN = tw_src<T, COMP>(a, tw_off(N));
+    const TwSrc<T, COMP> tw2N = tw_src<T, COMP>(a, tw_off(2 * N));
     const C<T>* F = (const C<T>*)a.f + c.of;
     const C<T>* Gp = (const C<T>*)a.g + c.og;
     C<T>* H = (C<T>*)a.h + c.oh;
@@ -234,7 +245,7 @@ k_conv1d_complex(RowArgs a)
             const int z = opaque_zero();
             const C<T>* Fz = F + z;
             const C<T>* Gz = Gp + z;
-            const C<T>* Wz = tw2N + z;
+            const TwSrc<T, COMP> Wz = tw2N + z;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const int k = t + e * G;
@@ -242,9 +253,9 @@ k_conv1d_complex(RowArgs a)
                 C<T> gv = ldz(Gz + i * a.g_i, k, c.m);
                 if (cjg) gv = conj(gv);
                 if (r) {
-                    const C<T> w = Wz[k];
-                    fv = fv * w;
-                    gv = gv * w;
+                    const auto w = Wz[k];
+                    fv = mulw<+1>(fv, w);
+                    gv = mulw<+1>(gv, w);
                 }
                 x[e] = fv;
                 y[e] = gv;
@@ -255,11 +266,11 @@ k_conv1d_complex(RowArgs a)
             for (int e = 0; e < E; ++e) P[e] = i > 0 ? P[e] + x[e] * y[e] : x[e] * y[e];
         }
         fft<T, N, E, -1>(P, t, lds, 1, twN);
-        const C<T>* Wo = tw2N + opaque_zero();
+        const TwSrc<T, COMP> Wo = tw2N + opaque_zero();
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = t + e * G;
-            const C<T> v = r ? mulc(P[e], Wo[k]) : P[e];
+            const C<T> v = r ? mulw<-1>(P[e], Wo[k]) : P[e];
             if constexpr (ACCG) {
                 if (k < c.m) {
                     C<T>* hp = H + (revo ? c.m - 1 - k : k);

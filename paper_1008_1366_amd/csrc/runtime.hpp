@@ -25,6 +25,8 @@ struct DevTables {
     const void* tw[2];   // [0] complex64, [1] complex128: concatenated zeta_N^j, offset N - 1
     const void* tw3[2];  // concatenated zeta_{3N}^j (j < N), offset N - 1
     const void* twq[2];  // concatenated zeta_{q NP}^j (j < q NP), offset twq_off(q, NP)
+    const void* twlo;    // complex64 low parts of tw: the FP64 value minus its FP32 rounding, rounded
+    const void* tw3lo;   // complex64 low parts of tw3
     int ncu;             // compute units
 };
 

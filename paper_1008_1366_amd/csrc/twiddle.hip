@@ -7,7 +7,8 @@
 // 2/3-rule shifts, and zeta_{q NP}^j, j < q NP, for the general p/q rule.
 // Each value is computed in long double with the argument reduced exactly
 // (integer j mod denom, folded into the first octant) and rounded once to
-// double; the complex64 tables round those doubles to float.
+// double; the complex64 tables round those doubles to float, and for the
+// compensated products a second complex64 table holds the rounded remainder.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -73,6 +74,15 @@ std::mutex g_mu;
 DevTables g_tab[64];
 bool g_have[64];
 
+// Low parts of a table for the compensated complex64 products:
+// lo = float(w - double(float(w))) per component.
+std::vector<double> low_parts(const std::vector<double>& src)
+{
+    std::vector<double> lo(src.size());
+    for (size_t i = 0; i < src.size(); ++i) lo[i] = (double)(float)(src[i] - (double)(float)src[i]);
+    return lo;
+}
+
 template <typename T>
 hipError_t upload(const std::vector<double>& src, const void** dst)
 {
@@ -130,7 +140,9 @@ const DevTables* tables()
         (e = upload<float>(tw3, &t.tw3[0])) != hipSuccess ||
         (e = upload<double>(tw3, &t.tw3[1])) != hipSuccess ||
         (e = upload<float>(twq, &t.twq[0])) != hipSuccess ||
-        (e = upload<double>(twq, &t.twq[1])) != hipSuccess) {
+        (e = upload<double>(twq, &t.twq[1])) != hipSuccess ||
+        (e = upload<float>(low_parts(tw), &t.twlo)) != hipSuccess ||
+        (e = upload<float>(low_parts(tw3), &t.tw3lo)) != hipSuccess) {
         hip_fail(e, "twiddle table upload");
         return nullptr;
     }

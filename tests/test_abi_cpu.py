@@ -141,7 +141,7 @@ def test_plan_create_validation(L):
     assert create(kind=2, ndim=2, m=(2048, 4, 0), n=(4096, 5, 0), flags=1) == 5  # explicit: m0 <= 1024
     assert create(kind=1, ndim=2, m=(4, 4, 0), n=(9, 5, 0)) == 2  # centered axis needs 2m-1 or 2m
     assert create(kind=0, ndim=2, m=(4, 4, 0), n=(4, 5, 0)) == 2  # complex storage n == m
-    assert create(flags=1 << 7) == 1
+    assert create(flags=1 << 8) == 1
     assert create(kind=0, ndim=2, m=(4, 4, 0), n=(4, 4, 0), flags=1 << 6) == 1  # PRUNED needs EXPLICIT
     n = ctypes.c_size_t()
     assert L.impconv_workspace_bytes(None, ctypes.byref(n)) == 1
@@ -174,3 +174,19 @@ def test_pq_rule_and_validation(L):
     assert fn(1, 1, 1, 5000, 4096, None, None, None, None, 0, 0, None) == 2   # complex128: 2048 at most
     assert fn(0, 1, 1, 1000, 512, None, None, None, None, 0, 0, None) == 1    # valid rule, null pointers
     assert fn(0, 1, 1, 1000, 512, None, None, None, None, 0, 1, None) == 1    # EXPLICIT_PADDED
+
+
+def test_compensated_flag_validation(L):
+    """IMPCONV_COMPENSATED: implicit complex convolutions only, the 1/2 rule,
+    m <= 8192 in 1D (host checks, before any device work)."""
+    out = ctypes.c_size_t()
+    C = 1 << 7
+    assert L.impconv_conv1d_workspace(0, 0, 4, 1, 3000, C, ctypes.byref(out)) == 0
+    assert L.impconv_conv1d_workspace(1, 0, 4, 1, 3000, C, ctypes.byref(out)) == 1      # Hermitian
+    assert L.impconv_conv1d_workspace(0, 0, 4, 1, 3000, C | 1, ctypes.byref(out)) == 1  # explicit
+    assert L.impconv_conv1d_workspace(0, 0, 4, 1, 9000, C, ctypes.byref(out)) == 5      # beyond one row pass
+    m2 = (ctypes.c_int64 * 2)(64, 64)
+    assert L.impconv_convnd_workspace(0, 0, 2, m2, m2, 2, 1, C, ctypes.byref(out)) == 0
+    assert L.impconv_convnd_workspace(0, 0, 2, m2, m2, 2, 1, C | 1, ctypes.byref(out)) == 1
+    n2 = (ctypes.c_int64 * 2)(127, 64)
+    assert L.impconv_convnd_workspace(1, 0, 2, m2, n2, 2, 1, C, ctypes.byref(out)) == 1
