@@ -633,7 +633,7 @@ def main():
 
     # implicit path, with per-launch event timing inside the library
     ms_clean = timed(W["run"], args.steps, args.warmup)  # the timed region of the metric
-    stats = step_stats(W["run"], max(args.steps, 10))
+    stats = step_stats(W["run"], max(args.steps, 50))  # at least 50 replays for sigma_L / sigma_H
     ic.timing_enable(True)  # second pass: per-launch kernel durations
     timed(W["run"], args.steps, 0, backlog=True)
     rep = ic.timing_report()
@@ -678,6 +678,7 @@ def main():
             # arithmetic intensity above the ridge point: bound by the vector ALUs
             roof = {"bound": "alu", "achieved": dom["tflops"], "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(alu_frac, 4), "traffic": traffic, "kernel": dom["name"],
+                    "measured_gbs": round(traffic / (dom["avg_ms"] * 1e-3) / 1e9, 1) if traffic else None,
                     "kernel_avg_ms": dom["avg_ms"], "algorithmic_flops_per_launch": dom["flops_per_launch"],
                     "frac_of_packed_fp32_peak": (round(dom["tflops"] / VALU_PEAK_PACKED_FP32_TFLOPS, 4)
                                                  if args.dtype == "c64" else None),
@@ -685,6 +686,7 @@ def main():
         elif hbm_frac is not None:
             roof = {"bound": "hbm", "achieved": dom["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(hbm_frac, 4), "traffic": traffic, "kernel": dom["name"],
+                    "measured_gbs": round(traffic / (dom["avg_ms"] * 1e-3) / 1e9, 1) if traffic else None,
                     "kernel_avg_ms": dom["avg_ms"], "algorithmic_bytes_per_launch": dom["bytes_per_launch"]}
 
     alg_gbs = W["step_bytes"] / (ms_clean * 1e-3) / 1e9
