@@ -434,6 +434,10 @@ k_colpass(ColArgs a)
             if (cj) v = conj(v);
             x[e] = ok ? v : zero<T>();
         }
+        // the column twiddles zeta_F^{j2 c} serve both residues: one gather
+        C<T> wf[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) wf[e] = twF[int64_t(t + e * G) * cc];
         static_for<2>([&](auto ri) {
             constexpr int R = decltype(ri)::value;
             C<T> y[E];
@@ -444,26 +448,22 @@ k_colpass(ColArgs a)
                 y[e] = R ? x[e] * tw2F[k + z] : x[e];
             }
             fft<T, N, E, +1>(y, t, lds, TC, twN);
-            const int z2 = opaque_zero();
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int j2 = t + e * G;
-                strow(R, j2, y[e] * twF[int64_t(j2) * cc + z2]);
-            }
+            for (int e = 0; e < E; ++e) strow(R, t + e * G, y[e] * wf[e]);
         });
     } else if constexpr (MODE == kFsFwd) {
         const C<T>* twF = twb + tw_off(a.nf);
         const C<T>* tw2F = twb + tw_off(2 * a.nf);
         C<T> acc[E];
+        // the column twiddles zeta_F^{j2 c} serve both residues: one gather
+        C<T> wf[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) wf[e] = twF[int64_t(t + e * G) * cc];
         static_for<2>([&](auto ri) {
             constexpr int R = decltype(ri)::value;
             C<T> x[E];
-            const int z = opaque_zero();
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int j2 = t + e * G;
-                x[e] = mulc(ldrow(R, j2, N), twF[int64_t(j2) * cc + z]);
-            }
+            for (int e = 0; e < E; ++e) x[e] = mulc(ldrow(R, t + e * G, N), wf[e]);
             fft<T, N, E, -1>(x, t, lds, TC, twN);
             const int z2 = opaque_zero();
 #pragma unroll
