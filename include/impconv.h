@@ -109,7 +109,11 @@ impconv_status impconv_conv1d_workspace(int kind, int dtype, int64_t batch, int6
  * method (inputs copied zero-padded to 2N in work, size-2N cyclic FFT
  * convolution, output cropped); REV/CONJ flags are not accepted with it.
  * The implicit method takes the general p/q rule of Sec. 2.4 where it needs
- * clearly fewer transforms (see impconv_conv1d_complex_pq).
+ * clearly fewer transforms (see impconv_conv1d_complex_pq).  Lengths whose
+ * power-of-two size exceeds 8192 otherwise run as three passes (column FFTs,
+ * row convolutions, column FFTs); the first such call for a given size
+ * creates that size's column twiddle table (synchronously, outside any
+ * graph capture).
  * IMPCONV_COMPENSATED (implicit method, m <= 8192): in complex64 every
  * product by a root of unity -- residue shifts, FFT stage twiddles,
  * recombination -- is formed from the FP32 rounding h of the FP64 value and

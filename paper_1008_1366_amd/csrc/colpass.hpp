@@ -85,6 +85,7 @@ struct ColArgs {
     const void* tw3;
     int ncu;                       // compute units of the device (persistent grids)
     const void* twlo;              // complex64 low parts of tw (fsflags 8: compensated products)
+    const void* twfs;              // four-step: zeta_nf^{j2 c} at [j2][c] (j2 < N, c < ncols)
 };
 
 // Elements per thread of a column pass.  The centered passes keep three
@@ -420,7 +421,6 @@ k_colpass(ColArgs a)
             if (k <= -a.m || k >= a.m) strow(0, row, zero<T>());
         }
     } else if constexpr (MODE == kFsBwd) {
-        const C<T>* twF = twb + tw_off(a.nf);
         const C<T>* tw2F = twb + tw_off(2 * a.nf);
         const int64_t m1 = a.slab_m ? a.slab_m[s1] : a.m;
         const C<T>* src = (const C<T>*)a.in[0] + (a.slab_off ? a.slab_off[s1] + s2 * a.in_bs2 : ib - cc);
@@ -434,10 +434,12 @@ k_colpass(ColArgs a)
             if (cj) v = conj(v);
             x[e] = ok ? v : zero<T>();
         }
-        // the column twiddles zeta_F^{j2 c} serve both residues: one gather
+        // the column twiddles zeta_F^{j2 c} serve both residues: one load
+        // each, contiguous across the columns of a wave
+        const C<T>* twT = (const C<T>*)a.twfs + cc;
         C<T> wf[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) wf[e] = twF[int64_t(t + e * G) * cc];
+        for (int e = 0; e < E; ++e) wf[e] = twT[int64_t(t + e * G) * a.ncols];
         static_for<2>([&](auto ri) {
             constexpr int R = decltype(ri)::value;
             C<T> y[E];
@@ -452,13 +454,14 @@ k_colpass(ColArgs a)
             for (int e = 0; e < E; ++e) strow(R, t + e * G, y[e] * wf[e]);
         });
     } else if constexpr (MODE == kFsFwd) {
-        const C<T>* twF = twb + tw_off(a.nf);
         const C<T>* tw2F = twb + tw_off(2 * a.nf);
         C<T> acc[E];
-        // the column twiddles zeta_F^{j2 c} serve both residues: one gather
+        // the column twiddles zeta_F^{j2 c} serve both residues: one load
+        // each, contiguous across the columns of a wave
+        const C<T>* twT = (const C<T>*)a.twfs + cc;
         C<T> wf[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) wf[e] = twF[int64_t(t + e * G) * cc];
+        for (int e = 0; e < E; ++e) wf[e] = twT[int64_t(t + e * G) * a.ncols];
         static_for<2>([&](auto ri) {
             constexpr int R = decltype(ri)::value;
             C<T> x[E];

@@ -103,6 +103,8 @@ static impconv_status fourstep(const DevTables& tb, int dt, int64_t batch, int64
     const size_t arr = size_t(batch) * M * N * cs;
     void* Wf[2] = {w, w + arr};
     void* Wg[2] = {w + 2 * arr, w + 3 * arr};
+    const void* twfs = fs_twiddles(dt, N2, N1);
+    if (!twfs) return IMPCONV_E_HIP;
     // pass 1: residue shift, column FFT (size N2), twiddle -> W[b][j2][i][k1]
     for (int q = 0; q < 2; ++q) {
         ColArgs a = col_args(tb, dt);
@@ -119,6 +121,7 @@ static impconv_status fourstep(const DevTables& tb, int dt, int64_t batch, int64
         a.out_ld = M * N1;
         a.m = int(m);
         a.nf = N;
+        a.twfs = twfs;
         a.slab_off = d_off;
         a.slab_m = d_m;
         a.fsflags = q == 0 ? ((flags & IMPCONV_REV_F) ? 1u : 0u) : ((flags & IMPCONV_CONJ_G) ? 2u : 0u);
@@ -151,6 +154,7 @@ static impconv_status fourstep(const DevTables& tb, int dt, int64_t batch, int64
     a.ncols = N1;
     a.m = int(m);
     a.nf = N;
+    a.twfs = twfs;
     a.slab_off = d_off;
     a.slab_m = d_m;
     a.fsflags = (flags & IMPCONV_REV_OUT) ? 1u : 0u;

@@ -111,6 +111,18 @@ impconv_status impconv_ragged_plan_create(int dtype, int64_t npairs, const int64
     }
     const int64_t* d = static_cast<const int64_t*>(p->dmem);
     for (const auto& q : pend) p->classes.push_back({q.N, q.count, q.maxm, d + q.off_at, d + q.m_at, 0, {}});
+    // the four-step classes' column twiddle tables are created here, so that
+    // executing the plan allocates nothing (and may be captured)
+    for (const auto& q : pend) {
+        if (q.N <= kRowMax) continue;
+        int64_t N1, N2;
+        fourstep_split(q.N, &N1, &N2);
+        if (!fs_twiddles(dtype, N2, N1)) {
+            if (p->dmem) (void)hipFree(p->dmem);
+            delete p;
+            return IMPCONV_E_HIP;
+        }
+    }
     *plan = p;
     return IMPCONV_OK;
 }

@@ -34,6 +34,11 @@ struct DevTables {
 // rounded to FP32 for the complex64 copy).  Returns nullptr on HIP failure.
 const DevTables* tables();
 
+// Column twiddles of the four-step passes, zeta_F^{j2 c} at [j2][c]
+// (j2 < N2, c < N1, F = N1 N2), created on first use per device, dtype and
+// split (synchronous; nullptr on HIP failure).
+const void* fs_twiddles(int dt, int64_t N2, int64_t N1);
+
 // FP64 host generation, exposed for the host-side unit test.
 void gen_roots(int64_t denom, int64_t count, double* out_re_im);
 

@@ -13,6 +13,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -149,6 +151,43 @@ const DevTables* tables()
     g_tab[dev] = t;
     g_have[dev] = true;
     return &g_tab[dev];
+}
+
+// zeta_F^{j2 c} stored at [j2][c] (j2 < N2, c < N1, F = N1 N2): the column
+// twiddles of the four-step passes, laid out so that the loads of a wave
+// (consecutive columns c) are contiguous instead of j2 elements apart.  The
+// values are the FP64 roots (rounded to float for complex64), as in the
+// zeta_F table.  Created once per device, dtype and split, on first use.
+const void* fs_twiddles(int dt, int64_t N2, int64_t N1)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        hip_fail(e, "hipGetDevice");
+        return nullptr;
+    }
+    static std::map<std::tuple<int, int, int64_t, int64_t>, const void*> cache;
+    std::lock_guard<std::mutex> lk(g_mu);
+    const auto key = std::make_tuple(dev, dt, N2, N1);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    const int64_t F = N1 * N2;
+    std::vector<double> roots(2 * F), t(2 * F);
+    gen_roots(F, F, roots.data());
+    for (int64_t j2 = 0; j2 < N2; ++j2)
+        for (int64_t c = 0; c < N1; ++c) {
+            const int64_t idx = (j2 * c) % F;
+            t[2 * (j2 * N1 + c)] = roots[2 * idx];
+            t[2 * (j2 * N1 + c) + 1] = roots[2 * idx + 1];
+        }
+    const void* p = nullptr;
+    e = dt ? upload<double>(t, &p) : upload<float>(t, &p);
+    if (e != hipSuccess) {
+        hip_fail(e, "four-step twiddle table upload");
+        return nullptr;
+    }
+    cache[key] = p;
+    return p;
 }
 
 // ------------------------------------------------------------------ timing
