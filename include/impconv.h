@@ -275,10 +275,16 @@ impconv_status impconv_conv2d_ternary(int dtype, int64_t batch, const int64_t* m
  * arrays (pairs must not overlap).  The plan copies the descriptors to the
  * device once (synchronously, at creation) and groups pairs by FFT size;
  * executing it launches nothing but kernels, so it may be captured in a
- * hipGraph.  Only impconv_ragged_plan_autotune changes a plan (its schedule,
- * never its results' definition); it must not overlap executions of the
- * same plan.  Concurrent executions need distinct workspaces.  REV_F /
- * CONJ_G / REV_OUT apply per pair as in impconv_conv1d_complex.
+ * hipGraph.  The size classes run concurrently: the plan owns three
+ * auxiliary streams (default priority) and events, execute forks them from
+ * `stream` with an event and joins them back into it, so all work of the
+ * call is ordered after what `stream` had queued and before what it queues
+ * next; each class with N > 8192 uses a region of the workspace of its own.
+ * Calls on one plan from several host threads are serialized while they
+ * enqueue (a mutex of the plan); executions that may overlap on the GPU need
+ * distinct workspaces.  Only impconv_ragged_plan_autotune changes a plan
+ * (its schedule, never its results' definition).  REV_F / CONJ_G / REV_OUT apply per pair
+ * as in impconv_conv1d_complex.
  * ---------------------------------------------------------------------- */
 typedef struct impconv_ragged_plan impconv_ragged_plan;
 

@@ -14,9 +14,11 @@
 // and column FFT sizes, hence the radix schedule of both passes) on
 // temporary arrays of the plan's packed shape and keeps the fastest.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -36,12 +38,38 @@ struct impconv_ragged_plan {
         const int64_t* d_m;
         int64_t n2;                       // four-step column length (0: default split)
         std::vector<std::pair<int64_t, double>> tuned;  // (n2, ms) measured by the autotuner
+        int lane;                         // stream lane: 0 the caller's stream, 1.. the auxiliary ones
+        size_t work_off;                  // four-step classes: byte offset of their work arrays
     };
     std::vector<Class> classes;
     void* dmem;
     size_t work;
     int device;
+    // The size classes run concurrently: the caller's stream forks to the
+    // auxiliary streams through an event and joins them back at the end, so
+    // the short fused classes overlap the long multi-pass ones (one launch
+    // of a short class fills only part of the chip).  Default priority.
+    std::vector<hipStream_t> aux;
+    std::vector<hipEvent_t> join;
+    hipEvent_t fork;
+    // held while an execution (or the autotuner) enqueues its work: the
+    // fork / join events and the auxiliary streams are shared by every call
+    std::mutex mu;
 };
+
+namespace {
+constexpr int kRaggedLanes = 4;  // the caller's stream and three auxiliary streams
+
+void destroy_streams(impconv_ragged_plan* p)
+{
+    for (hipStream_t a : p->aux) (void)hipStreamDestroy(a);
+    for (hipEvent_t e : p->join) (void)hipEventDestroy(e);
+    if (p->fork) (void)hipEventDestroy(p->fork);
+    p->aux.clear();
+    p->join.clear();
+    p->fork = nullptr;
+}
+}  // namespace
 
 namespace {
 #define HIPCHK(expr, what)                                   \
@@ -84,6 +112,7 @@ impconv_status impconv_ragged_plan_create(int dtype, int64_t npairs, const int64
     p->extent = extent;
     p->dmem = nullptr;
     p->work = 0;
+    p->fork = nullptr;
     (void)hipGetDevice(&p->device);
     std::vector<int64_t> host;
     struct Pending { int64_t N, count, maxm; size_t off_at, m_at; };
@@ -98,7 +127,6 @@ impconv_status impconv_ragged_plan_create(int dtype, int64_t npairs, const int64
             q.maxm = std::max(q.maxm, m_host[j]);
         }
         pend.push_back(q);
-        if (q.N > kRowMax) p->work = std::max(p->work, size_t(4) * q.count * q.N * cs);
     }
     if (!host.empty()) {
         hipError_t e = hipMalloc(&p->dmem, host.size() * sizeof(int64_t));
@@ -110,7 +138,39 @@ impconv_status impconv_ragged_plan_create(int dtype, int64_t npairs, const int64
         }
     }
     const int64_t* d = static_cast<const int64_t*>(p->dmem);
-    for (const auto& q : pend) p->classes.push_back({q.N, q.count, q.maxm, d + q.off_at, d + q.m_at, 0, {}});
+    // lanes: longest class first, each to the lane with the least estimated
+    // work (pairs x N log N); the four-step classes get work arrays of their
+    // own, since classes on different lanes run at the same time
+    double load[kRaggedLanes] = {0, 0, 0, 0};
+    for (const auto& q : pend) {
+        int lane = 0;
+        for (int l = 1; l < kRaggedLanes; ++l)
+            if (load[l] < load[lane]) lane = l;
+        load[lane] += double(q.count) * double(q.N) * std::log2(double(q.N) + 1.0) * (q.N > kRowMax ? 3.0 : 1.0);
+        size_t off = 0;
+        if (q.N > kRowMax) {
+            off = p->work;
+            p->work += size_t(4) * q.count * q.N * cs;
+        }
+        p->classes.push_back({q.N, q.count, q.maxm, d + q.off_at, d + q.m_at, 0, {}, lane, off});
+    }
+    {
+        hipError_t e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+        for (int l = 1; l < kRaggedLanes && e == hipSuccess; ++l) {
+            hipStream_t a = nullptr;
+            hipEvent_t j = nullptr;
+            e = hipStreamCreateWithFlags(&a, hipStreamNonBlocking);
+            if (e == hipSuccess) p->aux.push_back(a);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&j, hipEventDisableTiming);
+            if (e == hipSuccess) p->join.push_back(j);
+        }
+        if (e != hipSuccess) {
+            destroy_streams(p);
+            if (p->dmem) (void)hipFree(p->dmem);
+            delete p;
+            return hip_fail(e, "ragged plan streams");
+        }
+    }
     // the four-step classes' column twiddle tables are created here, so that
     // executing the plan allocates nothing (and may be captured)
     for (const auto& q : pend) {
@@ -118,6 +178,7 @@ impconv_status impconv_ragged_plan_create(int dtype, int64_t npairs, const int64
         int64_t N1, N2;
         fourstep_split(q.N, &N1, &N2);
         if (!fs_twiddles(dtype, N2, N1)) {
+            destroy_streams(p);
             if (p->dmem) (void)hipFree(p->dmem);
             delete p;
             return IMPCONV_E_HIP;
@@ -161,7 +222,12 @@ impconv_status impconv_ragged_execute(const impconv_ragged_plan* p, const void* 
     const DevTables* tb = tables();
     if (!tb) return IMPCONV_E_HIP;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(const_cast<impconv_ragged_plan*>(p)->mu);
+    // fork: every auxiliary stream waits for the work queued on s so far
+    HIPCHK(hipEventRecord(p->fork, s), "ragged fork");
+    for (hipStream_t a : p->aux) HIPCHK(hipStreamWaitEvent(a, p->fork, 0), "ragged fork");
     for (const auto& c : p->classes) {
+        hipStream_t cs_ = c.lane == 0 ? s : p->aux[c.lane - 1];
         if (c.N <= kRowMax) {
             RowArgs a;
             std::memset(&a, 0, sizeof(a));
@@ -174,12 +240,18 @@ impconv_status impconv_ragged_execute(const impconv_ragged_plan* p, const void* 
             a.row_off = c.d_off;
             a.row_m = c.d_m;
             a.flags = flags & (kRevF | kConjG | kRevOut);
-            HIPCHK(launch_row_complex(p->dt, int(c.N), a, s), "ragged row class");
+            HIPCHK(launch_row_complex(p->dt, int(c.N), a, cs_), "ragged row class");
         } else {
-            impconv_status st = large1d_run_ragged(*tb, p->dt, c.count, c.N, c.maxm, f, g, h, work,
-                                                   c.d_off, c.d_m, flags, s, c.n2);
+            impconv_status st = large1d_run_ragged(*tb, p->dt, c.count, c.N, c.maxm, f, g, h,
+                                                   static_cast<char*>(work) + c.work_off, c.d_off, c.d_m, flags,
+                                                   cs_, c.n2);
             if (st) return st;
         }
+    }
+    // join: s waits for every auxiliary stream
+    for (size_t l = 0; l < p->aux.size(); ++l) {
+        HIPCHK(hipEventRecord(p->join[l], p->aux[l]), "ragged join");
+        HIPCHK(hipStreamWaitEvent(s, p->join[l], 0), "ragged join");
     }
     return IMPCONV_OK;
 }
@@ -190,6 +262,7 @@ impconv_status impconv_ragged_plan_autotune(impconv_ragged_plan* p, void* stream
     int dev = -1;
     (void)hipGetDevice(&dev);
     if (dev != p->device) return fail(IMPCONV_E_ARG, "plan was created on another device");
+    std::lock_guard<std::mutex> lk(p->mu);  // no execution enqueues while the schedule changes
     bool any = false;
     for (const auto& c : p->classes) any = any || c.N > kRowMax;
     if (!any) return IMPCONV_OK;
@@ -264,7 +337,8 @@ impconv_status impconv_ragged_plan_schedule(const impconv_ragged_plan* p, char* 
             }
         }
         js += (i ? "," : "") + std::string("{\"N\":") + std::to_string(c.N) + ",\"pairs\":" + std::to_string(c.count) +
-              ",\"method\":\"" + (c.N <= kRowMax ? "fused" : "four-step") + "\"";
+              ",\"method\":\"" + (c.N <= kRowMax ? "fused" : "four-step") + "\"" +
+              ",\"stream\":" + std::to_string(c.lane);
         if (c.N > kRowMax) {
             js += ",\"N1\":" + std::to_string(N1) + ",\"N2\":" + std::to_string(N2) + ",\"tuned_ms\":{";
             for (size_t j = 0; j < c.tuned.size(); ++j) {
@@ -289,6 +363,7 @@ impconv_status impconv_ragged_plan_schedule(const impconv_ragged_plan* p, char* 
 impconv_status impconv_ragged_plan_destroy(impconv_ragged_plan* plan)
 {
     if (!plan) return IMPCONV_OK;
+    destroy_streams(plan);
     if (plan->dmem) (void)hipFree(plan->dmem);
     delete plan;
     return IMPCONV_OK;
