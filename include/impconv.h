@@ -222,7 +222,16 @@ size_t impconv_timing_report(char* buf, size_t cap);
  * IMPCONV_COMPLEX also accepts IMPCONV_COMPENSATED (implicit method; as in
  * 1D: compensated twiddle products in the complex64 column passes and rows;
  * the column passes then run one workgroup per tile).
- * IMPCONV_EXPLICIT_PADDED (2D complex only): the conventional comparator --
+ * IMPCONV_HERMITIAN with IMPCONV_EXPLICIT_PADDED (2D and 3D): the
+ * conventional 2/3-rule comparator -- every centered axis zero padded to the
+ * power of two P >= 3m - 2 (wavenumber k at index k mod P), the last axis to
+ * the real length 2 NC >= 3m - 2, full-size complex FFTs along the centered
+ * axes, real cyclic products (with the M-dot) along the last axis, inverse
+ * FFTs, crop; it reads the k_last = 0 hyperplane as its Hermitian projection
+ * (pass symmetric input to compare with the implicit path).  Workspace
+ * 2 * batch * M * prod(P) * (NC + 1) complex values; 3m - 2 <= 4096 on the
+ * centered axes and <= 16384 on the last.
+ * IMPCONV_EXPLICIT_PADDED (2D complex): the conventional comparator --
  * inputs copied into zero-padded 2N0 x 2N1 work arrays, full-size FFTs along
  * both axes, product, inverse, crop (m[d] <= 2048).  With
  * IMPCONV_EXPLICIT_PRUNED as well: the pruned comparator -- the same padded

@@ -334,8 +334,12 @@ def conv2d_ternary(f, g, e, m, symmetrize: bool = True, method: str = "implicit"
     return h.view(*n) if f.dim() == 2 else h
 
 
-def conv3d(f, g, kind: str = "complex", m=None, symmetrize: bool = True, flags: int = 0):
-    """3D convolution (Sec. 3.4); inputs (n0, n1, n2), (B, ...) or (B, M, ...)."""
+def conv3d(f, g, kind: str = "complex", m=None, symmetrize: bool = True, flags: int = 0,
+           method: str = "implicit"):
+    """3D convolution (Sec. 3.4); inputs (n0, n1, n2), (B, ...) or (B, M, ...);
+    method="explicit" runs the explicitly zero-padded comparator (centered
+    Hermitian)."""
+    flags |= {"implicit": 0, "explicit": EXPLICIT_PADDED}[method]
     return _convnd(3, f, g, kind, m, flags | (0 if symmetrize else NO_SYMMETRIZE))
 
 

@@ -184,6 +184,7 @@ namespace {
 struct PlanND {
     int kind, dt, nd;
     int64_t m[3], n[3], Np[3];  // logical modes, storage extents, padded transform sizes (outer axes)
+    int64_t Pe[3];              // Hermitian explicit comparator: padded sizes (last axis: NC, half the real length)
     int64_t batch, M;
     uint32_t flags;
     size_t work;
@@ -212,8 +213,8 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
         return fail(IMPCONV_E_ARG, "EXPLICIT_PRUNED qualifies EXPLICIT_PADDED");
     if ((flags & adj) && (kind != IMPCONV_COMPLEX || (flags & IMPCONV_EXPLICIT_PADDED)))
         return fail(IMPCONV_E_ARG, "REV/CONJ flags apply to implicit complex nD convolutions");
-    if ((flags & IMPCONV_EXPLICIT_PADDED) && kind == IMPCONV_HERMITIAN)
-        return fail(IMPCONV_E_UNSUPPORTED, "the explicitly padded comparator covers 2D complex convolutions");
+    if ((flags & IMPCONV_EXPLICIT_PRUNED) && kind == IMPCONV_HERMITIAN)
+        return fail(IMPCONV_E_UNSUPPORTED, "the pruned comparator covers complex 2D and ternary 2D convolutions");
     std::memset(p, 0, sizeof(*p));
     p->kind = kind; p->dt = dt; p->nd = nd; p->batch = batch; p->M = M; p->flags = flags;
     for (int d = 0; d < nd; ++d) {
@@ -240,6 +241,22 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
     }
     const size_t cs = csize(dt);
     const int R = kind == IMPCONV_COMPLEX ? 2 : 3;
+    if ((flags & IMPCONV_EXPLICIT_PADDED) && kind == IMPCONV_HERMITIAN) {
+        // conventional 2/3 rule: every centered axis zero padded to the power
+        // of two P >= 3m - 2, the Hermitian axis to the real length
+        // 2 NC >= 3m - 2 (half spectrum NC + 1); padded f and g are
+        // [b][P0]([P1])[M][NC + 1]
+        size_t vol = 1;
+        for (int d = 0; d < nd - 1; ++d) {
+            p->Pe[d] = next_pow2(std::max<int64_t>(3 * m[d] - 2, 1));
+            if (p->Pe[d] > kColMax) return fail(IMPCONV_E_UNSUPPORTED, "explicit Hermitian comparator: 3m - 2 <= 4096 on the centered axes");
+            vol *= size_t(p->Pe[d]);
+        }
+        p->Pe[nd - 1] = next_pow2(std::max<int64_t>(3 * m[nd - 1] - 2, 2)) / 2;
+        if (p->Pe[nd - 1] > kRowMax) return fail(IMPCONV_E_UNSUPPORTED, "explicit Hermitian comparator: 3m - 2 <= 16384 on the last axis");
+        p->work = size_t(2) * batch * M * vol * size_t(p->Pe[nd - 1] + 1) * cs;
+        return IMPCONV_OK;
+    }
     if ((flags & IMPCONV_EXPLICIT_PADDED) && kind == IMPCONV_COMPLEX) {
         // padded f and g, [b][2N0][M][2N1] (pruned: only the m1 data columns, [b][2N0][M][m1])
         const int64_t P0 = 2 * p->Np[0], P1 = 2 * p->Np[1];
@@ -516,6 +533,127 @@ impconv_status run2d_ternary(int dt, int64_t batch, const int64_t* m, const int6
     return IMPCONV_OK;
 }
 
+
+// Conventional centered Hermitian nD comparator (Secs. 3.2, 3.4 timing
+// comparisons): f and g copied into zero-padded arrays, every centered axis
+// of length P >= 3m - 2 (wavenumber k at index k mod P, so each line of the
+// transform is a real field in the last axis), the last axis as the half
+// spectrum of a real length 2 NC >= 3m - 2; full-size complex FFTs along the
+// centered axes, real cyclic products (M-dot) along the last axis, inverse
+// FFTs, crop.  No alias of |k| <= 2(m - 1) reaches an output |k| < m.  The
+// k_last = 0 hyperplane is read by the real transforms, i.e. as its
+// Hermitian projection (equal to the implicit path's reading for symmetric
+// input).
+impconv_status run_herm_explicit(const DevTables& tb, const PlanND& p, const void* f, const void* g, void* h,
+                                 char* w, hipStream_t s)
+{
+    const int nd = p.nd, dt = p.dt;
+    const int64_t B = p.batch, M = p.M;
+    const size_t cs = csize(dt);
+    const int64_t NC = p.Pe[nd - 1], L = NC + 1;
+    const int64_t m2 = p.m[nd - 1], n2 = p.n[nd - 1];
+    const int64_t P0 = p.Pe[0], P1 = nd == 3 ? p.Pe[1] : 1;
+    const int64_t m0 = p.m[0], n0 = p.n[0], m1 = nd == 3 ? p.m[1] : 1, n1 = nd == 3 ? p.n[1] : 1;
+    const int64_t vol = P0 * P1;                      // padded centered points
+    const size_t arr = size_t(B) * vol * M * L * cs;  // one padded input
+    void* W[2] = {w, w + arr};
+    const void* src[2] = {f, g};
+    auto at = [&](const void* base, int64_t elems) {
+        return static_cast<const char*>(base) + elems * int64_t(cs);
+    };
+    auto atw = [&](void* base, int64_t elems) { return static_cast<char*>(base) + elems * int64_t(cs); };
+    // centered index ranges: (first stored row, first padded row, count) for k >= 0 and k < 0
+    struct Seg { int64_t src0, dst0, cnt; };
+    auto segs = [](int64_t m, int64_t n, int64_t P) {
+        std::vector<Seg> v;
+        v.push_back({n - m, 0, m});                      // k = 0..m-1
+        if (m > 1) v.push_back({n - 2 * m + 1, P - m + 1, m - 1});  // k = -m+1..-1
+        return v;
+    };
+    const auto sx = segs(m0, n0, P0);
+    const auto sy = nd == 3 ? segs(m1, n1, P1) : std::vector<Seg>{{0, 0, 1}};
+    const int64_t sin_b = M * n0 * n1 * n2, sin_i = n0 * n1 * n2;   // input strides: batch, term
+    for (int q = 0; q < 2; ++q) {
+        // zero the padded array, then copy the (x, y) blocks of k_last < m
+        HIPCHK(launch_copy2d(dt, W[q], W[q], 1, 1, 0, 0, 0, 0, 0, L, 0, 0, B * vol * M, L, s), "explicit zero");
+        for (int64_t b = 0; b < B; ++b)
+            for (const Seg& X : sx)
+                for (const Seg& Y : sy) {
+                    // per x row (nb) and term (nsub): a block of Y.cnt rows x m2 columns
+                    const void* sp = at(src[q], b * sin_b + (X.src0 * n1 + Y.src0) * n2);
+                    void* dp = atw(W[q], ((b * P0 + X.dst0) * P1 + Y.dst0) * M * L);
+                    HIPCHK(launch_copy2d(dt, sp, dp, X.cnt * M, M, n1 * n2, sin_i, n2, P1 * M * L, L, M * L, Y.cnt, m2,
+                                         Y.cnt, m2, s), "explicit pad");
+                }
+        // FFT along x over the columns (y', i, z) of each batch entry
+        ColArgs a = col_args(tb, dt);
+        a.in[0] = a.out[0] = W[q];
+        a.nslab = B;
+        a.in_bs = a.out_bs = vol * M * L;
+        a.ncols = P1 * M * L;
+        a.in_ld = a.out_ld = P1 * M * L;
+        a.n_in = a.n_out = int(P0);
+        HIPCHK(launch_col(dt, int(P0), kFft, 1, a, s), "explicit x FFT");
+        if (nd == 3) {
+            ColArgs c = col_args(tb, dt);
+            c.in[0] = c.out[0] = W[q];
+            c.nslab = B * P0;
+            c.in_bs = c.out_bs = P1 * M * L;
+            c.ncols = M * L;
+            c.in_ld = c.out_ld = M * L;
+            c.n_in = c.n_out = int(P1);
+            HIPCHK(launch_col(dt, int(P1), kFft, 1, c, s), "explicit y FFT");
+        }
+    }
+    // real cyclic products along the last axis, summed over the M terms, into term 0 of W[0]
+    RowArgs ra = row_args(tb, dt);
+    ra.f = W[0]; ra.g = W[1]; ra.h = W[0];
+    ra.nrows = B * vol;
+    ra.m = L;
+    ra.m_out = m2;
+    ra.M = M;
+    ra.f_row = ra.g_row = ra.h_row = M * L;
+    ra.f_i = ra.g_i = L;
+    ra.scale = 1.0 / double(2 * NC);
+    HIPCHK(launch_row_realcyclic(dt, int(NC), ra, s), "explicit last-axis products");
+    if (nd == 3) {
+        ColArgs c = col_args(tb, dt);
+        c.in[0] = c.out[0] = W[0];
+        c.nslab = B * P0;
+        c.in_bs = c.out_bs = P1 * M * L;
+        c.ncols = m2;
+        c.in_ld = c.out_ld = M * L;
+        c.n_in = c.n_out = int(P1);
+        c.scale = 1.0 / double(P1);
+        HIPCHK(launch_col(dt, int(P1), kFft, -1, c, s), "explicit inverse y FFT");
+    }
+    {
+        // inverse x FFT of term 0: slabs (b, y'), columns z < m2, rows x' (stride P1 M L)
+        ColArgs a = col_args(tb, dt);
+        a.in[0] = a.out[0] = W[0];
+        a.nslab = B * P1;
+        a.nsub = P1;
+        a.in_bs = a.out_bs = vol * M * L;
+        a.in_bs2 = a.out_bs2 = M * L;
+        a.ncols = m2;
+        a.in_ld = a.out_ld = P1 * M * L;
+        a.n_in = a.n_out = int(P0);
+        a.scale = 1.0 / double(P0);
+        HIPCHK(launch_col(dt, int(P0), kFft, -1, a, s), "explicit inverse x FFT");
+    }
+    // crop into h (zero slots and the Hermitian slot column stay zero)
+    HIPCHK(launch_copy2d(dt, h, h, 1, 1, 0, 0, 0, 0, 0, n2, 0, 0, B * n0 * n1, n2, s), "explicit zero output");
+    for (int64_t b = 0; b < B; ++b)
+        for (const Seg& X : sx)
+            for (const Seg& Y : sy) {
+                const void* sp = at(W[0], ((b * P0 + X.dst0) * P1 + Y.dst0) * M * L);
+                void* dp = static_cast<char*>(h) + ((b * n0 + X.src0) * n1 + Y.src0) * n2 * int64_t(cs);
+                HIPCHK(launch_copy2d(dt, sp, dp, X.cnt, 1, P1 * M * L, 0, M * L, n1 * n2, 0, n2, Y.cnt, m2, Y.cnt,
+                                     m2, s), "explicit crop");
+            }
+    return IMPCONV_OK;
+}
+
 impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const int64_t* m,
                      const int64_t* n, const void* f, const void* g, void* h, void* work, size_t wb,
                      uint32_t flags, void* stream)
@@ -549,6 +687,7 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
     const bool sym = herm && !(flags & IMPCONV_NO_SYMMETRIZE);
     char* w = static_cast<char*>(work);
 
+    if ((flags & IMPCONV_EXPLICIT_PADDED) && herm) return run_herm_explicit(tb, p, f, g, h, w, s);
     if ((flags & IMPCONV_EXPLICIT_PADDED) && (flags & IMPCONV_EXPLICIT_PRUNED)) {
         // Pruned conventional method: the padded transforms with the zero
         // padding fused into the loads and no transform of an all-zero
