@@ -336,6 +336,7 @@ def wl_c4(args):
     S = int(np.prod(n)) * cs
     run = lambda: ic.conv3d(F, G, kind="hermitian", m=m)
     expl = lambda: ic.conv3d(F, G, kind="hermitian", m=m, method="explicit")
+    pruned = lambda: ic.conv3d(F, G, kind="hermitian", m=m, method="pruned")
     # Sec. 3.4 five-pass schedule, algorithmic bytes per step (S = one stored
     # array): x back 6S -> 9S and y back 9S -> 13.5S (colpass_cen_bwd), z
     # convolutions 13.5S -> 2.25S (3 m_x x 3 m_y rows, M = 3 per row), y
@@ -369,7 +370,7 @@ def wl_c4(args):
                        "(m=256 per axis), M=3 pairs summed, "
                        f"{'complex64' if cdt == torch.complex64 else 'complex128'}",
            "m": list(m), "n": list(n), "M": 3, "dtype": args.dtype}
-    return dict(run=run, explicit=expl, convs=1, step_bytes=step_bytes, kbytes_step=kbytes_step,
+    return dict(run=run, explicit=expl, pruned=pruned, convs=1, step_bytes=step_bytes, kbytes_step=kbytes_step,
                 kflops_step=kflops_step, cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy())
 
 

@@ -230,7 +230,8 @@ size_t impconv_timing_report(char* buf, size_t cap);
  * FFTs, crop; it reads the k_last = 0 hyperplane as its Hermitian projection
  * (pass symmetric input to compare with the implicit path).  Workspace
  * 2 * batch * M * prod(P) * (NC + 1) complex values; 3m - 2 <= 4096 on the
- * centered axes and <= 16384 on the last.
+ * centered axes and <= 16384 on the last.  With IMPCONV_EXPLICIT_PRUNED as
+ * well: the same transforms without those of all-zero columns.
  * IMPCONV_EXPLICIT_PADDED (2D complex): the conventional comparator --
  * inputs copied into zero-padded 2N0 x 2N1 work arrays, full-size FFTs along
  * both axes, product, inverse, crop (m[d] <= 2048).  With

@@ -338,8 +338,8 @@ def conv3d(f, g, kind: str = "complex", m=None, symmetrize: bool = True, flags: 
            method: str = "implicit"):
     """3D convolution (Sec. 3.4); inputs (n0, n1, n2), (B, ...) or (B, M, ...);
     method="explicit" runs the explicitly zero-padded comparator (centered
-    Hermitian)."""
-    flags |= {"implicit": 0, "explicit": EXPLICIT_PADDED}[method]
+    Hermitian), "pruned" its form without transforms of all-zero columns."""
+    flags |= {"implicit": 0, "explicit": EXPLICIT_PADDED, "pruned": EXPLICIT_PADDED | EXPLICIT_PRUNED}[method]
     return _convnd(3, f, g, kind, m, flags | (0 if symmetrize else NO_SYMMETRIZE))
 
 

@@ -213,8 +213,6 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
         return fail(IMPCONV_E_ARG, "EXPLICIT_PRUNED qualifies EXPLICIT_PADDED");
     if ((flags & adj) && (kind != IMPCONV_COMPLEX || (flags & IMPCONV_EXPLICIT_PADDED)))
         return fail(IMPCONV_E_ARG, "REV/CONJ flags apply to implicit complex nD convolutions");
-    if ((flags & IMPCONV_EXPLICIT_PRUNED) && kind == IMPCONV_HERMITIAN)
-        return fail(IMPCONV_E_UNSUPPORTED, "the pruned comparator covers complex 2D and ternary 2D convolutions");
     std::memset(p, 0, sizeof(*p));
     p->kind = kind; p->dt = dt; p->nd = nd; p->batch = batch; p->M = M; p->flags = flags;
     for (int d = 0; d < nd; ++d) {
@@ -543,9 +541,12 @@ impconv_status run2d_ternary(int dt, int64_t batch, const int64_t* m, const int6
 // FFTs, crop.  No alias of |k| <= 2(m - 1) reaches an output |k| < m.  The
 // k_last = 0 hyperplane is read by the real transforms, i.e. as its
 // Hermitian projection (equal to the implicit path's reading for symmetric
-// input).
+// input).  pruned: no transform of a column that is all zero -- the x FFTs
+// run over the data rows of y and the data columns of the last axis only,
+// the y FFTs over the data columns, the inverse x FFT over the rows the crop
+// keeps.
 impconv_status run_herm_explicit(const DevTables& tb, const PlanND& p, const void* f, const void* g, void* h,
-                                 char* w, hipStream_t s)
+                                 char* w, hipStream_t s, bool pruned)
 {
     const int nd = p.nd, dt = p.dt;
     const int64_t B = p.batch, M = p.M;
@@ -586,20 +587,39 @@ impconv_status run_herm_explicit(const DevTables& tb, const PlanND& p, const voi
                                          Y.cnt, m2, s), "explicit pad");
                 }
         // FFT along x over the columns (y', i, z) of each batch entry
-        ColArgs a = col_args(tb, dt);
-        a.in[0] = a.out[0] = W[q];
-        a.nslab = B;
-        a.in_bs = a.out_bs = vol * M * L;
-        a.ncols = P1 * M * L;
-        a.in_ld = a.out_ld = P1 * M * L;
-        a.n_in = a.n_out = int(P0);
-        HIPCHK(launch_col(dt, int(P0), kFft, 1, a, s), "explicit x FFT");
+        if (!pruned) {
+            ColArgs a = col_args(tb, dt);
+            a.in[0] = a.out[0] = W[q];
+            a.nslab = B;
+            a.in_bs = a.out_bs = vol * M * L;
+            a.ncols = P1 * M * L;
+            a.in_ld = a.out_ld = P1 * M * L;
+            a.n_in = a.n_out = int(P0);
+            HIPCHK(launch_col(dt, int(P0), kFft, 1, a, s), "explicit x FFT");
+        } else {
+            // slabs (b, y' data row, i), columns z < m2: (y', i) sit at (y' M + i) L
+            for (const Seg& Y : sy) {
+                ColArgs a = col_args(tb, dt);
+                a.in[0] = a.out[0] = atw(W[q], Y.dst0 * M * L);
+                a.nslab = B * Y.cnt * M;
+                a.nsub = Y.cnt * M;
+                a.in_bs = a.out_bs = vol * M * L;
+                a.in_bs2 = a.out_bs2 = L;
+                a.ncols = m2;
+                a.in_ld = a.out_ld = P1 * M * L;
+                a.n_in = a.n_out = int(P0);
+                HIPCHK(launch_col(dt, int(P0), kFft, 1, a, s), "explicit x FFT");
+            }
+        }
         if (nd == 3) {
+            // FFT along y in every (b, x') plane; pruned: slabs (b x', i), columns z < m2
             ColArgs c = col_args(tb, dt);
             c.in[0] = c.out[0] = W[q];
-            c.nslab = B * P0;
+            c.nslab = B * P0 * (pruned ? M : 1);
+            c.nsub = pruned ? M : 1;
             c.in_bs = c.out_bs = P1 * M * L;
-            c.ncols = M * L;
+            c.in_bs2 = c.out_bs2 = pruned ? L : 0;
+            c.ncols = pruned ? m2 : M * L;
             c.in_ld = c.out_ld = M * L;
             c.n_in = c.n_out = int(P1);
             HIPCHK(launch_col(dt, int(P1), kFft, 1, c, s), "explicit y FFT");
@@ -609,7 +629,7 @@ impconv_status run_herm_explicit(const DevTables& tb, const PlanND& p, const voi
     RowArgs ra = row_args(tb, dt);
     ra.f = W[0]; ra.g = W[1]; ra.h = W[0];
     ra.nrows = B * vol;
-    ra.m = L;
+    ra.m = pruned ? m2 : L;  // the entries from m2 on are zero
     ra.m_out = m2;
     ra.M = M;
     ra.f_row = ra.g_row = ra.h_row = M * L;
@@ -627,12 +647,14 @@ impconv_status run_herm_explicit(const DevTables& tb, const PlanND& p, const voi
         c.scale = 1.0 / double(P1);
         HIPCHK(launch_col(dt, int(P1), kFft, -1, c, s), "explicit inverse y FFT");
     }
-    {
-        // inverse x FFT of term 0: slabs (b, y'), columns z < m2, rows x' (stride P1 M L)
+    // inverse x FFT of term 0: slabs (b, y'), columns z < m2, rows x' (stride
+    // P1 M L); pruned: only the y' rows the crop keeps
+    const std::vector<Seg> yall{{0, 0, P1}};
+    for (const Seg& Y : pruned ? sy : yall) {
         ColArgs a = col_args(tb, dt);
-        a.in[0] = a.out[0] = W[0];
-        a.nslab = B * P1;
-        a.nsub = P1;
+        a.in[0] = a.out[0] = atw(W[0], Y.dst0 * M * L);
+        a.nslab = B * Y.cnt;
+        a.nsub = Y.cnt;
         a.in_bs = a.out_bs = vol * M * L;
         a.in_bs2 = a.out_bs2 = M * L;
         a.ncols = m2;
@@ -687,7 +709,8 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
     const bool sym = herm && !(flags & IMPCONV_NO_SYMMETRIZE);
     char* w = static_cast<char*>(work);
 
-    if ((flags & IMPCONV_EXPLICIT_PADDED) && herm) return run_herm_explicit(tb, p, f, g, h, w, s);
+    if ((flags & IMPCONV_EXPLICIT_PADDED) && herm)
+        return run_herm_explicit(tb, p, f, g, h, w, s, flags & IMPCONV_EXPLICIT_PRUNED);
     if ((flags & IMPCONV_EXPLICIT_PADDED) && (flags & IMPCONV_EXPLICIT_PRUNED)) {
         // Pruned conventional method: the padded transforms with the zero
         // padding fused into the loads and no transform of an all-zero

@@ -1,6 +1,6 @@
 """The explicitly zero-padded centered Hermitian 2D/3D comparator (padding
 to powers of two >= 3m - 2, full-size transforms, real cyclic products,
-crop) against the oracle, on inputs whose k_last = 0 hyperplane is already
+crop) and its pruned form against the oracle, on inputs whose k_last = 0 hyperplane is already
 Hermitian (the comparator reads that hyperplane by its real transforms)."""
 import numpy as np
 import pytest
@@ -35,15 +35,14 @@ def test_explicit_hermitian_nd_vs_oracle(dt, m, n):
     f = np.stack([np.stack([sym_storage(m, n, 800 + 4 * b + i) for i in range(M)]) for b in range(B)])
     g = np.stack([np.stack([sym_storage(m, n, 810 + 4 * b + i) for i in range(M)]) for b in range(B)])
     F, G = to_dev(f, dt), to_dev(g, dt)
-    if len(m) == 2:
-        he = ic.conv2d(F, G, kind="hermitian", m=m, method="explicit").cpu().numpy()
-        hi = ic.conv2d(F, G, kind="hermitian", m=m).cpu().numpy()
-    else:
-        he = ic.conv3d(F, G, kind="hermitian", m=m, method="explicit").cpu().numpy()
-        hi = ic.conv3d(F, G, kind="hermitian", m=m).cpu().numpy()
+    fn = ic.conv2d if len(m) == 2 else ic.conv3d
+    he = fn(F, G, kind="hermitian", m=m, method="explicit").cpu().numpy()
+    hp = fn(F, G, kind="hermitian", m=m, method="pruned").cpu().numpy()
+    hi = fn(F, G, kind="hermitian", m=m).cpu().numpy()
     for b in range(B):
         ref = oracle.convnd_hermitian(rounded(f[b], dt), rounded(g[b], dt), m)
         assert rel(he[b], ref) < TOL[dt], b
+        assert rel(hp[b], ref) < TOL[dt], b
         assert rel(hi[b], ref) < TOL[dt], b
 
 
@@ -56,9 +55,10 @@ def test_explicit_hermitian_3d_c4_shape_sampled():
     f = np.stack([sym_storage(m, n, 820 + i) for i in range(M)])
     g = np.stack([sym_storage(m, n, 830 + i) for i in range(M)])
     F, G = to_dev(f[None], np.complex64), to_dev(g[None], np.complex64)
-    he = ic.conv3d(F, G, kind="hermitian", m=m, method="explicit").cpu().numpy()[0]
     pts = np.array([[0, 0, 0], [255, -255, 255], [-100, 37, 0], [3, -4, 200], [-255, 0, 17]])
     ref = oracle.convnd_hermitian_at(rounded(f, np.complex64), rounded(g, np.complex64), m, pts)
-    got = he[pts[:, 0] + 256, pts[:, 1] + 256, pts[:, 2]]
-    assert rel(got, ref) < TOL[np.complex64]
-    assert np.all(he[0] == 0) and np.all(he[:, 0] == 0) and np.all(he[..., 256] == 0)  # zero slots
+    for method in ("explicit", "pruned"):
+        he = ic.conv3d(F, G, kind="hermitian", m=m, method=method).cpu().numpy()[0]
+        got = he[pts[:, 0] + 256, pts[:, 1] + 256, pts[:, 2]]
+        assert rel(got, ref) < TOL[np.complex64], method
+        assert np.all(he[0] == 0) and np.all(he[:, 0] == 0) and np.all(he[..., 256] == 0), method  # zero slots
