@@ -463,8 +463,35 @@ def wl_c5(args):
                        f"(both gradients) per step, {'complex64' if cdt == torch.complex64 else 'complex128'}",
            "pairs": int(len(ms)), "sum_m": tot, "dtype": args.dtype, "schedule": sched,
            "autotuned": not args.no_autotune}
+    def graph_step():
+        """The same step captured once in a hipGraph (forward, backward and
+        the gradient buffers); returns the replay and a check that a replay
+        reproduces the eager outputs bit for bit."""
+        run()
+        torch.cuda.synchronize()
+        h_eager = run().detach().clone()
+        gf_eager, gg_eager = F.grad.clone(), G.grad.clone()
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(graph, stream=side):
+            F.grad = None
+            G.grad = None
+            h_static = ic.ragged_conv_ad(plan, F, G)
+            h_static.backward(Wt)
+        torch.cuda.synchronize()
+
+        def check():
+            graph.replay()
+            torch.cuda.synchronize()
+            return bool(torch.equal(h_static, h_eager) and torch.equal(F.grad, gf_eager)
+                        and torch.equal(G.grad, gg_eager))
+        return graph.replay, check
+
     return dict(run=run, explicit=None, convs=len(ms), step_bytes=step_bytes, kbytes_step=kbytes_step,
-                kflops_step=kflops_step, cfg=cfg, cpu=cpu_baseline, out=lambda: run().detach().cpu().numpy())
+                kflops_step=kflops_step, cfg=cfg, cpu=cpu_baseline, out=lambda: run().detach().cpu().numpy(),
+                graph=graph_step)
 
 
 def wl_t2(args):
@@ -631,6 +658,7 @@ def main():
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-explicit", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="c5: skip the captured-graph replay leg")
     ap.add_argument("--no-autotune", action="store_true", help="c5: keep the default four-step splits")
     ap.add_argument("--t2-m", type=int, default=1024, help="t2: modes per axis")
     ap.add_argument("--e2-m", type=int, default=2048, help="e2: modes per axis")
@@ -739,6 +767,13 @@ def main():
         out["compensated"] = {"ms_per_step": round(ms_c, 5), "value": round(W["convs"] * 1000.0 / ms_c, 2),
                               "unit": "convs/s", "note": "IMPCONV_COMPENSATED: twiddle products from FP32 "
                               "high and low parts; errors under rel_err_vs_oracle.compensated"}
+
+    if W.get("graph") is not None and not args.no_graph:
+        replay, check = W["graph"]()
+        ms_g = timed(replay, args.steps, args.warmup)
+        out["hip_graph"] = {"ms_per_step": round(ms_g, 5), "value": round(W["convs"] * 1000.0 / ms_g, 2),
+                            "unit": "convs/s", "replay_equals_eager": check(),
+                            "note": "the whole step (forward, both gradients) captured once and replayed"}
 
     if args.profile_copy:
         n = args.profile_copy * (1 << 20) // 4
