@@ -76,6 +76,7 @@ typedef enum impconv_kind {
 #define IMPCONV_HERMITIAN_ADJOINT (1u << 5) /* Hermitian 1D/nD: vector-Jacobian product edits (see below) */
 #define IMPCONV_EXPLICIT_PRUNED (1u << 6) /* with EXPLICIT_PADDED (2D): skip all-zero transforms, fuse padding */
 #define IMPCONV_COMPENSATED (1u << 7)     /* complex64 complex convolutions: compensated twiddle products */
+#define IMPCONV_ONE_STREAM (1u << 8)      /* ragged batches: size classes one after another on `stream` */
 
 /* Version as 10000*major + 100*minor + patch. */
 int impconv_version(void);
@@ -294,7 +295,11 @@ impconv_status impconv_conv2d_ternary(int dtype, int64_t batch, const int64_t* m
  * enqueue (a mutex of the plan); executions that may overlap on the GPU need
  * distinct workspaces.  Only impconv_ragged_plan_autotune changes a plan
  * (its schedule, never its results' definition).  REV_F / CONJ_G / REV_OUT apply per pair
- * as in impconv_conv1d_complex.
+ * as in impconv_conv1d_complex.  IMPCONV_ONE_STREAM runs the size classes one
+ * after another on `stream` alone (no fork or join; the auxiliary streams
+ * stay idle) with the same kernels, so its results are bitwise those of the
+ * concurrent form: for callers that want every launch on their stream, and
+ * for timing each kernel without the classes overlapping.
  * ---------------------------------------------------------------------- */
 typedef struct impconv_ragged_plan impconv_ragged_plan;
 

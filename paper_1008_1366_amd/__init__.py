@@ -27,7 +27,7 @@ __all__ = [
     "lib", "available", "ImpconvError", "conv1d_complex", "conv1d_hermitian", "conv1d_ternary",
     "conv2d", "conv3d", "RaggedPlan", "conv1d_complex_ad", "ragged_conv_ad", "workspace_bytes",
     "timing_enable", "timing_report",
-    "EXPLICIT_PADDED", "REV_F", "CONJ_G", "REV_OUT", "NO_SYMMETRIZE",
+    "EXPLICIT_PADDED", "REV_F", "CONJ_G", "REV_OUT", "NO_SYMMETRIZE", "ONE_STREAM",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -35,6 +35,7 @@ LIB_PATH = os.path.join(HERE, "libimpconv.so")
 
 EXPLICIT_PADDED, REV_F, CONJ_G, REV_OUT, NO_SYMMETRIZE, HERMITIAN_ADJOINT, EXPLICIT_PRUNED = 1, 2, 4, 8, 16, 32, 64
 COMPENSATED = 128  # complex64: compensated twiddle products (complex convolutions)
+ONE_STREAM = 256  # ragged batches: size classes one after another on the caller's stream
 COMPLEX, HERMITIAN, TERNARY = 0, 1, 2
 C64, C128 = 0, 1
 
@@ -361,7 +362,11 @@ def timing_report() -> list:
 
 class RaggedPlan:
     """Uneven-length batch of complex 1D convolutions packed in one array:
-    pair j uses elements offsets[j] .. offsets[j] + ms[j] - 1."""
+    pair j uses elements offsets[j] .. offsets[j] + ms[j] - 1.  With
+    `one_stream` set, every execution (the autograd adjoints included) runs
+    the size classes one after another on the current stream (ONE_STREAM)."""
+
+    one_stream = False
 
     def __init__(self, ms, offsets, dtype=torch.complex64, device=None, autotune: bool = False):
         import numpy as np
@@ -418,6 +423,8 @@ class RaggedPlan:
         else:
             h = torch.zeros_like(f)
         w = self._work if work is None else work
+        if self.one_stream:
+            flags |= ONE_STREAM
         _check(lib().impconv_ragged_execute(self._h, _ptr(f), _ptr(g), _ptr(h), _ptr(w), self.work_bytes,
                                             flags, ctypes.c_void_p(_stream(f.device))), "ragged_execute")
         return h

@@ -200,8 +200,10 @@ impconv_status impconv_ragged_execute(const impconv_ragged_plan* p, const void* 
                                       void* stream)
 {
     if (!p) return fail(IMPCONV_E_ARG, "plan is NULL");
-    const uint32_t known = IMPCONV_REV_F | IMPCONV_CONJ_G | IMPCONV_REV_OUT;
+    const uint32_t known = IMPCONV_REV_F | IMPCONV_CONJ_G | IMPCONV_REV_OUT | IMPCONV_ONE_STREAM;
     if (flags & ~known) return fail(IMPCONV_E_ARG, "unsupported flag for a ragged batch");
+    const bool one = (flags & IMPCONV_ONE_STREAM) != 0;
+    flags &= ~IMPCONV_ONE_STREAM;
     if (p->npairs == 0) return IMPCONV_OK;
     const size_t cs = p->dt ? 16 : 8;
     for (const void* q : {f, g, (const void*)h}) {
@@ -224,10 +226,12 @@ impconv_status impconv_ragged_execute(const impconv_ragged_plan* p, const void* 
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(const_cast<impconv_ragged_plan*>(p)->mu);
     // fork: every auxiliary stream waits for the work queued on s so far
-    HIPCHK(hipEventRecord(p->fork, s), "ragged fork");
-    for (hipStream_t a : p->aux) HIPCHK(hipStreamWaitEvent(a, p->fork, 0), "ragged fork");
+    if (!one) {
+        HIPCHK(hipEventRecord(p->fork, s), "ragged fork");
+        for (hipStream_t a : p->aux) HIPCHK(hipStreamWaitEvent(a, p->fork, 0), "ragged fork");
+    }
     for (const auto& c : p->classes) {
-        hipStream_t cs_ = c.lane == 0 ? s : p->aux[c.lane - 1];
+        hipStream_t cs_ = one || c.lane == 0 ? s : p->aux[c.lane - 1];
         if (c.N <= kRowMax) {
             RowArgs a;
             std::memset(&a, 0, sizeof(a));
@@ -249,7 +253,7 @@ impconv_status impconv_ragged_execute(const impconv_ragged_plan* p, const void* 
         }
     }
     // join: s waits for every auxiliary stream
-    for (size_t l = 0; l < p->aux.size(); ++l) {
+    for (size_t l = 0; l < p->aux.size() && !one; ++l) {
         HIPCHK(hipEventRecord(p->join[l], p->aux[l]), "ragged join");
         HIPCHK(hipStreamWaitEvent(s, p->join[l], 0), "ragged join");
     }

@@ -141,7 +141,8 @@ def test_plan_create_validation(L):
     assert create(kind=2, ndim=2, m=(2048, 4, 0), n=(4096, 5, 0), flags=1) == 5  # explicit: m0 <= 1024
     assert create(kind=1, ndim=2, m=(4, 4, 0), n=(9, 5, 0)) == 2  # centered axis needs 2m-1 or 2m
     assert create(kind=0, ndim=2, m=(4, 4, 0), n=(4, 5, 0)) == 2  # complex storage n == m
-    assert create(flags=1 << 8) == 1
+    assert create(flags=1 << 8) == 1  # ONE_STREAM is for ragged batches only
+    assert create(flags=1 << 9) == 1
     assert create(kind=0, ndim=2, m=(4, 4, 0), n=(4, 4, 0), flags=1 << 6) == 1  # PRUNED needs EXPLICIT
     n = ctypes.c_size_t()
     assert L.impconv_workspace_bytes(None, ctypes.byref(n)) == 1

@@ -113,6 +113,47 @@ def test_ragged_autotuned_schedule():
         assert np.array_equal(out.cpu().numpy(), h), rep
 
 
+@pytest.mark.parametrize("dt", [np.complex64, np.complex128])
+def test_ragged_one_stream_matches_concurrent(dt):
+    """ONE_STREAM (every size class on the caller's stream, in turn) runs the
+    same kernels as the concurrent form: bitwise equal results, also with the
+    adjoint flags and through the autograd wrapper; forward checked against
+    the oracle on the short pairs and at sampled outputs of the long ones."""
+    ic = need_gpu()
+    import torch
+    tdt = torch.complex64 if dt == np.complex64 else torch.complex128
+    ms = np.array([64, 300, 4096, 16384, 65536, 9, 8193, 1, 40000])
+    offs, f = packed(ms, 141)
+    _, g = packed(ms, 142)
+    say(f"ragged one-stream {dt.__name__}")
+    F, G = to_dev(f, dt), to_dev(g, dt)
+    plan = ic.RaggedPlan(ms, offs, dtype=tdt)
+    for fl in (0, ic.REV_F | ic.CONJ_G | ic.REV_OUT):
+        conc = plan.execute(F, G, flags=fl)
+        one = plan.execute(F, G, flags=fl | ic.ONE_STREAM)
+        torch.cuda.synchronize()
+        assert torch.equal(conc, one), fl
+    fr, gr = rounded(f, dt), rounded(g, dt)
+    h = plan.execute(F, G, flags=ic.ONE_STREAM).cpu().numpy()
+    for m, o in zip(ms, offs):
+        if m <= 4096:
+            assert rel(h[o:o + m], oracle.conv1d_complex(fr[o:o + m], gr[o:o + m])) < TOL[dt], m
+        else:
+            ks = np.array([0, 1, m // 3, m - 1])
+            ref = oracle.convnd_complex_at(fr[o:o + m], gr[o:o + m], ks[:, None])
+            assert rel(h[o + ks], ref) < TOL[dt], m
+    w = to_dev(synth.unit_disk(f.shape[0], 143), dt)
+    grads = []
+    for one_stream in (False, True):
+        plan.one_stream = one_stream
+        Fr = F.clone().requires_grad_(True)
+        Gr = G.clone().requires_grad_(True)
+        ic.ragged_conv_ad(plan, Fr, Gr).backward(w)
+        grads.append((Fr.grad, Gr.grad))
+    plan.one_stream = False
+    assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
+
+
 def test_ragged_graph_replay_matches_eager():
     ic = need_gpu()
     import torch
