@@ -339,8 +339,10 @@ impconv_status impconv_ragged_plan_schedule(const impconv_ragged_plan* plan, cha
  * Descriptor-based plans: one create / execute pair for every kind and
  * dimension.  impconv_plan_create validates the descriptor with the same
  * rules (and error codes) as the matching one-shot call, creates the twiddle
- * tables of the current device and fixes the workspace size, so that
- * impconv_execute only launches kernels (it may be captured in a hipGraph).
+ * tables of the current device (with, for complex 1D lengths whose power-of-
+ * two size exceeds 8192, that size's column twiddle table) and fixes the
+ * workspace size, so that impconv_execute only launches kernels: even its
+ * first call may be captured in a hipGraph.
  * A plan is immutable and holds no data-sized memory; it may be executed
  * concurrently with distinct workspaces, on the device it was created on.
  * ---------------------------------------------------------------------- */

@@ -216,6 +216,22 @@ RowArgs row_args(const DevTables* tb, int dt)
 }
 
 }  // namespace
+
+// Device-side preparation of a 1D convolution that its execution would
+// otherwise do on first use: the column twiddle table of the three-pass form
+// (complex lengths whose power-of-two size exceeds kRowMax, 1/2 rule).
+impconv_status conv1d_prepare(int kind, int dt, int64_t batch, int64_t M, int64_t m, uint32_t flags)
+{
+    if (kind != IMPCONV_COMPLEX) return IMPCONV_OK;
+    Plan1D p;
+    impconv_status st = plan1d(kind, dt, batch, M, m, flags, &p);
+    if (st) return st;
+    if (p.explicit_ || p.np != 0 || p.N <= kRowMax) return IMPCONV_OK;
+    int64_t N1, N2;
+    fourstep_split(p.N, &N1, &N2);
+    return fs_twiddles(dt, N2, N1) ? IMPCONV_OK : IMPCONV_E_HIP;
+}
+
 }  // namespace impconv
 
 using namespace impconv;

@@ -14,6 +14,11 @@
 
 namespace impconv {
 
+// Creates, on the current device, what a 1D convolution of these parameters
+// would otherwise create on its first call (the three-pass form's column
+// twiddle table), so that later calls launch kernels only.
+impconv_status conv1d_prepare(int kind, int dt, int64_t batch, int64_t M, int64_t m, uint32_t flags);
+
 // Complex 1D convolution of length m > kRowMax (next_pow2(m) <= 2^17).
 impconv_status large1d_plan(int dt, int64_t batch, int64_t M, int64_t m, size_t* work);
 impconv_status large1d_run(const DevTables& tb, int dt, int64_t batch, int64_t M, int64_t m,

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "multid.hpp"
 #include "runtime.hpp"
 
 struct impconv_plan {
@@ -95,6 +96,9 @@ impconv_status impconv_plan_create(impconv_plan** plan, const impconv_desc* desc
     impconv_status st = validate(desc, &work);
     if (st) return st;
     if ((st = impconv_init())) return st;
+    if (desc->ndim == 1 && (st = conv1d_prepare(desc->kind, desc->dtype, desc->batch, desc->M, desc->m[0],
+                                                desc->flags)))
+        return st;
     auto* p = new impconv_plan();
     p->d = *desc;
     p->work = work;

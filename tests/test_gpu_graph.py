@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_util import need_gpu, say
+from gpu_util import need_gpu, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -83,3 +83,40 @@ def test_graph_replay_matches_eager(idx):
         torch.cuda.synchronize()
         assert torch.equal(out, eager), (name, rep)
         _ = (a * 2).sum().item()  # unrelated eager work between replays
+
+
+def test_plan_first_execution_is_capturable():
+    """A descriptor plan creates everything its execution needs: the first
+    execution of a long complex 1D plan (three-pass form, whose column
+    twiddle table is made at plan creation) may itself be captured, and the
+    replays equal an eager execution bit for bit."""
+    ic = need_gpu()
+    import torch
+    m, B = 70000, 2  # power-of-two size 131072, four-step split 512 x 256
+    say(f"plan capture complex 1D m={m}")
+    dev = torch.device("cuda:0")
+    plan = ic.Plan("complex", torch.complex128, (m,), batch=B)
+    A = torch.from_numpy(synth.unit_disk((B, m), 741)).to(dev)
+    Bv = torch.from_numpy(synth.unit_disk((B, m), 742)).to(dev)
+    out = torch.empty((B, m), dtype=torch.complex128, device=dev)
+    work = torch.empty(max(plan.work_bytes, 16), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        plan.execute(A, Bv, out=out, work=work)
+    for rep in range(2):
+        graph.replay()
+        torch.cuda.synchronize()
+        eager = plan.execute(A, Bv)
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+        A.copy_(torch.from_numpy(synth.unit_disk((B, m), 743 + rep)).to(dev))
+    ks = np.array([0, 1, 777, m - 1])
+    a, b = A.cpu().numpy(), Bv.cpu().numpy()
+    graph.replay()
+    torch.cuda.synchronize()
+    import oracle
+    ref = oracle.convnd_complex_at(a[1], b[1], ks[:, None])
+    assert rel(out[1].cpu().numpy()[ks], ref) < 1e-11
