@@ -63,3 +63,23 @@ def test_euler_nonlinearity_small(dt):
     assert rel(h, ref) < (1e-12 if dt == np.complex128 else 2e-6)
     # the same inputs through the oracle's M = 2 sum
     assert rel(h, oracle.convnd_hermitian(rounded(f, dt), rounded(g, dt), m)) < TOL[dt]
+
+
+def test_euler_nonlinearity_2048_sampled():
+    """The benchmarked size: 2048 x 2048 modes (storage 4096 x 2049), M = 2,
+    complex64, in the launch configuration the benchmark times; 40 outputs
+    (corners, the k_y = 0 line on both sides, random interior points) vs the
+    oracle's M = 2 centered Hermitian sums of the same rounded inputs."""
+    ic = need_gpu()
+    dt = np.complex64
+    m = (2048, 2048)
+    say("euler 2D 2048^2 sampled")
+    w, f, g = euler_inputs(m, 602)
+    h = ic.conv2d(to_dev(f[None], dt), to_dev(g[None], dt), kind="hermitian", m=m).cpu().numpy()[0]
+    rng = synth.rng(603)
+    pts = np.stack([rng.integers(-m[0] + 1, m[0], 32), rng.integers(0, m[1], 32)], 1)
+    pts = np.concatenate([[[0, 0], [m[0] - 1, m[1] - 1], [-m[0] + 1, 0], [-m[0] + 1, m[1] - 1],
+                           [5, 0], [-5, 0], [1, 1], [-1, 2047]], pts])
+    ref = oracle.convnd_hermitian_at(rounded(f, dt), rounded(g, dt), m, pts)
+    off = f.shape[1] - m[0]
+    assert rel(h[pts[:, 0] + off, pts[:, 1]], ref) < TOL[dt]
