@@ -97,6 +97,24 @@ def kernel_source_hash(kernel: str = "") -> str:
     return h.hexdigest()[:16]
 
 
+def oracle_one_thread(fn, budget_s=2.0):
+    """Seconds per call of fn with the oracle on one host thread (repeated up
+    to about budget_s), the thread count restored afterwards."""
+    import oracle
+    n0 = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        calls, t0 = 0, time.perf_counter()
+        while True:
+            fn()
+            calls += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
+        return (time.perf_counter() - t0) / calls
+    finally:
+        oracle.set_num_threads(n0)
+
+
 def timed(fn, steps, warmup, backlog=False):
     """Average ms per step over `steps` calls, bracketed by events on the
     current stream.  backlog=True first queues a ~20 ms spin kernel so the
@@ -255,15 +273,20 @@ def wl_c2(args):
         ref = oracle.conv1d_hermitian(fr[:, None], gr[:, None])
         dt = time.perf_counter() - t0
         err = float(np.linalg.norm(h_gpu[:nb] - ref) / np.linalg.norm(ref))
+        t1 = oracle_one_thread(lambda: oracle.conv1d_hermitian(fr[:1, None], gr[:1, None]))
         return {"value": nb / dt, "unit": "convs/s", "cores": oracle.num_threads(), "kind": "oracle",
-                "sample": f"{nb} of the {B} convolutions, direct FP64 sums ({dt:.2f} s)"}, err
+                "sample": f"{nb} of the {B} convolutions, direct FP64 sums ({dt:.2f} s)",
+                "one_thread_s_per_conv": t1}, err
 
     cfg = {"workload": f"1D centered Hermitian implicit dealiased convolution m={m}, batch {B}, "
                        f"{'complex64' if cdt == torch.complex64 else 'complex128'}",
            "m": m, "batch": B, "dtype": args.dtype}
     expl = None
+    F1, G1 = F[:1].contiguous(), G[:1].contiguous()
+    single = {"run": lambda: ic.conv1d_hermitian(F1, G1), "explicit": None,
+              "note": "one convolution (one workgroup): latency-bound"}
     return dict(run=run, explicit=expl, convs=B, step_bytes=3 * B * m * cs, kbytes=kbytes, kflops=kflops,
-                cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy())
+                cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy(), single=single)
 
 
 def wl_c1(args):
@@ -296,14 +319,21 @@ def wl_c1(args):
             if h is not None:
                 e = [float(np.linalg.norm(h[i] - ref[i]) / np.linalg.norm(ref[i])) for i in range(nb)]
                 err[key] = {"max": max(e), "median": float(np.median(e)), "pairs": nb}
+        f1 = np.asarray(f[:1].astype(np.complex64 if cdt == torch.complex64 else np.complex128), np.complex128)
+        g1 = np.asarray(g[:1].astype(np.complex64 if cdt == torch.complex64 else np.complex128), np.complex128)
+        t1 = oracle_one_thread(lambda: oracle.conv1d_complex(f1[:, None], g1[:, None]))
         return {"value": nb / dt, "unit": "convs/s", "cores": oracle.num_threads(), "kind": "oracle",
-                "sample": f"{nb} of the {B} pairs, direct FP64 sums ({dt:.2f} s)"}, err
+                "sample": f"{nb} of the {B} pairs, direct FP64 sums ({dt:.2f} s)",
+                "one_thread_s_per_conv": t1}, err
 
     cfg = {"workload": f"1D complex implicit dealiased convolution m={m}, batch {B}, "
                        f"{'complex64' if cdt == torch.complex64 else 'complex128'}", "m": m, "batch": B,
            "dtype": args.dtype}
+    F1, G1 = F[:1].contiguous(), G[:1].contiguous()
+    single = {"run": lambda: ic.conv1d_complex(F1, G1), "explicit": lambda: ic.conv1d_complex(F1, G1, method="explicit"),
+              "note": "one pair (one workgroup): latency-bound"}
     return dict(run=run, explicit=expl, compensated=comp, convs=B, step_bytes=3 * B * m * cs, kbytes=kbytes,
-                kflops=kflops, cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy())
+                kflops=kflops, cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy(), single=single)
 
 
 def wl_c4(args):
@@ -661,7 +691,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
-    ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--dtype", default=None, choices=["c64", "c128"],
+                    help="default: c128 for c1 (the 1D complex case is stated in FP64), c64 otherwise")
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-explicit", action="store_true")
@@ -676,6 +707,7 @@ def main():
     ap.add_argument("--profile-copy", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
+    args.dtype = args.dtype or ("c128" if args.workload == "c1" else "c64")
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the workloads "
               "shard by batch with no exchange between GPUs, so they are measured on one", file=sys.stderr)
@@ -779,6 +811,17 @@ def main():
         out["compensated"] = {"ms_per_step": round(ms_c, 5), "value": round(W["convs"] * 1000.0 / ms_c, 2),
                               "unit": "convs/s", "note": "IMPCONV_COMPENSATED: twiddle products from FP32 "
                               "high and low parts; errors under rel_err_vs_oracle.compensated"}
+
+    if W.get("single") is not None:
+        # the same convolution on one pair: a latency figure beside the batch throughput
+        sg = W["single"]
+        ms_1 = timed(sg["run"], max(args.steps, 50), args.warmup)
+        out["single_pair"] = {"ms": round(ms_1, 5), "value": round(1000.0 / ms_1, 2), "unit": "convs/s",
+                              "note": sg["note"]}
+        if sg.get("explicit") is not None and not args.no_explicit:
+            ms_1e = timed(sg["explicit"], max(args.steps, 50), args.warmup)
+            out["single_pair"]["explicit_ms"] = round(ms_1e, 5)
+            out["single_pair"]["speedup_vs_explicit"] = round(ms_1e / ms_1, 3)
 
     if W.get("graph") is not None and not args.no_graph:
         replay, check = W["graph"]()
