@@ -97,6 +97,19 @@ def kernel_source_hash(kernel: str = "") -> str:
     return h.hexdigest()[:16]
 
 
+def fp32_vs_fp64(h32, run64):
+    """Relative L2 difference, per pair over the whole field, between the
+    complex64 result h32 (host array, pairs on axis 0) and the complex128
+    path run on the GPU on the same (complex64-rounded) inputs; the FP64
+    result is itself checked against the oracle in the FP64 runs and tests."""
+    import torch
+    h64 = run64().cpu().numpy()
+    torch.cuda.empty_cache()
+    e = [float(np.linalg.norm(h32[b].astype(np.complex128) - h64[b]) / np.linalg.norm(h64[b]))
+         for b in range(h64.shape[0])]
+    return {"max": max(e), "median": float(np.median(e)), "pairs": len(e)}
+
+
 def oracle_one_thread(fn, budget_s=2.0):
     """Seconds per call of fn with the oracle on one host thread (repeated up
     to about budget_s), the thread count restored afterwards."""
@@ -236,6 +249,9 @@ def wl_c3(args):
         convs_per_s = 1.0 / (t_oracle / macs * full)
         errs = {k: {"max": max(v), "median": float(np.median(v)), "pairs": len(v)} for k, v in res.items() if v}
         errs["estimate"] = "full-field relative L2 per pair, from the stratified sample"
+        if cdt == torch.complex64:
+            errs["fp32_vs_fp64_full_field"] = fp32_vs_fp64(
+                h_gpu, lambda: ic.conv2d(F.to(torch.complex128), G.to(torch.complex128)))
         return {"value": convs_per_s, "unit": "convs/s", "cores": oracle.num_threads(), "kind": "oracle",
                 "sample": f"per pair the {L}x{L} low-wavenumber block plus {nrand} uniform random "
                           f"output points, direct FP64 sums ({t_oracle:.2f} s), extrapolated to whole "
@@ -378,7 +394,10 @@ def wl_c4(args):
 
     def cpu_baseline(h_gpu, h_expl=None):
         import oracle
-        pts = np.array([[0, 0, 0], [255, 255, 255], [-255, 0, 3], [5, -7, 0]])
+        rng = synth.rng(206)
+        pts = np.concatenate([[[0, 0, 0], [255, 255, 255], [-255, 0, 3], [5, -7, 0], [-3, 9, 0], [0, -200, 0]],
+                              np.stack([rng.integers(-255, 256, 10), rng.integers(-255, 256, 10),
+                                        rng.integers(0, 256, 10)], 1)])
         fr = np.asarray(f[0].astype(np.complex64 if cdt == torch.complex64 else np.complex128), np.complex128)
         gr = np.asarray(g[0].astype(np.complex64 if cdt == torch.complex64 else np.complex128), np.complex128)
         t0 = time.perf_counter()
@@ -390,6 +409,9 @@ def wl_c4(args):
                 got = hh[0][pts[:, 0] + 256, pts[:, 1] + 256, pts[:, 2]]
                 err[key] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
         err["points"] = len(pts)
+        if cdt == torch.complex64:
+            err["fp32_vs_fp64_full_field"] = fp32_vs_fp64(
+                h_gpu, lambda: ic.conv3d(F.to(torch.complex128), G.to(torch.complex128), kind="hermitian", m=m))
         # terms per output point ~ prod(2m-1) * M / 2 on average; 256^2 * 256 outputs
         per_pt = dt / len(pts)
         nout = 511 * 511 * 256
