@@ -15,7 +15,6 @@
  *   Complex values are interleaved (re, im): complex64 = 2 x float,
  *   complex128 = 2 x double (the layout of torch.complex64/complex128).
  *   Arrays are C-contiguous, last axis stride 1.
- * - Inputs are read only.  h must not overlap f, g or e (E_ARG).
  * - The result is the exact (unnormalized) convolution sum, as defined per
  *   entry point below; only the summation order differs from the definition.
  * - Work arrays are separate from the data and provided by the caller
@@ -24,11 +23,15 @@
  * - All work is enqueued on `stream` (a hipStream_t; NULL = default stream).
  *   Nothing synchronizes; device-side faults surface at the caller's next
  *   synchronization.
+ * - Inputs are read only.  The output h may be an input itself (h == f, g
+ *   or e) when the two arrays have the same extent, e.g. M = 1: the paper's
+ *   in-place form (an input given as h is overwritten by the result).  Any
+ *   other overlap of h with an input is IMPCONV_E_ARG.
  * - The library allocates no data-sized memory.  On first use on a device it
  *   allocates ~12 MB of twiddle tables (impconv_init); call impconv_init()
  *   outside any stream capture before capturing calls into a hipGraph.
  * - Every argument check happens on the host before any launch.  Errors:
- *     IMPCONV_E_ARG        null pointer, bad kind/dtype/flags, aliasing
+ *     IMPCONV_E_ARG        null pointer, bad kind/dtype/flags, overlapping h
  *     IMPCONV_E_SIZE       m < 1, batch < 0, M < 1, bad storage extents
  *     IMPCONV_E_WORKSPACE  work_bytes smaller than the queried size
  *     IMPCONV_E_ALIGN      pointer not aligned to its complex element size

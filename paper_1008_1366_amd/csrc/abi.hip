@@ -34,14 +34,6 @@ size_t csize(int dt) { return dt ? 16 : 8; }
 
 bool aligned(const void* p, int dt) { return (reinterpret_cast<uintptr_t>(p) % csize(dt)) == 0; }
 
-bool overlap(const void* a, size_t na, const void* b, size_t nb)
-{
-    if (!a || !b || na == 0 || nb == 0) return false;
-    const char* x = static_cast<const char*>(a);
-    const char* y = static_cast<const char*>(b);
-    return x < y + nb && y < x + na;
-}
-
 impconv_status check_dtype(int dt)
 {
     if (dt != IMPCONV_C64 && dt != IMPCONV_C128) return fail(IMPCONV_E_ARG, "dtype must be IMPCONV_C64 or IMPCONV_C128");
@@ -285,8 +277,8 @@ static impconv_status run1d(int kind, int dtype, int64_t batch, int64_t M, int64
     if (st) return st;
     const size_t cs = csize(dt);
     const size_t nin = size_t(batch) * (kind == IMPCONV_TERNARY ? 1 : M) * m * cs, nout = size_t(batch) * m * cs;
-    if (overlap(h, nout, f, nin) || overlap(h, nout, g, nin) || (e && overlap(h, nout, e, nin)))
-        return fail(IMPCONV_E_ARG, "h overlaps an input");
+    if (bad_alias(h, nout, f, nin) || bad_alias(h, nout, g, nin) || (e && bad_alias(h, nout, e, nin)))
+        return fail(IMPCONV_E_ARG, "h overlaps an input (only h == input of the same extent is allowed)");
     if (wb < p.work) return fail(IMPCONV_E_WORKSPACE, "workspace too small: need " + std::to_string(p.work) + " bytes");
     if (p.work && !work) return fail(IMPCONV_E_ARG, "work is NULL");
     if (p.work && !aligned(work, dt)) return fail(IMPCONV_E_ALIGN, "work not aligned");

@@ -395,11 +395,8 @@ impconv_status run2d_ternary(int dt, int64_t batch, const int64_t* m, const int6
         if (reinterpret_cast<uintptr_t>(q) % cs) return fail(IMPCONV_E_ALIGN, "data pointer misaligned");
     const int64_t n0 = n[0], n1 = n[1], m0 = m[0], m1 = m[1];
     const size_t vol = size_t(batch) * n0 * n1 * cs;
-    auto ov = [](const void* a, size_t na, const void* b, size_t nb) {
-        const char* x = (const char*)a; const char* y = (const char*)b;
-        return x < y + nb && y < x + na;
-    };
-    if (ov(h, vol, f, vol) || ov(h, vol, g, vol) || ov(h, vol, e, vol)) return fail(IMPCONV_E_ARG, "h overlaps an input");
+    if (bad_alias(h, vol, f, vol) || bad_alias(h, vol, g, vol) || bad_alias(h, vol, e, vol))
+        return fail(IMPCONV_E_ARG, "h overlaps an input (only h == input of the same extent is allowed)");
     if (wb < p.work) return fail(IMPCONV_E_WORKSPACE, "workspace too small: need " + std::to_string(p.work) + " bytes");
     if (!work) return fail(IMPCONV_E_ARG, "work is NULL");
     if (reinterpret_cast<uintptr_t>(work) % cs) return fail(IMPCONV_E_ALIGN, "work misaligned");
@@ -692,11 +689,8 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
     size_t vol = 1;
     for (int d = 0; d < nd; ++d) vol *= size_t(n[d]);
     const size_t nin = batch * M * vol * cs, nout = batch * vol * cs;
-    auto ov = [](const void* a, size_t na, const void* b, size_t nb) {
-        const char* x = (const char*)a; const char* y = (const char*)b;
-        return x < y + nb && y < x + na;
-    };
-    if (ov(h, nout, f, nin) || ov(h, nout, g, nin)) return fail(IMPCONV_E_ARG, "h overlaps an input");
+    if (bad_alias(h, nout, f, nin) || bad_alias(h, nout, g, nin))
+        return fail(IMPCONV_E_ARG, "h overlaps an input (only h == input of the same extent is allowed)");
     if (wb < p.work) return fail(IMPCONV_E_WORKSPACE, "workspace too small: need " + std::to_string(p.work) + " bytes");
     if (!work) return fail(IMPCONV_E_ARG, "work is NULL");
     if (reinterpret_cast<uintptr_t>(work) % cs) return fail(IMPCONV_E_ALIGN, "work misaligned");

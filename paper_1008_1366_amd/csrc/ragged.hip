@@ -211,11 +211,8 @@ impconv_status impconv_ragged_execute(const impconv_ragged_plan* p, const void* 
         if (reinterpret_cast<uintptr_t>(q) % cs) return fail(IMPCONV_E_ALIGN, "data pointer misaligned");
     }
     const size_t bytes = size_t(p->extent) * cs;
-    auto ov = [](const void* a, const void* b, size_t n) {
-        const char* x = (const char*)a; const char* y = (const char*)b;
-        return x < y + n && y < x + n;
-    };
-    if (ov(h, f, bytes) || ov(h, g, bytes)) return fail(IMPCONV_E_ARG, "h overlaps an input");
+    if (bad_alias(h, bytes, f, bytes) || bad_alias(h, bytes, g, bytes))
+        return fail(IMPCONV_E_ARG, "h overlaps an input (only h == f or h == g is allowed)");
     if (work_bytes < p->work) return fail(IMPCONV_E_WORKSPACE, "workspace too small: need " + std::to_string(p->work) + " bytes");
     if (p->work && !work) return fail(IMPCONV_E_ARG, "work is NULL");
     int dev = -1;

@@ -52,6 +52,20 @@ bool timing_on();
 void timing_begin(hipStream_t s);
 void timing_end(const char* name, hipStream_t s);
 
+// Whether output h (nh bytes) overlaps input x (nx bytes) in a way the
+// kernels do not support.  h may be x itself when both have the same extent
+// (the in-place form): every pass reads its input rows or columns before the
+// pass that writes the same elements, and no launch writes data another
+// workgroup of it still reads.
+inline bool bad_alias(const void* h, size_t nh, const void* x, size_t nx)
+{
+    if (!h || !x || nh == 0 || nx == 0) return false;
+    if (h == x && nh == nx) return false;
+    const char* a = static_cast<const char*>(h);
+    const char* b = static_cast<const char*>(x);
+    return a < b + nx && b < a + nh;
+}
+
 inline int64_t next_pow2(int64_t x)
 {
     int64_t p = 1;

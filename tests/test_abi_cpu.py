@@ -73,8 +73,11 @@ def test_call_errors_before_launch(L):
     assert L.impconv_conv1d_complex(0, 1, 1, 8, None, None, None, None, 0, 0, None) == 1
     # misaligned pointer
     assert L.impconv_conv1d_complex(0, 1, 1, 8, c(8), c(4099), c(1 << 20), None, 0, 0, None) == 4
-    # h overlapping f
+    # h overlapping f other than exactly (in place is h == f with the same extent)
     assert L.impconv_conv1d_complex(0, 1, 1, 8, c(1 << 20), c(1 << 24), c((1 << 20) + 16), None, 0, 0, None) == 1
+    # h == f but f is [batch][M][m] with M = 2: extents differ, rejected
+    assert L.impconv_conv1d_complex(0, 1, 2, 8, c(1 << 20), c(1 << 24), c(1 << 20), None, 0, 0, None) == 1
+    assert b"overlaps" in L.impconv_last_error()
     # undersized workspace (explicit comparator needs one)
     assert L.impconv_conv1d_complex(0, 1, 1, 8, c(1 << 20), c(1 << 24), c(1 << 26), c(1 << 28), 8, 1, None) == 3
     assert b"workspace" in L.impconv_last_error()

@@ -1,0 +1,90 @@
+"""The in-place form (the paper keeps results in the input storage): h may
+be f, g or e itself when the arrays have the same extent.  Every path -- row
+kernels, the general p/q rule, the three-pass long 1D form, the multi-pass
+2D/3D forms, the explicit comparators and a ragged batch -- must give, in
+place, bit for bit what it gives out of place."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def herm_storage(m, n, seed):
+    u = synth.unit_disk(n, seed)
+    for d in range(len(m) - 1):
+        if n[d] == 2 * m[d]:
+            idx = [slice(None)] * len(m)
+            idx[d] = 0
+            u[tuple(idx)] = 0
+    if n[-1] == m[-1] + 1:
+        u[..., m[-1]] = 0
+    return u
+
+
+CASES = [
+    # kind, dtype, m, n, batch, flags
+    ("complex", "c64", (1000,), None, 3, 0),
+    ("complex", "c64", (10000,), None, 2, 0),       # general p/q rule (one pass)
+    ("complex", "c128", (20000,), None, 2, 0),      # three-pass form
+    ("hermitian", "c64", (3000,), None, 2, 0),
+    ("ternary", "c128", (200,), None, 2, 0),
+    ("complex", "c64", (40, 33), None, 2, 0),
+    ("hermitian", "c128", (5, 6, 4), (9, 12, 5), 2, 0),
+    ("ternary", "c64", (12, 9), (24, 10), 2, 0),
+    ("complex", "c64", (500,), None, 2, 1),         # explicit comparator
+    ("hermitian", "c64", (20, 17), (40, 18), 2, 1),  # explicit comparator
+]
+
+
+@pytest.mark.parametrize("idx", range(len(CASES)))
+def test_in_place_equals_out_of_place(idx):
+    ic = need_gpu()
+    import torch
+    kind, dts, m, n, B, flags = CASES[idx]
+    dt = torch.complex64 if dts == "c64" else torch.complex128
+    n = n or m
+    say(f"in place {kind} {dts} m={m} n={n} flags={flags}")
+    dev = torch.device("cuda:0")
+
+    def make(seed):
+        if kind == "complex" or len(m) == 1:
+            a = synth.unit_disk((B, *n), seed)
+        else:
+            a = np.stack([herm_storage(m, n, seed + b) for b in range(B)])
+        return torch.from_numpy(a).to(dev, dt)
+
+    F, G = make(801), make(811)
+    E = make(821) if kind == "ternary" else None
+    plan = ic.Plan(kind, dt, m, n=n if len(m) > 1 else None, batch=B, flags=flags)
+    ref = plan.execute(F, G, e=E)
+    torch.cuda.synchronize()
+    targets = ["f", "g"] + (["e"] if E is not None else [])
+    for which in targets:
+        F2, G2 = F.clone(), G.clone()
+        E2 = E.clone() if E is not None else None
+        out = {"f": F2, "g": G2, "e": E2}[which]
+        plan.execute(F2, G2, e=E2, out=out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), which
+
+
+def test_ragged_in_place():
+    ic = need_gpu()
+    import torch
+    ms = np.array([64, 300, 4096, 16384, 9, 8193, 1, 40000])
+    offs = np.concatenate([[0], np.cumsum(ms)[:-1]])
+    tot = int(ms.sum())
+    dev = torch.device("cuda:0")
+    F = torch.from_numpy(synth.unit_disk(tot, 831)).to(dev, torch.complex64)
+    G = torch.from_numpy(synth.unit_disk(tot, 832)).to(dev, torch.complex64)
+    plan = ic.RaggedPlan(ms, offs, dtype=torch.complex64)
+    ref = plan.execute(F, G)
+    for which in ("f", "g"):
+        F2, G2 = F.clone(), G.clone()
+        out = F2 if which == "f" else G2
+        plan.execute(F2, G2, out=out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), which
