@@ -476,10 +476,27 @@ class Plan:
             pass
 
 
-def conv1d_complex_ragged(f, g, ms, offsets, flags: int = 0):
+def conv1d_complex_ragged(f, g, ms=None, offsets=None, flags: int = 0):
     """One-shot ragged batch (impconv_conv1d_complex_ragged; the library
-    caches the plan of each layout)."""
+    caches the plan of each layout).  Packed form: f, g 1D tensors holding
+    pair j at offsets[j] .. offsets[j] + ms[j] - 1; returns the packed h.
+    List form: f, g equal-length sequences of 1D tensors (pair j = f[j],
+    g[j], same length); they are packed end to end and the list of the pairs'
+    outputs is returned."""
     import numpy as np
+    if isinstance(f, (list, tuple)):
+        if not isinstance(g, (list, tuple)) or len(f) != len(g):
+            raise ValueError("list form: f and g must be sequences of the same length")
+        if ms is not None or offsets is not None:
+            raise ValueError("list form: lengths and offsets come from the tensors")
+        if len(f) == 0:
+            return []
+        lens = [int(a.numel()) for a in f]
+        if any(int(b.numel()) != n for b, n in zip(g, lens)) or min(lens) < 1:
+            raise ValueError("list form: f[j] and g[j] must have the same length >= 1")
+        hp = conv1d_complex_ragged(torch.cat([a.reshape(-1) for a in f]), torch.cat([b.reshape(-1) for b in g]),
+                                   lens, np.concatenate([[0], np.cumsum(lens)[:-1]]), flags)
+        return list(torch.split(hp, lens))
     _dev(f, g)
     ms = np.ascontiguousarray(np.asarray(ms, dtype=np.int64))
     offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))

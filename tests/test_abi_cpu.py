@@ -194,3 +194,18 @@ def test_compensated_flag_validation(L):
     assert L.impconv_convnd_workspace(0, 0, 2, m2, m2, 2, 1, C | 1, ctypes.byref(out)) == 1
     n2 = (ctypes.c_int64 * 2)(127, 64)
     assert L.impconv_convnd_workspace(1, 0, 2, m2, n2, 2, 1, C, ctypes.byref(out)) == 1
+
+
+def test_ragged_list_form_validation():
+    """The Python list form checks its arguments before any device work."""
+    import pytest as _pt
+    import torch
+    import paper_1008_1366_amd as ic
+    a = [torch.zeros(3, dtype=torch.complex64), torch.zeros(2, dtype=torch.complex64)]
+    assert ic.conv1d_complex_ragged([], []) == []
+    with _pt.raises(ValueError):
+        ic.conv1d_complex_ragged(a, a[:1])
+    with _pt.raises(ValueError):
+        ic.conv1d_complex_ragged(a, [a[1], a[0]])
+    with _pt.raises(ValueError):
+        ic.conv1d_complex_ragged(a, a, ms=[3, 2])

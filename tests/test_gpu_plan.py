@@ -89,6 +89,11 @@ def test_oneshot_ragged_matches_plan():
     for m, o in zip(ms[:4], offs[:4]):
         assert rel(hr[o:o + m], oracle.conv1d_complex(rounded(f[o:o + m], np.complex64),
                                                       rounded(g[o:o + m], np.complex64))) < TOL[np.complex64]
+    # list form: one tensor per pair, packed end to end by the wrapper
+    hl = ic.conv1d_complex_ragged([F[o:o + m] for m, o in zip(ms, offs)], [G[o:o + m] for m, o in zip(ms, offs)])
+    assert len(hl) == len(ms)
+    for hj, m, o in zip(hl, ms, offs):
+        assert torch.equal(hj, ref[o:o + m])
 
 
 def test_plan_ternary_2d():
