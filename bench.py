@@ -151,8 +151,10 @@ def timed(fn, steps, warmup, backlog=False):
 
 
 def step_stats(fn, n):
-    """Per-step times (events around each step): mean and the root-mean-square
-    deviations of the steps below and above the mean (sigma_L, sigma_H)."""
+    """Per-step times (events around each step): the mean T and the one-sided
+    deviations of the paper's timing statistics, sigma_L (sigma_H) the square
+    root of the summed squared deviations of the steps below (above) T
+    divided by n/2 - 1."""
     import torch
     s = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
@@ -164,10 +166,10 @@ def step_stats(fn, n):
     torch.cuda.synchronize()
     t = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(n)])
     mu = t.mean()
-    lo, hi = t[t < mu], t[t >= mu]
-    rms = lambda d: float(np.sqrt(np.mean(d ** 2))) if len(d) else 0.0
-    return {"n": n, "mean_ms": round(float(mu), 5), "sigma_lo_ms": round(rms(mu - lo), 5),
-            "sigma_hi_ms": round(rms(hi - mu), 5)}
+    lo, hi = t[t < mu], t[t > mu]
+    one_sided = lambda d: float(np.sqrt(np.sum(d ** 2) / (n / 2.0 - 1.0)))
+    return {"n": n, "mean_ms": round(float(mu), 5), "sigma_lo_ms": round(one_sided(mu - lo), 5),
+            "sigma_hi_ms": round(one_sided(hi - mu), 5)}
 
 
 def copy_bandwidth(mib=1024):
