@@ -721,6 +721,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-explicit", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="c5: skip the captured-graph replay leg")
+    ap.add_argument("--no-single", action="store_true", help="c1/c2: skip the one-pair latency leg")
     ap.add_argument("--no-autotune", action="store_true", help="c5: keep the default four-step splits")
     ap.add_argument("--t2-m", type=int, default=1024, help="t2: modes per axis")
     ap.add_argument("--e2-m", type=int, default=2048, help="e2: modes per axis")
@@ -836,7 +837,7 @@ def main():
                               "unit": "convs/s", "note": "IMPCONV_COMPENSATED: twiddle products from FP32 "
                               "high and low parts; errors under rel_err_vs_oracle.compensated"}
 
-    if W.get("single") is not None:
+    if W.get("single") is not None and not args.no_single:
         # the same convolution on one pair: a latency figure beside the batch throughput
         sg = W["single"]
         ms_1 = timed(sg["run"], max(args.steps, 50), args.warmup)
