@@ -321,6 +321,7 @@ def wl_c1(args):
     cs = 8 if cdt == torch.complex64 else 16
     run = lambda: ic.conv1d_complex(F, G)
     expl = lambda: ic.conv1d_complex(F, G, method="explicit")
+    pruned = lambda: ic.conv1d_complex(F, G, method="pruned")
     comp = (lambda: ic.conv1d_complex(F, G, flags=ic.COMPENSATED)) if cdt == torch.complex64 else None
     kbytes = {"k_conv1d_complex": 3 * B * m * cs}
     kflops = {"k_conv1d_complex": B * flops_row_complex(m)}
@@ -350,7 +351,7 @@ def wl_c1(args):
     F1, G1 = F[:1].contiguous(), G[:1].contiguous()
     single = {"run": lambda: ic.conv1d_complex(F1, G1), "explicit": lambda: ic.conv1d_complex(F1, G1, method="explicit"),
               "note": "one pair (one workgroup): latency-bound"}
-    return dict(run=run, explicit=expl, compensated=comp, convs=B, step_bytes=3 * B * m * cs, kbytes=kbytes,
+    return dict(run=run, explicit=expl, pruned=pruned, compensated=comp, convs=B, step_bytes=3 * B * m * cs, kbytes=kbytes,
                 kflops=kflops, cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy(), single=single)
 
 

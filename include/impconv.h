@@ -77,7 +77,7 @@ typedef enum impconv_kind {
 #define IMPCONV_REV_OUT (1u << 3)         /* complex 1D: write h reversed */
 #define IMPCONV_NO_SYMMETRIZE (1u << 4)   /* Hermitian nD: trust the k_last = 0 plane (see conv2d) */
 #define IMPCONV_HERMITIAN_ADJOINT (1u << 5) /* Hermitian 1D/nD: vector-Jacobian product edits (see below) */
-#define IMPCONV_EXPLICIT_PRUNED (1u << 6) /* with EXPLICIT_PADDED (2D): skip all-zero transforms, fuse padding */
+#define IMPCONV_EXPLICIT_PRUNED (1u << 6) /* with EXPLICIT_PADDED: skip all-zero transforms, fuse padding */
 #define IMPCONV_COMPENSATED (1u << 7)     /* complex64 complex convolutions: compensated twiddle products */
 #define IMPCONV_ONE_STREAM (1u << 8)      /* ragged batches: size classes one after another on `stream` */
 
@@ -112,6 +112,9 @@ impconv_status impconv_conv1d_workspace(int kind, int dtype, int64_t batch, int6
  * With IMPCONV_EXPLICIT_PADDED the same sum is computed by the conventional
  * method (inputs copied zero-padded to 2N in work, size-2N cyclic FFT
  * convolution, output cropped); REV/CONJ flags are not accepted with it.
+ * With IMPCONV_EXPLICIT_PRUNED as well, the padding is fused into the loads
+ * instead (one size-2N cyclic convolution per row reads f and g, zero beyond
+ * m, and writes the first m outputs; no workspace).
  * The implicit method takes the general p/q rule of Sec. 2.4 where it needs
  * clearly fewer transforms (see impconv_conv1d_complex_pq).  Lengths whose
  * power-of-two size exceeds 8192 otherwise run as three passes (column FFTs,

@@ -187,8 +187,10 @@ def _conv1d(kind: int, f, g, method: str, flags: int):
     dt = _dtype_code(f)
     if method == "explicit":
         flags |= EXPLICIT_PADDED
+    elif method == "pruned" and kind == COMPLEX:
+        flags |= EXPLICIT_PADDED | EXPLICIT_PRUNED
     elif method != "implicit":
-        raise ValueError("method must be 'implicit' or 'explicit'")
+        raise ValueError("method must be 'implicit' or 'explicit' (complex also 'pruned')")
     h = torch.empty((B, m), dtype=f.dtype, device=dev)
     wb = workspace_bytes(kind, dt, B, M, m, flags)
     w = _work(wb, dev)
@@ -202,7 +204,9 @@ def _conv1d(kind: int, f, g, method: str, flags: int):
 
 def conv1d_complex(f, g, method: str = "implicit", flags: int = 0):
     """Complex 1D dealiased convolution (Sec. 2.1) of (m,), (B, m) or (B, M, m)
-    inputs (M = dot-product width); returns (m,) or (B, m)."""
+    inputs (M = dot-product width); returns (m,) or (B, m).  method="explicit"
+    runs the explicitly zero-padded comparator, "pruned" its form with the
+    padding fused into the loads."""
     return _conv1d(COMPLEX, f, g, method, flags)
 
 

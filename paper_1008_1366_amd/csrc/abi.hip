@@ -119,9 +119,11 @@ impconv_status plan1d(int kind, int dt, int64_t batch, int64_t M, int64_t m, uin
     if (m < 1) return fail(IMPCONV_E_SIZE, "m must be >= 1");
     if (batch < 0) return fail(IMPCONV_E_SIZE, "batch must be >= 0");
     if (M < 1) return fail(IMPCONV_E_SIZE, "M must be >= 1");
-    const uint32_t known = IMPCONV_EXPLICIT_PADDED | IMPCONV_REV_F | IMPCONV_CONJ_G | IMPCONV_REV_OUT |
-                           IMPCONV_HERMITIAN_ADJOINT | IMPCONV_COMPENSATED;
+    const uint32_t known = IMPCONV_EXPLICIT_PADDED | IMPCONV_EXPLICIT_PRUNED | IMPCONV_REV_F | IMPCONV_CONJ_G |
+                           IMPCONV_REV_OUT | IMPCONV_HERMITIAN_ADJOINT | IMPCONV_COMPENSATED;
     if (flags & ~known) return fail(IMPCONV_E_ARG, "unknown flag bits for a 1D convolution");
+    if ((flags & IMPCONV_EXPLICIT_PRUNED) && (kind != IMPCONV_COMPLEX || !(flags & IMPCONV_EXPLICIT_PADDED)))
+        return fail(IMPCONV_E_ARG, "EXPLICIT_PRUNED qualifies EXPLICIT_PADDED (complex 1D)");
     if ((flags & IMPCONV_COMPENSATED) && (kind != IMPCONV_COMPLEX || (flags & IMPCONV_EXPLICIT_PADDED)))
         return fail(IMPCONV_E_ARG, "COMPENSATED applies to the implicit complex convolution");
     const bool adj = flags & (IMPCONV_REV_F | IMPCONV_CONJ_G | IMPCONV_REV_OUT | IMPCONV_HERMITIAN_ADJOINT);
@@ -164,7 +166,8 @@ impconv_status plan1d(int kind, int dt, int64_t batch, int64_t M, int64_t m, uin
         } else {
             p->Ne = 2 * p->N;
             if (p->Ne > kRowMax) return fail(IMPCONV_E_UNSUPPORTED, "explicit complex comparator supports m <= 4096");
-            p->work = size_t(batch) * (2 * M + 1) * p->Ne * cs;
+            // pruned form: the zero padding is read, not stored; no workspace
+            p->work = (flags & IMPCONV_EXPLICIT_PRUNED) ? 0 : size_t(batch) * (2 * M + 1) * p->Ne * cs;
         }
     } else if (kind == IMPCONV_HERMITIAN) {
         int64_t N = next_pow2(m);
@@ -316,6 +319,20 @@ static impconv_status run1d(int kind, int dtype, int64_t batch, int64_t M, int64
             }
         }
         if (err != hipSuccess) return hip_fail(err, "row kernel launch");
+        return IMPCONV_OK;
+    }
+    if (kind == IMPCONV_COMPLEX && (flags & IMPCONV_EXPLICIT_PRUNED)) {
+        // Explicit comparator with the padding fused into the loads: one
+        // size-2N cyclic convolution per row reads f and g (zero beyond m)
+        // and writes the first m outputs.
+        a.f = f; a.g = g; a.h = h;
+        a.f_row = a.g_row = M * m;
+        a.f_i = a.g_i = m;
+        a.h_row = m;
+        a.m_out = m;
+        a.scale = 1.0 / double(p.Ne);
+        err = launch_row_cyclic(dt, int(p.Ne), a, s);
+        if (err != hipSuccess) return hip_fail(err, "explicit pruned launch");
         return IMPCONV_OK;
     }
     // Explicit comparator: materialize zero-padded copies in the workspace,

@@ -65,6 +65,12 @@ def test_workspace_query_and_size_errors(L):
     assert ws(L, 0, 0, 1, 1, 1 << 20)[0] == 5          # beyond the four-step range
     assert ws(L, 1, 0, 1, 1, 16384)[0] == 0
     assert ws(L, 1, 0, 1, 1, 16385)[0] == 5
+    # EXPLICIT_PRUNED: complex 1D with EXPLICIT_PADDED only; no workspace
+    assert ws(L, 0, 0, 4, 2, 1000, 1 | (1 << 6)) == (0, 0)
+    assert ws(L, 0, 0, 4, 2, 1000, 1)[1] > 0
+    assert ws(L, 0, 0, 4, 2, 1000, 1 << 6)[0] == 1
+    assert ws(L, 1, 0, 4, 2, 1000, 1 | (1 << 6))[0] == 1
+    assert ws(L, 0, 0, 1, 1, 4097, 1 | (1 << 6))[0] == 5
 
 
 def test_call_errors_before_launch(L):

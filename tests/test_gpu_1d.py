@@ -137,6 +137,18 @@ def test_explicit_complex_matches_oracle(dt, m):
 
 
 @pytest.mark.parametrize("dt", DT)
+@pytest.mark.parametrize("m", [1, 5, 100, 2000, 4096])
+def test_pruned_explicit_complex_matches_oracle(dt, m):
+    """EXPLICIT_PADDED | EXPLICIT_PRUNED: the size-2N cyclic convolution with
+    the zero padding read rather than stored, M = 2 dot products."""
+    ic = need_gpu()
+    f, g = synth.unit_disk((3, 2, m), 45), synth.unit_disk((3, 2, m), 46)
+    h = ic.conv1d_complex(to_dev(f, dt), to_dev(g, dt), method="pruned").cpu().numpy()
+    ref = oracle.conv1d_complex(rounded(f, dt), rounded(g, dt))
+    assert rel(h, ref) < TOL[dt]
+
+
+@pytest.mark.parametrize("dt", DT)
 @pytest.mark.parametrize("m", [1, 2, 7, 300, 4000])
 def test_explicit_hermitian_matches_oracle(dt, m):
     ic = need_gpu()
