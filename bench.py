@@ -707,7 +707,58 @@ def wl_e2(args):
                 kflops_step=kflops_step, cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy())
 
 
-WORKLOADS = {"c1": wl_c1, "c2": wl_c2, "c3": wl_c3, "c4": wl_c4, "c5": wl_c5, "t2": wl_t2, "e2": wl_e2}
+def wl_t1(args):
+    """1D centered Hermitian ternary convolution (Sec. 4.2, tconv), m = 2048
+    non-negative modes, |k|^-5/6 random phase, DC = 1, batch of B."""
+    import torch
+    import paper_1008_1366_amd as ic
+    import synth
+    cdt = torch.complex64 if args.dtype == "c64" else torch.complex128
+    dt_np = np.complex64 if cdt == torch.complex64 else np.complex128
+    m, B = 2048, args.batch or 2048
+    f = synth.power_spectrum_1d(m, 5 / 6, 34, batch=B)
+    g = synth.power_spectrum_1d(m, 5 / 6, 35, batch=B)
+    e = synth.power_spectrum_1d(m, 5 / 6, 36, batch=B)
+    F, G, E = (torch.from_numpy(x).to("cuda", cdt) for x in (f, g, e))
+    cs = 8 if cdt == torch.complex64 else 16
+    run = lambda: ic.conv1d_ternary(F, G, E)
+    expl = lambda: ic.conv1d_ternary(F, G, E, method="explicit")
+    NN = 1 << int(np.ceil(np.log2(m)))
+    kbytes = {"k_conv1d_ternary": 4 * B * m * cs}
+    kflops = {"k_conv1d_ternary": B * flops_row_ternary(NN)}
+
+    def cpu_baseline(h_gpu, h_expl=None):
+        """Oracle ternary sums (O(m^2) per output) at sampled outputs of the
+        first pairs, extrapolated to whole convolutions by output count."""
+        import oracle
+        rng = synth.rng(37)
+        nb, nk = 4, max(8, args.cpu_points // 64)
+        t_or, errs = 0.0, {"implicit": [], "explicit": []}
+        for b in range(nb):
+            ks = np.unique(np.concatenate([[0, 1, m - 1], rng.integers(0, m, nk)]))
+            fr, gr, er = (np.asarray(x[b].astype(dt_np), np.complex128) for x in (f, g, e))
+            t0 = time.perf_counter()
+            ref = oracle.conv1d_ternary_at(fr, gr, er, ks)
+            t_or += time.perf_counter() - t0
+            for key, h in (("implicit", h_gpu), ("explicit", h_expl)):
+                if h is not None:
+                    errs[key].append(float(np.linalg.norm(h[b][ks] - ref) / np.linalg.norm(ref)))
+            nk_done = len(ks)
+        per_out = t_or / (nb * nk_done)
+        err = {k: {"max": max(v), "median": float(np.median(v)), "pairs": len(v)} for k, v in errs.items() if v}
+        return {"value": 1.0 / (per_out * m), "unit": "convs/s", "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": f"{nk_done} sampled outputs of each of {nb} convolutions, direct FP64 ternary sums "
+                          f"({t_or:.2f} s), extrapolated to {m} outputs per convolution"}, err
+
+    cfg = {"workload": f"1D centered Hermitian ternary implicit dealiased convolution m={m}, batch {B}, "
+                       f"{'complex64' if cdt == torch.complex64 else 'complex128'}",
+           "m": m, "batch": B, "dtype": args.dtype}
+    return dict(run=run, explicit=expl, convs=B, step_bytes=4 * B * m * cs, kbytes=kbytes, kflops=kflops,
+                cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy())
+
+
+WORKLOADS = {"c1": wl_c1, "c2": wl_c2, "c3": wl_c3, "c4": wl_c4, "c5": wl_c5, "t1": wl_t1, "t2": wl_t2,
+             "e2": wl_e2}
 
 
 def main():
