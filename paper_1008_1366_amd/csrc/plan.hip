@@ -49,6 +49,8 @@ std::mutex c_mu;
 std::deque<CachedRagged> c_plans;
 constexpr size_t kCacheMax = 16;
 
+// The caller holds c_mu until it has finished with *out: another thread's
+// lookup may evict (destroy) any plan it did not just return.
 impconv_status cached_ragged(int dtype, int64_t npairs, const int64_t* m_host, const int64_t* off_host,
                              impconv_ragged_plan** out)
 {
@@ -57,7 +59,6 @@ impconv_status cached_ragged(int dtype, int64_t npairs, const int64_t* m_host, c
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    std::lock_guard<std::mutex> lk(c_mu);
     for (auto it = c_plans.begin(); it != c_plans.end(); ++it) {
         if (it->device == dev && it->dtype == dtype && int64_t(it->m.size()) == npairs &&
             std::equal(it->m.begin(), it->m.end(), m_host) && std::equal(it->off.begin(), it->off.end(), off_host)) {
@@ -148,6 +149,7 @@ impconv_status impconv_conv1d_complex_ragged_workspace(int dtype, int64_t npairs
 {
     if (!bytes) return fail(IMPCONV_E_ARG, "bytes is NULL");
     impconv_ragged_plan* p = nullptr;
+    std::lock_guard<std::mutex> lk(c_mu);
     impconv_status st = cached_ragged(dtype, npairs, m_host, offset_host, &p);
     if (st) return st;
     return impconv_ragged_workspace(p, bytes);
@@ -158,6 +160,8 @@ impconv_status impconv_conv1d_complex_ragged(int dtype, int64_t npairs, const in
                                              void* work, size_t work_bytes, uint32_t flags, void* stream)
 {
     impconv_ragged_plan* p = nullptr;
+    // held through the execution's enqueue, so that no other call evicts p
+    std::lock_guard<std::mutex> lk(c_mu);
     impconv_status st = cached_ragged(dtype, npairs, m_host, offset_host, &p);
     if (st) return st;
     return impconv_ragged_execute(p, f, g, h, work, work_bytes, flags, stream);
