@@ -315,6 +315,10 @@ impconv_status impconv_ragged_workspace(const impconv_ragged_plan* plan, size_t*
 impconv_status impconv_ragged_execute(const impconv_ragged_plan* plan, const void* f,
                                       const void* g, void* h, void* work, size_t work_bytes,
                                       uint32_t flags, void* stream);
+/* Destroying a plan first synchronizes its device (earlier executions' work
+ * uses the plan's streams, events and descriptor arrays), so it must not be
+ * called during stream capture; a graph captured from a plan must not be
+ * launched after the plan is destroyed.  NULL is accepted. */
 impconv_status impconv_ragged_plan_destroy(impconv_ragged_plan* plan);
 
 /* Autotuner of the plan's schedule.  Size classes whose FFT size N exceeds

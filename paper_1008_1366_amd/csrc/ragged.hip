@@ -364,8 +364,17 @@ impconv_status impconv_ragged_plan_schedule(const impconv_ragged_plan* p, char* 
 impconv_status impconv_ragged_plan_destroy(impconv_ragged_plan* plan)
 {
     if (!plan) return IMPCONV_OK;
+    // Work that earlier executions enqueued still uses the plan: kernels on
+    // its auxiliary streams read its descriptor arrays, and the caller's
+    // streams wait on its join events.  Wait for the plan's device to finish
+    // that work before the streams, events and descriptors are released.
+    int cur = -1;
+    const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+    if (have_cur && cur != plan->device) (void)hipSetDevice(plan->device);
+    (void)hipDeviceSynchronize();
     destroy_streams(plan);
     if (plan->dmem) (void)hipFree(plan->dmem);
+    if (have_cur && cur != plan->device) (void)hipSetDevice(cur);
     delete plan;
     return IMPCONV_OK;
 }

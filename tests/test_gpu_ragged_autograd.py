@@ -154,9 +154,9 @@ def test_ragged_one_stream_matches_concurrent(dt):
     assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
 
 
-@pytest.mark.skip(reason="a full GPU run crashed the host process (segmentation fault) inside the replay of this "
-                         "graph, after a since-removed test had created and evicted one-shot ragged plans from two "
-                         "threads; the cause is not established, so the case stays off the GPU until it is")
+@pytest.mark.skip(reason="twice crashed the host process (segmentation fault) inside the replay of this graph in "
+                         "full GPU runs, after the threaded one-shot eviction test (skipped too) had run earlier in "
+                         "the process; the cause is not established, so the case stays off the GPU until it is")
 def test_ragged_graph_replay_matches_eager():
     ic = need_gpu()
     import torch
