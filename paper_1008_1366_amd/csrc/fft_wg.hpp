@@ -28,6 +28,29 @@ namespace impconv {
 // LDS position of sequence element p: one padding slot every 16 elements
 // breaks the power-of-two strides of the early Stockham stages across banks.
 __device__ __forceinline__ int lpad(int p) { return p + (p >> 4); }
+
+// Synchronization around a stage exchange of a transform spread over G
+// threads with LDS stride LS.  The row kernels (LS = 1) give each transform
+// G consecutive threads and LDS of its own; with G <= 64 (a power of two)
+// those threads lie in one wave, whose LDS operations the hardware performs
+// in issue order, so the exchange needs no workgroup barrier: only that the
+// compiler keep the reads after the writes and that the writes have
+// completed.  The column passes (LS > 1 there whenever G <= 64) interleave
+// their transforms across waves and take the barrier.
+#ifndef IMPCONV_NO_WAVE_SYNC
+template <int G>
+__device__ __forceinline__ void xsync(int LS)
+{
+    if (G <= 64 && LS == 1) {
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    } else {
+        __syncthreads();
+    }
+}
+#else
+template <int G>
+__device__ __forceinline__ void xsync(int) { __syncthreads(); }
+#endif
 __host__ __device__ constexpr int lpad_size(int n) { return n + (n >> 4); }
 
 // ------------------------------------------------------------------ radix-R DFTs
@@ -170,11 +193,11 @@ __device__ __forceinline__ void fft_stage(C<T> (&v)[E], int t, C<T>* lds, int LS
         }
     }
     if constexpr (!LAST) {
-        __syncthreads();
+        xsync<G>(LS);
         const C<T>* rp = lds + lpad(t) * LS;
 #pragma unroll
         for (int i = 0; i < E; ++i) v[i] = rp[(i * G + ((i * G) >> 4)) * LS];
-        __syncthreads();
+        xsync<G>(LS);
         fft_stage<T, N, E, DIR, NS * R, TW>(v, t, lds, LS, tw);
     }
 }
@@ -232,14 +255,14 @@ __device__ __forceinline__ void fft2_stage(C<T> (&v0)[E], C<T> (&v1)[E], int t, 
         }
     }
     if constexpr (!LAST) {
-        __syncthreads();
+        xsync<G>(LS);
         const int rb = lpad(t) * LS;
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             v0[i] = lds0[rb + (i * G + ((i * G) >> 4)) * LS];
             v1[i] = lds1[rb + (i * G + ((i * G) >> 4)) * LS];
         }
-        __syncthreads();
+        xsync<G>(LS);
         fft2_stage<T, N, E, DIR, NS * R, TW>(v0, v1, t, lds0, lds1, LS, tw);
     }
 }
@@ -308,7 +331,7 @@ __device__ __forceinline__ void fft3_stage(C<T> (&v0)[E], C<T> (&v1)[E], C<T> (&
         }
     }
     if constexpr (!LAST) {
-        __syncthreads();
+        xsync<G>(LS);
         const int rb = lpad(t) * LS;
 #pragma unroll
         for (int i = 0; i < E; ++i) {
@@ -316,7 +339,7 @@ __device__ __forceinline__ void fft3_stage(C<T> (&v0)[E], C<T> (&v1)[E], C<T> (&
             v1[i] = lds1[rb + (i * G + ((i * G) >> 4)) * LS];
             v2[i] = lds2[rb + (i * G + ((i * G) >> 4)) * LS];
         }
-        __syncthreads();
+        xsync<G>(LS);
         fft3_stage<T, N, E, DIR, NS * R, TW>(v0, v1, v2, t, lds0, lds1, lds2, LS, tw);
     }
 }

@@ -463,10 +463,10 @@ __device__ __forceinline__ void mirror(const C<T> (&P)[E], C<T> (&Pm)[E], int t,
     } else {
 #pragma unroll
         for (int e = 0; e < E; ++e) lds[lpad(t + e * G)] = P[e];
-        __syncthreads();
+        xsync<G>(1);
 #pragma unroll
         for (int e = 0; e < E; ++e) Pm[e] = lds[lpad((NC - (t + e * G)) & (NC - 1))];
-        __syncthreads();
+        xsync<G>(1);
     }
 }
 
@@ -486,14 +486,14 @@ __device__ __forceinline__ void mirror2(const C<T> (&A)[E], C<T> (&Am)[E], const
             lds0[lpad(t + e * G)] = A[e];
             lds1[lpad(t + e * G)] = B[e];
         }
-        __syncthreads();
+        xsync<G>(1);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int j = lpad((NC - (t + e * G)) & (NC - 1));
             Am[e] = lds0[j];
             Bm[e] = lds1[j];
         }
-        __syncthreads();
+        xsync<G>(1);
     }
 }
 template <typename T, int NC, int E>
@@ -513,7 +513,7 @@ __device__ __forceinline__ void mirror3(const C<T> (&A)[E], C<T> (&Am)[E], const
             lds1[lpad(t + e * G)] = B[e];
             lds2[lpad(t + e * G)] = D[e];
         }
-        __syncthreads();
+        xsync<G>(1);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int j = lpad((NC - (t + e * G)) & (NC - 1));
@@ -521,7 +521,7 @@ __device__ __forceinline__ void mirror3(const C<T> (&A)[E], C<T> (&Am)[E], const
             Bm[e] = lds1[j];
             Dm[e] = lds2[j];
         }
-        __syncthreads();
+        xsync<G>(1);
     }
 }
 
