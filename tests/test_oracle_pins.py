@@ -367,6 +367,72 @@ def test_hermitian_nd_symmetrization_reading(orc):
     assert rel(Hf, np.conj(Hf[::-1, ::-1, ::-1])) < 1e-15
 
 
+def expand_projected_np(u, m):
+    """Full centered field under the NO_SYMMETRIZE reading, written with numpy
+    array operations (independent of the oracle's per-point loop): off the
+    k_last = 0 hyperplane the stored value or the conjugate of its mirror; on
+    it the Hermitian projection (U_k + conj U_{-k}) / 2 of the stored plane
+    (concluding remarks: the routine reads what a real transform of an
+    unsymmetrized plane represents)."""
+    nd = len(m)
+    n = u.shape
+    # dense centered array D[j] = stored value at wavenumber j - (m - 1) for
+    # k_last >= 0 (zero elsewhere), gathered by slicing
+    sl = tuple(slice(n[d] - m[d] - (m[d] - 1), n[d] - m[d] + m[d]) for d in range(nd - 1))
+    pos = u[sl + (slice(0, m[-1]),)]                  # k_last = 0..m-1
+    full = np.zeros(tuple(2 * x - 1 for x in m), complex)
+    full[(Ellipsis, slice(m[-1] - 1, None))] = pos
+    # mirror: U_{-k} = conj U_k for k_last > 0 (flip every axis)
+    mir = np.conj(pos[(slice(None, None, -1),) * (nd - 1) + (slice(m[-1] - 1, 0, -1),)])
+    full[(Ellipsis, slice(0, m[-1] - 1))] = mir
+    plane = pos[..., 0]
+    full[..., m[-1] - 1] = 0.5 * (plane + np.conj(plane[(slice(None, None, -1),) * (nd - 1)]))
+    return full
+
+
+@pytest.mark.parametrize("m,n", [((3, 4), (5, 4)), ((4, 4), (8, 5)), ((3, 3, 4), (6, 5, 5)),
+                                 ((2, 3, 2), (3, 6, 2))])
+def test_hermitian_nd_no_symmetrize_projection(orc, m, n):
+    """NO_SYMMETRIZE reading: the k_last = 0 hyperplane enters as its Hermitian
+    projection.  The oracle (symmetrize=False) must equal scipy's direct
+    convolution of fields expanded by the numpy projection above, for the
+    binary and the ternary sums; on already-symmetric input both readings
+    agree, and on an unsymmetrized plane they differ."""
+    f, g, e = herm_storage(m, n, 141), herm_storage(m, n, 142), herm_storage(m, n, 143)
+    F, G, E = expand_projected_np(f, m), expand_projected_np(g, m), expand_projected_np(e, m)
+    assert rel(orc.hermitian_expand(f, m, symmetrize=False), F) < 1e-15
+    nd = len(m)
+    full2 = scipy.signal.convolve(F, G, method="direct")
+    full3 = scipy.signal.convolve(full2, E, method="direct")
+    h2 = orc.convnd_hermitian(f, g, m, symmetrize=False)
+    h3 = orc.convnd_ternary(f, g, e, m, symmetrize=False)
+    for idx in np.ndindex(*n):
+        k = [idx[d] - (n[d] - m[d]) if d < nd - 1 else idx[d] for d in range(nd)]
+        if not (all(abs(k[d]) <= m[d] - 1 for d in range(nd)) and k[-1] >= 0):
+            assert h2[idx] == 0 and h3[idx] == 0
+            continue
+        r2 = full2[tuple(k[d] + 2 * (m[d] - 1) for d in range(nd))]
+        r3 = full3[tuple(k[d] + 3 * (m[d] - 1) for d in range(nd))]
+        assert abs(h2[idx] - r2) < 1e-12 * max(1, abs(r2))
+        assert abs(h3[idx] - r3) < 1e-12 * max(1, abs(r3))
+    # the two readings differ on this (unsymmetrized) input ...
+    assert rel(h2, orc.convnd_hermitian(f, g, m)) > 1e-3
+    # ... and agree once the plane is Hermitian (symmetrized by the numpy rule)
+    fs, gs, es = (herm_from_full(expand_np(x, m), m, n) for x in (f, g, e))
+    assert rel(orc.convnd_hermitian(fs, gs, m, symmetrize=False), orc.convnd_hermitian(fs, gs, m)) < 1e-14
+    assert rel(orc.convnd_ternary(fs, gs, es, m, symmetrize=False), orc.convnd_ternary(fs, gs, es, m)) < 1e-14
+
+
+def herm_from_full(full, m, n):
+    """Stored half (storage extents n, zero slots 0) of a dense centered field."""
+    nd = len(m)
+    u = np.zeros(n, complex)
+    sl = tuple(slice(n[d] - m[d] - (m[d] - 1), n[d]) for d in range(nd - 1))
+    u[sl + (slice(0, m[-1]),)] = full[(Ellipsis, slice(m[-1] - 1, None))][
+        tuple(slice(0, 2 * m[d] - 1) for d in range(nd - 1))]
+    return u
+
+
 def test_hermitian_2d_separable(orc):
     """F = A (x) B with A, B Hermitian-symmetric 1D fields: the 2D centered
     Hermitian sum factors into a centered 1D sum in x and a Hermitian 1D sum
