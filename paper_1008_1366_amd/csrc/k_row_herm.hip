@@ -63,6 +63,22 @@ hipError_t launch_row_realcyclic(int dt, int NC, const RowArgs& a, hipStream_t s
     return hipErrorInvalidValue;
 }
 
+template <typename T, int NN>
+static bool tern_accumulates()
+{
+    return !regs_fit<T>(5, row_E<T, 1>(NN), row_block<T, 1>(NN));
+}
+
+bool row_ternary_accumulates(int dt, int NN)
+{
+    switch (NN) {
+#define X(n) case n: return dt ? tern_accumulates<double, n>() : tern_accumulates<float, n>();
+        IMPCONV_POW2_CASES(X)
+#undef X
+    }
+    return true;
+}
+
 hipError_t launch_row_ternary(int dt, int NN, const RowArgs& a, hipStream_t s)
 {
     switch (NN) {

@@ -18,6 +18,10 @@ hipError_t launch_row_cyclic(int dt, int N, const RowArgs& a, hipStream_t s);
 hipError_t launch_row_complex_comp(int N, const RowArgs& a, hipStream_t s);
 hipError_t launch_row_hermitian(int dt, int NC, const RowArgs& a, hipStream_t s);
 hipError_t launch_row_ternary(int dt, int NN, const RowArgs& a, hipStream_t s);
+// Whether the ternary row kernel of size NN accumulates its result in h
+// residue by residue (rows too long for registers); otherwise each row is
+// read completely before any of its outputs is written, so h may be f.
+bool row_ternary_accumulates(int dt, int NN);
 hipError_t launch_row_realcyclic(int dt, int NC, const RowArgs& a, hipStream_t s);
 // General p/q rule: block size NP <= kPqMax (power of two), P in {2, 3};
 // a.q residues, a.twq = zeta_{q NP} table.

@@ -188,7 +188,24 @@ struct PlanND {
     int64_t batch, M;
     uint32_t flags;
     size_t work;
+    int64_t ychunk;             // 3D: (b, x') planes per y-stage chunk
 };
+
+// 3D: the y backward pass, the innermost rows and the y forward pass run
+// over chunks of the (b, x') planes, one chunk after another, with one set of
+// y-residue arrays sized for a chunk.  kYChunks chunks (fewer when there are
+// fewer planes) keep that region at 1 / kYChunks of the full y-residue
+// volume, which brings the 3D work memory under the explicitly padded
+// method's storage (Sec. 3.4 storage counts) while every launch still spans
+// many planes.
+#ifndef IMPCONV_3D_YCHUNKS
+#define IMPCONV_3D_YCHUNKS 4
+#endif
+constexpr int64_t kYChunks = IMPCONV_3D_YCHUNKS;
+int64_t y_chunk_planes(int64_t planes)
+{
+    return std::max<int64_t>(1, (planes + kYChunks - 1) / kYChunks);
+}
 
 impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t* n, int64_t batch,
                       int64_t M, uint32_t flags, PlanND* p)
@@ -269,16 +286,23 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
             return fail(IMPCONV_E_UNSUPPORTED, "explicit ternary 2D comparator supports m0 <= 1024, m1 <= 4096");
         p->work = size_t(3) * batch * P0 * L * cs;
     } else if (kind == IMPCONV_TERNARY) {
-        // x residues of f, g, e (2 each, 2 Np0 rows) and the two row outputs
-        p->work = size_t(8) * batch * 2 * p->Np[0] * n[1] * cs;
+        // x residues of f, g, e (2 each, 2 Np0 rows); the rows write their
+        // result over the residues of f unless the row kernel accumulates
+        // in its output (then two more arrays)
+        const int extra = row_ternary_accumulates(dt, int(p->Np[1])) ? 2 : 0;
+        p->work = size_t(6 + extra) * batch * 2 * p->Np[0] * n[1] * cs;
     } else if (nd == 2) {
         // residue arrays [b][x'][i][y] for f and g
         p->work = size_t(2) * R * batch * M * p->Np[0] * n[1] * cs;
     } else {
+        // x-residue arrays of f and g (the y-forward output of each plane is
+        // written back into its own x-residue plane), plus the y-residue
+        // arrays of one chunk of planes, reused by every chunk and x residue
         const size_t X = size_t(2) * R * batch * M * p->Np[0] * n[1] * n[2];
-        const size_t Y = size_t(2) * R * R * batch * M * p->Np[0] * p->Np[1] * n[2];
-        const size_t Q = size_t(R) * batch * p->Np[0] * n[1] * n[2];
-        p->work = (X + Y + Q) * cs;
+        const int64_t planes = batch * p->Np[0];
+        p->ychunk = y_chunk_planes(planes);
+        const size_t Y = size_t(2) * R * p->ychunk * M * p->Np[1] * n[2];
+        p->work = (X + Y) * cs;
     }
     return IMPCONV_OK;
 }
@@ -472,7 +496,11 @@ impconv_status run2d_ternary(int dt, int64_t batch, const int64_t* m, const int6
     void* X[3][2];
     for (int q = 0; q < 3; ++q)
         for (int r = 0; r < 2; ++r) X[q][r] = w + (2 * q + r) * arr;
-    void* Q[2] = {w + 6 * arr, w + 7 * arr};
+    void* Q[2] = {X[0][0], X[0][1]};
+    if (row_ternary_accumulates(dt, int(p.Np[1]))) {
+        Q[0] = w + 6 * arr;
+        Q[1] = w + 7 * arr;
+    }
     const void* src[3] = {f, g, e};
     for (int q = 0; q < 3; ++q) {
         ColArgs a = col_args(tb, dt);
@@ -842,19 +870,32 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
                             ha ? 1 : 0))) return st;
         return IMPCONV_OK;
     }
-    // 3D
+    // 3D (Sec. 3.4): x backward pass into the x-residue arrays Xf[rx], Xg[rx]
+    // ([b][x'][i][y][z]); then, per x residue and per chunk of (b, x')
+    // planes, the y backward pass into the chunk's y-residue arrays
+    // ([plane][y'][i][z]), the z rows (M-dot, in place in Yf), and the y
+    // forward pass, whose result ([plane][y][z]) overwrites term 0 of the
+    // plane in Xf[rx] (every element of the plane has been read by then);
+    // last, the x forward pass over term 0 of the three Xf[rx].
     const int64_t N0 = p.Np[0], N1 = p.Np[1];
     const int64_t n0 = n[0], n1 = n[1], n2 = n[2], m0 = m[0], m1 = m[1], m2 = m[2];
-    const size_t xa = size_t(batch) * M * N0 * n1 * n2 * cs;      // one x-residue array
-    const size_t ya = size_t(batch) * M * N0 * N1 * n2 * cs;       // one (x, y)-residue array
-    const size_t qa = size_t(batch) * N0 * n1 * n2 * cs;           // one y-forward output
+    const int64_t plane = M * n1 * n2;                            // elements of one x-residue plane
+    const size_t xa = size_t(batch) * N0 * plane * cs;            // one x-residue array
+    const int64_t nplanes = batch * N0;
+    const int64_t P = p.ychunk;                                   // planes per chunk
+    const size_t ya = size_t(P) * M * N1 * n2 * cs;               // one y-residue array of a chunk
     void* Xf[3]; void* Xg[3];
     for (int r = 0; r < 3; ++r) {
         Xf[r] = w + (r < R ? r : R - 1) * xa;
         Xg[r] = w + (R + (r < R ? r : R - 1)) * xa;
     }
     char* yb = w + 2 * R * xa;
-    char* qb = yb + 2 * R * R * ya;
+    void* Yf[3]; void* Yg[3];
+    for (int ry = 0; ry < 3; ++ry) {
+        const int rr = ry < R ? ry : R - 1;
+        Yf[ry] = yb + size_t(rr) * ya;
+        Yg[ry] = yb + size_t(R + rr) * ya;
+    }
     // x pass over columns (y, z): valid columns skip the zero slots of y and z
     const int ylo = herm ? int(n1 - (2 * m1 - 1)) : 0;
     const int64_t mask_nz = herm ? n2 : 0;
@@ -862,55 +903,44 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
                         int(n1 - m1), int(n1), mask_nz, ylo, int(n1), int(m2), s, fs_f | ha))) return st;
     if ((st = outer_bwd(tb, p, g, Xg, batch, M * n0 * n1 * n2, n0, m0, N0, n1 * n2, sym ? 2 : 0, n2,
                         int(n1 - m1), int(n1), mask_nz, ylo, int(n1), int(m2), s, fs_g))) return st;
-    void* Q[3];
+    // y backward pass of np planes: slabs (plane, i) of [n1][n2] -> [plane][y'][i][n2]
+    auto ypass = [&](const void* src, void* const* dst, int64_t np, uint32_t fsf) -> impconv_status {
+        ColArgs c = col_args(tb, dt);
+        c.fsflags = fsf;
+        c.in[0] = src;
+        for (int r = 0; r < 3; ++r) c.out[r] = dst[r];
+        c.nslab = np * M;
+        c.nsub = M;
+        c.in_bs = M * n1 * n2;
+        c.in_bs2 = n1 * n2;
+        c.out_bs = N1 * M * n2;
+        c.out_bs2 = n2;
+        c.ncols = n2;
+        c.in_ld = n2;
+        c.out_ld = M * n2;
+        c.n_in = int(n1);
+        c.m = int(m1);
+        c.off_in = int(n1 - m1);
+        if (herm) { c.mask_nz = n2; c.mask_ylo = 0; c.mask_yhi = 1; c.mask_zhi = int(m2); }
+        HIPCHK(launch_col(dt, int(N1), herm ? kCenBwd : kPadBwd, 1, c, s), "y backward pass");
+        return IMPCONV_OK;
+    };
     for (int rx = 0; rx < R; ++rx) {
-        void* Yf[3]; void* Yg[3];
-        for (int ry = 0; ry < 3; ++ry) {
-            const int rr = ry < R ? ry : R - 1;
-            Yf[ry] = yb + (size_t(rx) * R + rr) * ya;
-            Yg[ry] = yb + (size_t(R) * R + rx * R + rr) * ya;
-        }
-        // y pass: slabs (b, x') of [n1][M][n2] -> [b, x'][y'][M][n2]
-        ColArgs a = col_args(tb, dt);
-        a.in[0] = nullptr;
-        PlanND py = p;
-        py.Np[0] = N1;
-        const int64_t nplanes = batch * N0;
-        // input layout after the x pass: [b][x'][i][y][z] -> slab (plane, i), rows y (ld n2)
-        auto ypass = [&](const void* src, void* const* dst, uint32_t fsf) -> impconv_status {
-            ColArgs c = col_args(tb, dt);
-            c.fsflags = fsf;
-            c.in[0] = src;
-            for (int r = 0; r < 3; ++r) c.out[r] = dst[r];
-            c.nslab = nplanes * M;
-            c.nsub = M;
-            c.in_bs = M * n1 * n2;
-            c.in_bs2 = n1 * n2;
-            c.out_bs = N1 * M * n2;
-            c.out_bs2 = n2;
-            c.ncols = n2;
-            c.in_ld = n2;
-            c.out_ld = M * n2;
-            c.n_in = int(n1);
-            c.m = int(m1);
-            c.off_in = int(n1 - m1);
-            if (herm) { c.mask_nz = n2; c.mask_ylo = 0; c.mask_yhi = 1; c.mask_zhi = int(m2); }
-            HIPCHK(launch_col(dt, int(N1), herm ? kCenBwd : kPadBwd, 1, c, s), "y backward pass");
-            return IMPCONV_OK;
-        };
-        if ((st = ypass(Xf[rx], Yf, fs_f))) return st;
-        if ((st = ypass(Xg[rx], Yg, cb))) return st;
-        for (int ry = 0; ry < R; ++ry)
-            if ((st = inner_rows(tb, p, Yf[ry], Yg[ry], nplanes * N1, s, rowfl))) return st;
-        // y forward: [plane][y'][M][n2] (3 residues) -> Q[rx] [plane][n1][n2]
-        Q[rx] = qb + size_t(rx) * qa;
-        {
+        for (int64_t p0 = 0; p0 < nplanes; p0 += P) {
+            const int64_t np = std::min(P, nplanes - p0);
+            char* xf = static_cast<char*>(Xf[rx]) + size_t(p0) * plane * cs;
+            const char* xg = static_cast<const char*>(Xg[rx]) + size_t(p0) * plane * cs;
+            if ((st = ypass(xf, Yf, np, fs_f))) return st;
+            if ((st = ypass(xg, Yg, np, cb))) return st;
+            for (int ry = 0; ry < R; ++ry)
+                if ((st = inner_rows(tb, p, Yf[ry], Yg[ry], np * N1, s, rowfl))) return st;
+            // y forward: [plane][y'][i = 0][n2] (R residues) -> term 0 of the plane in Xf[rx]
             ColArgs c = col_args(tb, dt);
             for (int r = 0; r < 3; ++r) c.in[r] = Yf[r];
-            c.out[0] = Q[rx];
-            c.nslab = nplanes;
+            c.out[0] = xf;
+            c.nslab = np;
             c.in_bs = N1 * M * n2;
-            c.out_bs = n1 * n2;
+            c.out_bs = plane;
             c.ncols = n2;
             c.in_ld = M * n2;
             c.out_ld = n2;
@@ -921,14 +951,11 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
             c.fsflags = fs_o;
             HIPCHK(launch_col(dt, int(N1), herm ? kCenFwd : kPadFwd, 1, c, s), "y forward pass");
         }
-        (void)a;
-        (void)py;
     }
-    if (!herm) Q[2] = Q[1];
-    // x forward: Q[rx] [b][x'][n1 n2] -> h [b][n0][n1 n2]
+    // x forward: term 0 of Xf[rx], [b][x'][(i = 0) y z] -> h [b][n0][n1 n2]
     PlanND px = p;
     px.M = 1;
-    if ((st = outer_fwd(tb, px, Q, h, batch, N0 * n1 * n2, n1 * n2, n0, m0, N0, n1 * n2, s, fs_o | ha,
+    if ((st = outer_fwd(tb, px, Xf, h, batch, N0 * plane, plane, n0, m0, N0, n1 * n2, s, fs_o | ha,
                         ha ? 2 : 0, n2, int(n1 - m1), int(n1)))) return st;
     return IMPCONV_OK;
 }
