@@ -292,14 +292,19 @@ impconv_status impconv_conv2d_ternary(int dtype, int64_t batch, const int64_t* m
  * arrays (pairs must not overlap).  The plan copies the descriptors to the
  * device once (synchronously, at creation) and groups pairs by FFT size;
  * executing it launches nothing but kernels, so it may be captured in a
- * hipGraph.  The size classes run concurrently: the plan owns three
- * auxiliary streams (default priority) and events, execute forks them from
- * `stream` with an event and joins them back into it, so all work of the
+ * hipGraph.  The size classes run concurrently: the device has three
+ * auxiliary streams (default priority) and events, created with its first
+ * ragged plan and kept until the process ends (shared by all plans of the
+ * device); execute forks them from `stream` with an event and joins them
+ * back into it -- also when a launch fails part way -- so all work of the
  * call is ordered after what `stream` had queued and before what it queues
  * next; each class with N > 8192 uses a region of the workspace of its own.
- * Calls on one plan from several host threads are serialized while they
- * enqueue (a mutex of the plan); executions that may overlap on the GPU need
- * distinct workspaces.  Only impconv_ragged_plan_autotune changes a plan
+ * Calls from several host threads are serialized while they enqueue (a
+ * mutex of the plan and one of the device's auxiliary streams); executions
+ * that may overlap on the GPU need distinct workspaces.  While one thread
+ * captures an execution, no other thread may execute a ragged plan on the
+ * same device without IMPCONV_ONE_STREAM (the auxiliary streams are part of
+ * the capture until it ends).  Only impconv_ragged_plan_autotune changes a plan
  * (its schedule, never its results' definition).  REV_F / CONJ_G / REV_OUT apply per pair
  * as in impconv_conv1d_complex.  IMPCONV_ONE_STREAM runs the size classes one
  * after another on `stream` alone (no fork or join; the auxiliary streams
@@ -315,10 +320,12 @@ impconv_status impconv_ragged_workspace(const impconv_ragged_plan* plan, size_t*
 impconv_status impconv_ragged_execute(const impconv_ragged_plan* plan, const void* f,
                                       const void* g, void* h, void* work, size_t work_bytes,
                                       uint32_t flags, void* stream);
-/* Destroying a plan first synchronizes its device (earlier executions' work
- * uses the plan's streams, events and descriptor arrays), so it must not be
- * called during stream capture; a graph captured from a plan must not be
- * launched after the plan is destroyed.  NULL is accepted. */
+/* Destroying a plan first waits (on the host) for the plan's earlier eager
+ * executions to finish -- each execution records a completion event on its
+ * stream, and destruction waits for the last one of every stream -- since
+ * their kernels read the plan's descriptor arrays; it waits for nothing
+ * else on the device and destroys no stream.  A graph captured from a plan
+ * must not be launched after the plan is destroyed.  NULL is accepted. */
 impconv_status impconv_ragged_plan_destroy(impconv_ragged_plan* plan);
 
 /* Autotuner of the plan's schedule.  Size classes whose FFT size N exceeds
@@ -385,8 +392,9 @@ impconv_status impconv_plan_destroy(impconv_plan* plan);
  * in a process-wide cache (16 most recently used layouts) keyed by device,
  * dtype and the contents of m_host / offset_host.  The first call with a
  * layout creates the plan (synchronous descriptor upload: not under stream
- * capture); later calls only launch kernels.  Evicting a plan synchronizes
- * the device.  Errors as impconv_ragged_plan_create and
+ * capture); later calls only launch kernels.  Evicting a plan waits for
+ * that plan's earlier executions (impconv_ragged_plan_destroy).  Errors as
+ * impconv_ragged_plan_create and
  * impconv_ragged_execute. */
 impconv_status impconv_conv1d_complex_ragged_workspace(int dtype, int64_t npairs, const int64_t* m_host,
                                                        const int64_t* offset_host, size_t* bytes);

@@ -364,6 +364,25 @@ def timing_report() -> list:
     return json.loads(buf.value.decode() or "[]")
 
 
+# Ragged plans whose destruction was requested (by the garbage collector)
+# while the current stream was being captured: destroying a plan waits on
+# the host for its executions, which a capture must not see, so they are
+# destroyed at the next plan creation or destruction outside a capture.
+_deferred_plans: list = []
+
+
+def _capturing() -> bool:
+    try:
+        return torch.cuda.is_available() and torch.cuda.is_current_stream_capturing()
+    except Exception:
+        return False
+
+
+def _destroy_deferred() -> None:
+    while _deferred_plans and not _capturing():
+        _lib.impconv_ragged_plan_destroy(_deferred_plans.pop())
+
+
 class RaggedPlan:
     """Uneven-length batch of complex 1D convolutions packed in one array:
     pair j uses elements offsets[j] .. offsets[j] + ms[j] - 1.  With
@@ -385,6 +404,8 @@ class RaggedPlan:
         self.dense = bool(len(self.ms) and self.offsets[order][0] == 0 and np.all(self.offsets[order][1:] == ends[:-1]))
         dt = C64 if dtype == torch.complex64 else C128
         self._h = ctypes.c_void_p()
+        lib()
+        _destroy_deferred()
         with torch.cuda.device(self.device):
             _check(lib().impconv_ragged_plan_create(dt, len(self.ms), self.ms.ctypes.data_as(_p),
                                                     self.offsets.ctypes.data_as(_p), ctypes.byref(self._h)),
@@ -436,7 +457,11 @@ class RaggedPlan:
     def __del__(self):
         try:
             if self._h and _lib is not None:
-                _lib.impconv_ragged_plan_destroy(self._h)
+                if _capturing():
+                    _deferred_plans.append(self._h)
+                else:
+                    _lib.impconv_ragged_plan_destroy(self._h)
+                    _destroy_deferred()
         except Exception:
             pass
 

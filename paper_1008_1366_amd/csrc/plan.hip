@@ -75,7 +75,7 @@ impconv_status cached_ragged(int dtype, int64_t npairs, const int64_t* m_host, c
     c_plans.push_front({dev, dtype, std::vector<int64_t>(m_host, m_host + npairs),
                         std::vector<int64_t>(off_host, off_host + npairs), p});
     while (c_plans.size() > kCacheMax) {
-        // (destroying a plan waits for the work that still uses it)
+        // (destroying a plan waits for its own executions still in flight)
         (void)impconv_ragged_plan_destroy(c_plans.back().plan);
         c_plans.pop_back();
     }

@@ -45,29 +45,73 @@ struct impconv_ragged_plan {
     void* dmem;
     size_t work;
     int device;
-    // The size classes run concurrently: the caller's stream forks to the
-    // auxiliary streams through an event and joins them back at the end, so
-    // the short fused classes overlap the long multi-pass ones (one launch
-    // of a short class fills only part of the chip).  Default priority.
-    std::vector<hipStream_t> aux;
-    std::vector<hipEvent_t> join;
-    hipEvent_t fork;
-    // held while an execution (or the autotuner) enqueues its work: the
-    // fork / join events and the auxiliary streams are shared by every call
+    // Completion events, one per stream the plan was executed on, recorded
+    // after each execution's join: destruction waits for these (the work
+    // that reads the plan's descriptor arrays) rather than for the device.
+    std::map<hipStream_t, hipEvent_t> done;
+    // held while an execution (or the autotuner) enqueues its work or
+    // changes the schedule, and by destruction
     std::mutex mu;
 };
 
 namespace {
 constexpr int kRaggedLanes = 4;  // the caller's stream and three auxiliary streams
 
-void destroy_streams(impconv_ragged_plan* p)
+// The size classes of a plan run concurrently: the caller's stream forks to
+// three auxiliary streams through an event and joins them back at the end,
+// so the short fused classes overlap the long multi-pass ones (one launch of
+// a short class fills only part of the chip).  The auxiliary streams
+// (default priority) and the fork / join events belong to the device, not to
+// a plan: they are created once, on the first plan of the device, and kept
+// until the process ends, so that creating and destroying plans creates and
+// destroys no streams.  `mu` serializes the executions that enqueue through
+// them (the events are re-recorded by every execution).
+struct Lanes {
+    hipStream_t aux[kRaggedLanes - 1];
+    hipEvent_t fork;
+    hipEvent_t join[kRaggedLanes - 1];
+    std::mutex mu;
+};
+std::mutex g_lanes_mu;
+Lanes* g_lanes[64];
+
+Lanes* device_lanes(int dev)
 {
-    for (hipStream_t a : p->aux) (void)hipStreamDestroy(a);
-    for (hipEvent_t e : p->join) (void)hipEventDestroy(e);
-    if (p->fork) (void)hipEventDestroy(p->fork);
-    p->aux.clear();
-    p->join.clear();
-    p->fork = nullptr;
+    if (dev < 0 || dev >= 64) {
+        hip_fail(hipErrorInvalidDevice, "ragged streams");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_lanes_mu);
+    if (g_lanes[dev]) return g_lanes[dev];
+    auto* L = new Lanes();
+    int streams = 0, joins = 0;
+    hipError_t e = hipEventCreateWithFlags(&L->fork, hipEventDisableTiming);
+    if (e != hipSuccess) L->fork = nullptr;
+    for (int l = 0; l < kRaggedLanes - 1 && e == hipSuccess; ++l) {
+        e = hipStreamCreateWithFlags(&L->aux[l], hipStreamNonBlocking);
+        if (e != hipSuccess) break;
+        ++streams;
+        e = hipEventCreateWithFlags(&L->join[l], hipEventDisableTiming);
+        if (e == hipSuccess) ++joins;
+    }
+    if (e != hipSuccess) {
+        // (nothing has used them yet: safe to release)
+        for (int l = 0; l < streams; ++l) (void)hipStreamDestroy(L->aux[l]);
+        for (int l = 0; l < joins; ++l) (void)hipEventDestroy(L->join[l]);
+        if (L->fork) (void)hipEventDestroy(L->fork);
+        delete L;
+        hip_fail(e, "ragged streams");
+        return nullptr;
+    }
+    g_lanes[dev] = L;
+    return L;
+}
+
+// Destroys a plan that was never executed (creation failed part way).
+void free_unused(impconv_ragged_plan* p)
+{
+    if (p->dmem) (void)hipFree(p->dmem);
+    delete p;
 }
 }  // namespace
 
@@ -112,8 +156,11 @@ impconv_status impconv_ragged_plan_create(int dtype, int64_t npairs, const int64
     p->extent = extent;
     p->dmem = nullptr;
     p->work = 0;
-    p->fork = nullptr;
     (void)hipGetDevice(&p->device);
+    if (!device_lanes(p->device)) {
+        delete p;
+        return IMPCONV_E_HIP;
+    }
     std::vector<int64_t> host;
     struct Pending { int64_t N, count, maxm; size_t off_at, m_at; };
     std::vector<Pending> pend;
@@ -154,23 +201,6 @@ impconv_status impconv_ragged_plan_create(int dtype, int64_t npairs, const int64
         }
         p->classes.push_back({q.N, q.count, q.maxm, d + q.off_at, d + q.m_at, 0, {}, lane, off});
     }
-    {
-        hipError_t e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
-        for (int l = 1; l < kRaggedLanes && e == hipSuccess; ++l) {
-            hipStream_t a = nullptr;
-            hipEvent_t j = nullptr;
-            e = hipStreamCreateWithFlags(&a, hipStreamNonBlocking);
-            if (e == hipSuccess) p->aux.push_back(a);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&j, hipEventDisableTiming);
-            if (e == hipSuccess) p->join.push_back(j);
-        }
-        if (e != hipSuccess) {
-            destroy_streams(p);
-            if (p->dmem) (void)hipFree(p->dmem);
-            delete p;
-            return hip_fail(e, "ragged plan streams");
-        }
-    }
     // the four-step classes' column twiddle tables are created here, so that
     // executing the plan allocates nothing (and may be captured)
     for (const auto& q : pend) {
@@ -178,9 +208,7 @@ impconv_status impconv_ragged_plan_create(int dtype, int64_t npairs, const int64
         int64_t N1, N2;
         fourstep_split(q.N, &N1, &N2);
         if (!fs_twiddles(dtype, N2, N1)) {
-            destroy_streams(p);
-            if (p->dmem) (void)hipFree(p->dmem);
-            delete p;
+            free_unused(p);
             return IMPCONV_E_HIP;
         }
     }
@@ -221,14 +249,24 @@ impconv_status impconv_ragged_execute(const impconv_ragged_plan* p, const void* 
     const DevTables* tb = tables();
     if (!tb) return IMPCONV_E_HIP;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    std::lock_guard<std::mutex> lk(const_cast<impconv_ragged_plan*>(p)->mu);
-    // fork: every auxiliary stream waits for the work queued on s so far
+    Lanes* L = device_lanes(p->device);
+    if (!L) return IMPCONV_E_HIP;
+    auto* pm = const_cast<impconv_ragged_plan*>(p);
+    // lock order: the plan, then the device's lanes
+    std::lock_guard<std::mutex> lk(pm->mu);
+    std::unique_lock<std::mutex> lanes_lock(L->mu, std::defer_lock);
+    impconv_status st = IMPCONV_OK;
+    bool forked = false;
     if (!one) {
-        HIPCHK(hipEventRecord(p->fork, s), "ragged fork");
-        for (hipStream_t a : p->aux) HIPCHK(hipStreamWaitEvent(a, p->fork, 0), "ragged fork");
+        // fork: every auxiliary stream waits for the work queued on s so far
+        lanes_lock.lock();
+        hipError_t e = hipEventRecord(L->fork, s);
+        for (int l = 0; l < kRaggedLanes - 1 && e == hipSuccess; ++l) e = hipStreamWaitEvent(L->aux[l], L->fork, 0);
+        if (e != hipSuccess) return hip_fail(e, "ragged fork");
+        forked = true;
     }
     for (const auto& c : p->classes) {
-        hipStream_t cs_ = one || c.lane == 0 ? s : p->aux[c.lane - 1];
+        hipStream_t cs_ = one || c.lane == 0 ? s : L->aux[c.lane - 1];
         if (c.N <= kRowMax) {
             RowArgs a;
             std::memset(&a, 0, sizeof(a));
@@ -241,20 +279,30 @@ impconv_status impconv_ragged_execute(const impconv_ragged_plan* p, const void* 
             a.row_off = c.d_off;
             a.row_m = c.d_m;
             a.flags = flags & (kRevF | kConjG | kRevOut);
-            HIPCHK(launch_row_complex(p->dt, int(c.N), a, cs_), "ragged row class");
+            const hipError_t e = launch_row_complex(p->dt, int(c.N), a, cs_);
+            if (e != hipSuccess) st = hip_fail(e, "ragged row class");
         } else {
-            impconv_status st = large1d_run_ragged(*tb, p->dt, c.count, c.N, c.maxm, f, g, h,
-                                                   static_cast<char*>(work) + c.work_off, c.d_off, c.d_m, flags,
-                                                   cs_, c.n2);
-            if (st) return st;
+            st = large1d_run_ragged(*tb, p->dt, c.count, c.N, c.maxm, f, g, h,
+                                    static_cast<char*>(work) + c.work_off, c.d_off, c.d_m, flags, cs_, c.n2);
+        }
+        if (st) break;
+    }
+    // join, also after a failed launch: s waits for every auxiliary stream,
+    // so that nothing of this call is left unordered with what s does next
+    // (and a capture sees every forked stream rejoin)
+    if (forked) {
+        for (int l = 0; l < kRaggedLanes - 1; ++l) {
+            hipError_t e = hipEventRecord(L->join[l], L->aux[l]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, L->join[l], 0);
+            if (e != hipSuccess && !st) st = hip_fail(e, "ragged join");
         }
     }
-    // join: s waits for every auxiliary stream
-    for (size_t l = 0; l < p->aux.size() && !one; ++l) {
-        HIPCHK(hipEventRecord(p->join[l], p->aux[l]), "ragged join");
-        HIPCHK(hipStreamWaitEvent(s, p->join[l], 0), "ragged join");
-    }
-    return IMPCONV_OK;
+    // completion of this execution on s, for destruction
+    hipEvent_t& dn = pm->done[s];
+    hipError_t e = dn ? hipSuccess : hipEventCreateWithFlags(&dn, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(dn, s);
+    if (e != hipSuccess && !st) st = hip_fail(e, "ragged completion event");
+    return st;
 }
 
 impconv_status impconv_ragged_plan_autotune(impconv_ragged_plan* p, void* stream)
@@ -276,6 +324,9 @@ impconv_status impconv_ragged_plan_autotune(impconv_ragged_plan* p, void* stream
     hipEvent_t e0 = nullptr, e1 = nullptr;
     impconv_status st = IMPCONV_OK;
     auto cleanup = [&]() {
+        // kernels already launched on s may still use the arrays (also
+        // after a failure part way): wait for them before freeing
+        (void)hipStreamSynchronize(s);
         for (void* q : {f, g, h, w})
             if (q) (void)hipFree(q);
         if (e0) (void)hipEventDestroy(e0);
@@ -364,15 +415,21 @@ impconv_status impconv_ragged_plan_schedule(const impconv_ragged_plan* p, char* 
 impconv_status impconv_ragged_plan_destroy(impconv_ragged_plan* plan)
 {
     if (!plan) return IMPCONV_OK;
-    // Work that earlier executions enqueued still uses the plan: kernels on
-    // its auxiliary streams read its descriptor arrays, and the caller's
-    // streams wait on its join events.  Wait for the plan's device to finish
-    // that work before the streams, events and descriptors are released.
+    {
+        // Executions still in flight read the plan's descriptor arrays: wait
+        // for the completion event each stream recorded after its last
+        // execution (a host wait on those points of those streams only; the
+        // device's auxiliary streams are not the plan's and stay).
+        std::lock_guard<std::mutex> lk(plan->mu);
+        for (auto& kv : plan->done) {
+            (void)hipEventSynchronize(kv.second);
+            (void)hipEventDestroy(kv.second);
+        }
+        plan->done.clear();
+    }
     int cur = -1;
     const bool have_cur = hipGetDevice(&cur) == hipSuccess;
     if (have_cur && cur != plan->device) (void)hipSetDevice(plan->device);
-    (void)hipDeviceSynchronize();
-    destroy_streams(plan);
     if (plan->dmem) (void)hipFree(plan->dmem);
     if (have_cur && cur != plan->device) (void)hipSetDevice(cur);
     delete plan;

@@ -10,6 +10,7 @@
 // double; the complex64 tables round those doubles to float, and for the
 // compensated products a second complex64 table holds the rounded remainder.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -197,7 +198,7 @@ struct Rec {
     hipEvent_t a, b;
 };
 std::mutex t_mu;
-bool t_on = false;
+std::atomic<bool> t_on{false};  // read by launches on any thread
 std::vector<Rec> t_recs;
 thread_local hipEvent_t t_pending = nullptr;
 
@@ -209,18 +210,18 @@ hipEvent_t new_event()
 }
 }  // namespace
 
-bool timing_on() { return t_on; }
+bool timing_on() { return t_on.load(); }
 
 void timing_begin(hipStream_t s)
 {
-    if (!t_on) return;
+    if (!t_on.load()) return;
     t_pending = new_event();
     if (t_pending) (void)hipEventRecord(t_pending, s);
 }
 
 void timing_end(const char* name, hipStream_t s)
 {
-    if (!t_on || !t_pending) return;
+    if (!t_on.load() || !t_pending) return;
     hipEvent_t b = new_event();
     if (!b) return;
     (void)hipEventRecord(b, s);
@@ -235,8 +236,7 @@ extern "C" {
 
 void impconv_timing_enable(int on)
 {
-    std::lock_guard<std::mutex> lk(impconv::t_mu);
-    impconv::t_on = on != 0;
+    impconv::t_on.store(on != 0);
 }
 
 // Waits for the recorded events, writes a JSON array of per-kernel aggregates
