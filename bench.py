@@ -1,19 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark of the implicitly dealiased convolution on one MI355X.
 
-Default workload (c3): 2D complex dealiased convolutions of 2048 x 2048
-complex64 inputs, a batch of 8 independent pairs per step, one call of
-conv2d.  Each step's result is a batch of 8 dealiased convolutions; value =
-convolutions per second, with inputs resident in HBM before the timed region.
-The explicitly zero-padded comparator (same FFT kernels, padded 4096 x 4096
-arrays materialized in HBM) and its pruned form (padding fused into the
-loads, no transform of an all-zero column) are timed the same way.
+Default workload (c4): the 3D centered Hermitian (2/3 rule) convolution of
+the pseudospectral configuration, storage 512 x 512 x 257 (m = 256 per axis,
+zero slots), three velocity-vorticity products summed per call (M = 3), in
+complex128 (FP64 arithmetic, the paper's precision), with a complex64 leg
+(FP32 arithmetic, FP64-generated twiddles) and its error in the same line.
+A step is one conv3d call; value = convolutions per second, with inputs
+resident in HBM before the timed region.  The explicitly zero-padded
+comparator (same FFT kernels, every axis padded to a power of two >= 3m - 2
+and materialized in HBM) and its pruned form are timed the same way.
 
 Other workloads (--workload): c1 (1D complex m=1024 complex128, batch 16384),
-c2 (1D centered Hermitian m=16384, batch 256), c4 (3D centered Hermitian
-512x512x257, M=3), c5 (4096 uneven 1D complex pairs, forward + backward),
-t2 (2D centered Hermitian ternary, 1024^2 modes, batch 8), e2 (2D Euler
-nonlinearity: Hermitian 2D with M = 2, 2048^2 modes).
+c2 (1D centered Hermitian m=16384, batch 256), c3 (2D complex 2048^2, batch
+8), c5 (4096 uneven 1D complex pairs, forward + backward), t1 (1D Hermitian
+ternary m=2048), t2 (2D centered Hermitian ternary, 1024^2 modes, batch 8),
+e2 (2D Euler nonlinearity: Hermitian 2D with M = 2, 2048^2 modes).
 
 Output: one JSON line (rank 0) with the metric, per-step time (mean and the
 one-sided deviations below and above it), per-kernel algorithmic bytes and
@@ -38,11 +40,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "dealiased convs/sec + HBM GB/s, implicit vs explicit-padded, FP32/FP64 at rel err"
 HBM_PEAK_GBS = 8000.0
-# Vector FMA rate of 256 CUs x 4 SIMDs x 16 lanes x 2 flops at 2.4 GHz.  The
-# chip's 157.3 TFLOP/s FP32 figure needs packed FP32 instructions, which this
-# library is built without; FP64 runs at the same 78.6 TFLOP/s.
-VALU_PEAK_TFLOPS = 78.6
-VALU_PEAK_PACKED_FP32_TFLOPS = 157.3
+# Published MI355X vector peaks: FP64 78.6 TFLOP/s, FP32 157.3 TFLOP/s.  The
+# FP32 figure counts packed FP32 instructions (two FMAs per lane and cycle),
+# which this library is built without, so FP32 kernels also report their
+# fraction of the non-packed rate, 256 CUs x 4 SIMDs x 16 lanes x 2 flops x
+# 2.4 GHz = 78.6 TFLOP/s.
+PEAK_TFLOPS = {"c128": 78.6, "c64": 157.3}
+VALU_NONPACKED_TFLOPS = 78.6
+
+
+def note(msg: str) -> None:
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def flops_row_complex(N: int) -> float:
@@ -355,8 +364,41 @@ def wl_c1(args):
                 kflops=kflops, cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy(), single=single)
 
 
+def numpy_explicit_hermitian_3d(f, g, m, workers):
+    """FP64 explicitly padded FFT convolution on the host (scipy.fft, i.e.
+    pocketfft): every axis padded to 3m (the 2/3 rule's size; wavenumber k
+    of a centered axis at index k mod 3m, the last axis the half spectrum of
+    a real length 3m), the M-dot of the physical-space products, one forward
+    real transform, crop.  f, g: [M][2m][2m][m+1] in the library's storage
+    (index k + m on the centered axes).  Returns h in that storage."""
+    import scipy.fft as sf
+    M = f.shape[0]
+    P = [3 * x for x in m]
+    k0 = np.arange(-(m[0] - 1), m[0])
+    k1 = np.arange(-(m[1] - 1), m[1])
+    src = np.ix_(k0 + f.shape[1] - m[0], k1 + f.shape[2] - m[1], np.arange(m[2]))
+    dst = np.ix_(k0 % P[0], k1 % P[1], np.arange(m[2]))
+    buf = np.zeros((P[0], P[1], P[2] // 2 + 1), np.complex128)
+    acc = None
+    for i in range(M):
+        buf[dst] = f[i][src]
+        a = sf.irfftn(buf, s=P, workers=workers)
+        buf[dst] = g[i][src]
+        a *= sf.irfftn(buf, s=P, workers=workers)
+        acc = a if acc is None else acc + a
+        del a
+    H = sf.rfftn(acc, workers=workers)
+    del acc
+    H *= float(np.prod(P))  # irfftn's 1/N on each factor, rfftn's none
+    h = np.zeros(f.shape[1:], np.complex128)
+    h[src] = H[dst]
+    return h
+
+
 def wl_c4(args):
-    """3D centered Hermitian, storage 512x512x257 (m=256/axis), M=3 pairs summed."""
+    """3D centered Hermitian, storage 512x512x257 (m=256/axis), M=3 pairs
+    summed: the headline workload, complex128 by default, with a complex64
+    leg (FP64-generated twiddles) timed in the same run."""
     import torch
     import paper_1008_1366_amd as ic
     import synth
@@ -395,12 +437,19 @@ def wl_c4(args):
     kflops_step = {"k_conv1d_hermitian": 9 * m[0] * m[1] * flops_row_hermitian(m[2] // 2, 3)}
     step_bytes = int(59.5 * S)
 
+    def oracle_points():
+        rng = synth.rng(206)
+        return np.concatenate([[[0, 0, 0], [255, 255, 255], [-255, 0, 3], [5, -7, 0], [-3, 9, 0], [0, -200, 0]],
+                               np.stack([rng.integers(-255, 256, 10), rng.integers(-255, 256, 10),
+                                         rng.integers(0, 256, 10)], 1)])
+
+    def sampled_err(hh, pts, ref):
+        got = hh[0][pts[:, 0] + 256, pts[:, 1] + 256, pts[:, 2]]
+        return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
     def cpu_baseline(h_gpu, h_expl=None):
         import oracle
-        rng = synth.rng(206)
-        pts = np.concatenate([[[0, 0, 0], [255, 255, 255], [-255, 0, 3], [5, -7, 0], [-3, 9, 0], [0, -200, 0]],
-                              np.stack([rng.integers(-255, 256, 10), rng.integers(-255, 256, 10),
-                                        rng.integers(0, 256, 10)], 1)])
+        pts = oracle_points()
         fr = np.asarray(f[0].astype(np.complex64 if cdt == torch.complex64 else np.complex128), np.complex128)
         gr = np.asarray(g[0].astype(np.complex64 if cdt == torch.complex64 else np.complex128), np.complex128)
         t0 = time.perf_counter()
@@ -409,8 +458,7 @@ def wl_c4(args):
         err = {}
         for key, hh in (("implicit", h_gpu), ("explicit", h_expl)):
             if hh is not None:
-                got = hh[0][pts[:, 0] + 256, pts[:, 1] + 256, pts[:, 2]]
-                err[key] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+                err[key] = sampled_err(hh, pts, ref)
         err["points"] = len(pts)
         if cdt == torch.complex64:
             err["fp32_vs_fp64_full_field"] = fp32_vs_fp64(
@@ -418,15 +466,56 @@ def wl_c4(args):
         # terms per output point ~ prod(2m-1) * M / 2 on average; 256^2 * 256 outputs
         per_pt = dt / len(pts)
         nout = 511 * 511 * 256
-        return {"value": 1.0 / (per_pt * nout), "unit": "convs/s", "cores": oracle.num_threads(),
-                "kind": "oracle", "sample": f"{len(pts)} output points, extrapolated by output count"}, err
+        cpu = {"value": 1.0 / (per_pt * nout), "unit": "convs/s", "cores": oracle.num_threads(),
+               "kind": "oracle", "sample": f"{len(pts)} output points ({dt:.2f} s), extrapolated to the whole "
+                                           "convolution by output count"}
+        if not args.no_numpy:
+            # the practical CPU method: FP64 explicitly padded FFT convolution
+            # (scipy.fft) of the same inputs, whole field, timed once
+            workers = len(os.sched_getaffinity(0))
+            t0 = time.perf_counter()
+            hn = numpy_explicit_hermitian_3d(fr, gr, m, workers)
+            tn = time.perf_counter() - t0
+            cpu["numpy_explicit_fp64"] = {"value": 1.0 / tn, "unit": "convs/s", "seconds_per_conv": tn,
+                                          "cores": workers, "padded_size": [3 * x for x in m],
+                                          "rel_err_at_oracle_points": sampled_err(hn[None], pts, ref)}
+            err["implicit_vs_numpy_full_field"] = float(np.linalg.norm(h_gpu[0] - hn) / np.linalg.norm(hn))
+            del hn
+        return cpu, err
+
+    def c64_leg():
+        """The complex64 path on the same inputs (rounded), timed like the
+        headline, with its error over the whole field against the complex128
+        result of the library (itself checked against the oracle) and at the
+        oracle's sampled points."""
+        import oracle
+        if cdt == torch.complex64:
+            return None
+        F32, G32 = F.to(torch.complex64), G.to(torch.complex64)
+        run32 = lambda: ic.conv3d(F32, G32, kind="hermitian", m=m)
+        ms32 = timed(run32, args.steps, args.warmup)
+        h32 = run32().cpu().numpy()
+        h64 = ic.conv3d(F32.to(torch.complex128), G32.to(torch.complex128), kind="hermitian", m=m).cpu().numpy()
+        e_full = float(np.linalg.norm(h32.astype(np.complex128) - h64) / np.linalg.norm(h64))
+        pts = oracle_points()
+        fr = np.asarray(f[0].astype(np.complex64), np.complex128)
+        gr = np.asarray(g[0].astype(np.complex64), np.complex128)
+        e_pts = sampled_err(h32, pts, oracle.convnd_hermitian_at(fr, gr, m, pts))
+        S32 = int(np.prod(n)) * 8
+        del F32, G32, h32, h64
+        torch.cuda.empty_cache()
+        return {"dtype": "fp32 (complex64, FP64-generated twiddles)", "ms_per_step": round(ms32, 5),
+                "value": round(1000.0 / ms32, 2), "unit": "convs/s",
+                "hbm_gbps_algorithmic": round(59.5 * S32 / (ms32 * 1e-3) / 1e9, 1),
+                "rel_err_vs_fp64_full_field": e_full, "rel_err_vs_oracle_sampled": e_pts}
 
     cfg = {"workload": "3D centered Hermitian implicit dealiased convolution, storage 512x512x257 "
                        "(m=256 per axis), M=3 pairs summed, "
                        f"{'complex64' if cdt == torch.complex64 else 'complex128'}",
            "m": list(m), "n": list(n), "M": 3, "dtype": args.dtype}
     return dict(run=run, explicit=expl, pruned=pruned, convs=1, step_bytes=step_bytes, kbytes_step=kbytes_step,
-                kflops_step=kflops_step, cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy())
+                kflops_step=kflops_step, cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy(),
+                bound="hbm", leg=c64_leg)
 
 
 def wl_c5(args):
@@ -766,9 +855,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
     ap.add_argument("--dtype", default=None, choices=["c64", "c128"],
-                    help="default: c128 for c1 (the 1D complex case is stated in FP64), c64 otherwise")
+                    help="default: c128 for c1 and c4 (stated in FP64; c4 adds a complex64 leg), c64 otherwise")
+    ap.add_argument("--no-numpy", action="store_true", help="c4: skip the FP64 NumPy explicit-padded CPU time")
+    ap.add_argument("--no-leg", action="store_true", help="c4: skip the complex64 leg")
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-explicit", action="store_true")
@@ -784,7 +875,7 @@ def main():
     ap.add_argument("--profile-copy", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
-    args.dtype = args.dtype or ("c128" if args.workload == "c1" else "c64")
+    args.dtype = args.dtype or ("c128" if args.workload in ("c1", "c4") else "c64")
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the workloads "
               "shard by batch with no exchange between GPUs, so they are measured on one", file=sys.stderr)
@@ -794,7 +885,9 @@ def main():
     import paper_1008_1366_amd as ic
     ic.lib()  # fail loudly without the HIP library
     torch.cuda.set_device(0)
+    note(f"workload {args.workload} {args.dtype}: preparing inputs")
     W = WORKLOADS[args.workload](args)
+    note("timing the implicit path")
 
     # implicit path, with per-launch event timing inside the library
     ms_clean = timed(W["run"], args.steps, args.warmup)  # the timed region of the metric
@@ -807,6 +900,7 @@ def main():
     if timing_note:
         W["kernel_timing_mode"](False)
     convs_s = W["convs"] * 1000.0 / ms_clean
+    note(f"implicit: {ms_clean:.4f} ms per step")
     copy_gbs = copy_bandwidth()
 
     # per-kernel algorithmic bytes and flops: per launch (kbytes / kflops) or
@@ -841,21 +935,29 @@ def main():
             if isinstance(rec, dict) and rec.get("source_hash") == kernel_source_hash(dom["name"]):
                 traffic = rec["bytes"]
         hbm_frac = dom["gbs"] / HBM_PEAK_GBS if "gbs" in dom else None
-        alu_frac = dom["tflops"] / VALU_PEAK_TFLOPS if "tflops" in dom else None
-        if alu_frac is not None and (hbm_frac is None or alu_frac > hbm_frac):
-            # arithmetic intensity above the ridge point: bound by the vector ALUs
-            roof = {"bound": "alu", "achieved": dom["tflops"], "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(alu_frac, 4), "traffic": traffic, "kernel": dom["name"],
-                    "measured_gbs": round(traffic / (dom["avg_ms"] * 1e-3) / 1e9, 1) if traffic else None,
-                    "kernel_avg_ms": dom["avg_ms"], "algorithmic_flops_per_launch": dom["flops_per_launch"],
-                    "frac_of_packed_fp32_peak": (round(dom["tflops"] / VALU_PEAK_PACKED_FP32_TFLOPS, 4)
-                                                 if args.dtype == "c64" else None),
+        peak_tf = PEAK_TFLOPS[args.dtype]
+        alu_frac = dom["tflops"] / peak_tf if "tflops" in dom else None
+        bound = W.get("bound")
+        if bound is None:  # by arithmetic intensity: whichever roof the kernel is nearer
+            bound = "alu" if alu_frac is not None and (hbm_frac is None or alu_frac > hbm_frac) else "hbm"
+        common = {"traffic": traffic, "kernel": dom["name"], "kernel_avg_ms": dom["avg_ms"],
+                  "measured_gbs": round(traffic / (dom["avg_ms"] * 1e-3) / 1e9, 1) if traffic else None,
+                  "traffic_over_algorithmic": (round(traffic / dom["bytes_per_launch"], 3)
+                                               if traffic and dom.get("bytes_per_launch") else None)}
+        if bound == "alu" and alu_frac is not None:
+            roof = {"bound": "alu", "achieved": dom["tflops"], "peak": peak_tf, "unit": "TFLOP/s",
+                    "frac": round(alu_frac, 4), **common,
+                    "algorithmic_flops_per_launch": dom["flops_per_launch"],
+                    "frac_of_nonpacked_valu": round(dom["tflops"] / VALU_NONPACKED_TFLOPS, 4),
                     "hbm_view": {"achieved_gbs": dom.get("gbs"), "frac": round(hbm_frac, 4) if hbm_frac else None}}
         elif hbm_frac is not None:
             roof = {"bound": "hbm", "achieved": dom["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(hbm_frac, 4), "traffic": traffic, "kernel": dom["name"],
-                    "measured_gbs": round(traffic / (dom["avg_ms"] * 1e-3) / 1e9, 1) if traffic else None,
-                    "kernel_avg_ms": dom["avg_ms"], "algorithmic_bytes_per_launch": dom["bytes_per_launch"]}
+                    "frac": round(hbm_frac, 4), **common,
+                    "algorithmic_bytes_per_launch": dom["bytes_per_launch"]}
+            if alu_frac is not None:
+                roof["alu_view"] = {"achieved_tflops": dom["tflops"], "peak": peak_tf,
+                                    "frac": round(alu_frac, 4),
+                                    "frac_of_nonpacked_valu": round(dom["tflops"] / VALU_NONPACKED_TFLOPS, 4)}
 
     alg_gbs = W["step_bytes"] / (ms_clean * 1e-3) / 1e9
     out = {"metric": METRIC, "value": round(convs_s, 2), "unit": "convs/s", "n_gpus": 1,
@@ -873,6 +975,7 @@ def main():
         out["kernel_timing"] = timing_note
 
     if W.get("explicit") is not None and not args.no_explicit:
+        note("timing the explicit comparator")
         ms_e = timed(W["explicit"], max(3, args.steps // 2), 1)
         out["explicit_padded"] = {"ms_per_step": round(ms_e, 5), "value": round(W["convs"] * 1000.0 / ms_e, 2),
                                   "unit": "convs/s"}
@@ -900,6 +1003,12 @@ def main():
             out["single_pair"]["explicit_ms"] = round(ms_1e, 5)
             out["single_pair"]["speedup_vs_explicit"] = round(ms_1e / ms_1, 3)
 
+    if W.get("leg") is not None and not args.no_leg:
+        note("complex64 leg")
+        leg = W["leg"]()
+        if leg is not None:
+            out["complex64_leg"] = leg
+
     if W.get("graph") is not None and not args.no_graph:
         replay, check = W["graph"]()
         ms_g = timed(replay, args.steps, args.warmup)
@@ -917,6 +1026,7 @@ def main():
         out["copy_kernel_bytes"] = {"read": n * 4, "write": n * 4}
 
     if not args.no_cpu:
+        note("CPU baseline (oracle sample)")
         h = W["out"]()
         if W.get("explicit") is not None and not args.no_explicit:
             extra = {}

@@ -114,16 +114,44 @@ def test_ternary_1d(dt, m):
 
 @pytest.mark.parametrize("dt", DT)
 def test_ternary_1d_m2048_sampled(dt):
-    """The m = 2048 ternary workload, oracle at sampled outputs."""
+    """The m = 2048 ternary workload (batch of 4): the oracle at 64 sampled
+    outputs of every convolution, and every output against the FP64 direct
+    sum of the Hermitian-extended inputs (two numpy direct convolutions)."""
+    ic = need_gpu()
+    m, B = 2048, 4
+    f = synth.power_spectrum_1d(m, 5 / 6, 34, batch=B)
+    g = synth.power_spectrum_1d(m, 5 / 6, 35, batch=B)
+    e = synth.power_spectrum_1d(m, 5 / 6, 36, batch=B)
+    h = ic.conv1d_ternary(to_dev(f, dt), to_dev(g, dt), to_dev(e, dt)).cpu().numpy()
+    rng = synth.rng(37)
+    ks = np.unique(np.concatenate([[0, 1, 2, 100, 1023, 1024, 2046, 2047], rng.integers(0, m, 56)]))
+    assert len(ks) >= 60
+    ext = lambda u: np.concatenate([np.conj(u[:0:-1]), [u[0].real], u[1:]])  # k = -m+1 .. m-1
+    for b in range(B):
+        fr, gr, er = rounded(f[b], dt), rounded(g[b], dt), rounded(e[b], dt)
+        ref = oracle.conv1d_ternary_at(fr, gr, er, ks)
+        assert rel(h[b][ks], ref) < TOL[dt], b
+        full = np.convolve(np.convolve(ext(fr), ext(gr)), ext(er))[3 * (m - 1):3 * (m - 1) + m]
+        assert rel(h[b], full) < TOL[dt], b
+
+
+@pytest.mark.parametrize("dt", DT)
+def test_ternary_1d_m2048_closed_form(dt):
+    """f_k = F e^{ik}, g_k = G e^{ik}, e_k = E e^{ik} (F, G, E real, Hermitian
+    extension): h_k = F G E N(k) e^{ik} with N(k) the number of triples of
+    wavenumbers in [-m+1, m-1] summing to k (an inclusion-exclusion count
+    pinned by brute force on the CPU); every output at m = 2048."""
+    from test_oracle_pins import ternary_count
     ic = need_gpu()
     m = 2048
-    f = synth.power_spectrum_1d(m, 5 / 6, 34)
-    g = synth.power_spectrum_1d(m, 5 / 6, 35)
-    e = synth.power_spectrum_1d(m, 5 / 6, 36)
+    F, G, E = np.sqrt(3), np.sqrt(5), np.sqrt(7)
+    k = np.arange(m)
+    ph = np.exp(1j * k)
+    f, g, e = F * ph, G * ph, E * ph
     h = ic.conv1d_ternary(to_dev(f, dt), to_dev(g, dt), to_dev(e, dt)).cpu().numpy()
-    ks = [0, 1, 2, 100, 1023, 1024, 2046, 2047]
-    ref = oracle.conv1d_ternary_at(rounded(f, dt), rounded(g, dt), rounded(e, dt), ks)
-    assert rel(h[ks], ref) < TOL[dt]
+    ref = F * G * E * np.array([ternary_count(m, int(q)) for q in k], float) * ph
+    # complex64: the inputs are rounded once (relative 6e-8 per entry)
+    assert rel(h, ref) < TOL[dt]
 
 
 @pytest.mark.parametrize("dt", DT)

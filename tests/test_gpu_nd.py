@@ -108,13 +108,13 @@ def test_complex_2d_c3_workload(dt):
     for b in range(0, B - 1, 3):
         ref = oracle.convnd_complex_at(rounded(f[b], dt), rounded(g[b], dt), pts)
         assert rel(h[b][pts[:, 0], pts[:, 1]], ref) < TOL[dt], b
-    full = np.outer(oracle.conv1d_complex(rounded(a, dt) if dt == np.complex128 else a, c),
-                    oracle.conv1d_complex(bb, d))
-    if dt == np.complex128:
-        assert rel(h[B - 1], full) < TOL[dt]
-    else:
-        ref = oracle.convnd_complex_at(rounded(f[B - 1], dt), rounded(g[B - 1], dt), pts)
-        assert rel(h[B - 1][pts[:, 0], pts[:, 1]], ref) < TOL[dt]
+    # every output of the rank-one pair; in complex64 the products a b and
+    # c d are rounded once on input (relative 6e-8 per entry), which the FP32
+    # tolerance covers
+    full = np.outer(oracle.conv1d_complex(a, c), oracle.conv1d_complex(bb, d))
+    assert rel(h[B - 1], full) < TOL[dt]
+    ref = oracle.convnd_complex_at(rounded(f[B - 1], dt), rounded(g[B - 1], dt), pts)
+    assert rel(h[B - 1][pts[:, 0], pts[:, 1]], ref) < TOL[dt]
 
 
 @pytest.mark.parametrize("dt", DT)
@@ -160,6 +160,43 @@ def test_hermitian_3d_c4_workload(dt):
     got = h[pts[:, 0] + 256, pts[:, 1] + 256, pts[:, 2]]
     assert rel(got, ref) < TOL[dt]
     assert np.all(h[0] == 0) and np.all(h[:, 0] == 0) and np.all(h[:, :, 256] == 0)
+
+
+def _herm_full_1d(m, seed):
+    """A Hermitian-symmetric centered 1D field, wavenumbers -m+1..m-1."""
+    a = synth.power_spectrum_1d(m, 11 / 6, seed)
+    return np.concatenate([np.conj(a[:0:-1]), [a[0].real], a[1:]])
+
+
+@pytest.mark.parametrize("dt", DT)
+def test_hermitian_3d_c4_separable_full_field(dt):
+    """Every output of the 512 x 512 x 257 (m = 256 per axis), M = 3
+    workload on separable inputs: pair i is f_i = A_i (x) B_i (x) c_i with
+    A, B Hermitian centered fields along x and y and c a Hermitian half along
+    z (c_0 real), so the k_z = 0 plane is already symmetric and the sum
+    factors, per pair, into the full centered 1D sums along x and y and the
+    centered Hermitian 1D sum along z (Sec. 3.4 builds the 3D convolution from
+    these axes).  Reference: sum over i of outer products of the 1D oracle
+    results, compared on the whole stored field (zero slots included)."""
+    ic = need_gpu()
+    say(f"hermitian3d C4 separable full field {dt.__name__}")
+    m, n = 256, (512, 512, 257)
+    f = np.zeros((3, *n), complex)
+    g = np.zeros((3, *n), complex)
+    ref = np.zeros(n, complex)
+    for i in range(3):
+        A, B, A2, B2 = (_herm_full_1d(m, 400 + 10 * i + j) for j in range(4))
+        c, c2 = (synth.power_spectrum_1d(m, 11 / 6, 450 + 10 * i + j) for j in range(2))
+        c[0], c2[0] = c[0].real, c2[0].real
+        f[i, 1:, 1:, :m] = np.einsum("x,y,z->xyz", A, B, c)
+        g[i, 1:, 1:, :m] = np.einsum("x,y,z->xyz", A2, B2, c2)
+        ref[1:, 1:, :m] += np.einsum("x,y,z->xyz", oracle.conv1d_centered(A, A2),
+                                     oracle.conv1d_centered(B, B2), oracle.conv1d_hermitian(c, c2))
+    h = ic.conv3d(to_dev(f[None], dt), to_dev(g[None], dt), kind="hermitian", m=(m, m, m)).cpu().numpy()[0]
+    # complex64: the products A B c are rounded once on input (relative 6e-8
+    # per entry); the FP32 tolerance covers it
+    assert rel(h, ref) < TOL[dt]
+    assert np.all(h[0] == 0) and np.all(h[:, 0] == 0) and np.all(h[:, :, m] == 0)
 
 
 @pytest.mark.parametrize("dt", DT)
