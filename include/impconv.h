@@ -90,8 +90,11 @@ const char* impconv_status_string(int status);
 /* Text of the last error raised on the calling thread ("" if none). */
 const char* impconv_last_error(void);
 
-/* Create the twiddle tables of the current HIP device (idempotent,
- * thread-safe, synchronous).  Every entry point calls it implicitly. */
+/* Create the twiddle tables of the current HIP device and resolve the
+ * device address of the work memory of impconv_conv2d_noalloc there
+ * (idempotent, thread-safe, synchronous).  Every other entry point calls the
+ * table part implicitly; impconv_conv2d_noalloc requires it to have run on
+ * its device. */
 impconv_status impconv_init(void);
 
 /* ----------------------------------------------------------------------
@@ -260,6 +263,32 @@ impconv_status impconv_conv2d(int kind, int dtype, int64_t batch, int64_t M, con
 impconv_status impconv_conv3d(int kind, int dtype, int64_t batch, int64_t M, const int64_t* m,
                               const int64_t* n, const void* f, const void* g, void* h,
                               void* work, size_t work_bytes, uint32_t flags, void* stream);
+
+/* Allocation-free form of impconv_conv2d, for callers that cannot allocate
+ * device memory: code under hipGraph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, results, flags and errors as
+ * impconv_conv2d, without work / work_bytes: the work arrays live in a fixed
+ * region of device memory that belongs to the library's device code (one per
+ * device, impconv_noalloc_capacity() bytes = 64 MiB, held until the process
+ * ends).  The call allocates and frees nothing; it only enqueues kernels on
+ * `stream`.
+ *  - impconv_init() must have run on the current device first (it resolves
+ *    the region's address); otherwise IMPCONV_E_ARG.
+ *  - A convolution whose impconv_convnd_workspace exceeds the capacity is
+ *    IMPCONV_E_WORKSPACE (e.g. complex64 complex 2D: 4 * batch * M *
+ *    2^ceil(log2 m0) * m1 * 8 bytes must be <= 64 MiB).
+ *  - Every call on a device shares that device's region and leaves its last
+ *    contents there (nothing in the region needs to start at zero: each
+ *    kernel writes the work it reads).  Calls that can overlap in time on one
+ *    device -- on different streams, or from different threads without
+ *    ordering between their streams -- race on the region and give wrong
+ *    results: order them on one stream. */
+impconv_status impconv_conv2d_noalloc(int kind, int dtype, int64_t batch, int64_t M, const int64_t* m,
+                                      const int64_t* n, const void* f, const void* g, void* h,
+                                      uint32_t flags, void* stream);
+
+/* Bytes of work memory available to impconv_conv2d_noalloc on each device. */
+size_t impconv_noalloc_capacity(void);
 
 /* 2D centered Hermitian ternary convolution, Sec. 4 (tconv2): f, g, e and h
  * are [batch][n0][n1] in the 2D Hermitian storage of impconv_conv2d

@@ -25,7 +25,7 @@ import torch
 
 __all__ = [
     "lib", "available", "ImpconvError", "conv1d_complex", "conv1d_hermitian", "conv1d_ternary",
-    "conv2d", "conv3d", "RaggedPlan", "conv1d_complex_ad", "ragged_conv_ad", "workspace_bytes",
+    "conv2d", "conv3d", "conv2d_noalloc", "noalloc_capacity", "RaggedPlan", "conv1d_complex_ad", "ragged_conv_ad", "workspace_bytes",
     "timing_enable", "timing_report",
     "EXPLICIT_PADDED", "REV_F", "CONJ_G", "REV_OUT", "NO_SYMMETRIZE", "ONE_STREAM",
 ]
@@ -95,6 +95,9 @@ def lib():
                                 _u32, _p], st),
             "impconv_conv3d": ([ctypes.c_int, ctypes.c_int, _i64, _i64, _p, _p, _p, _p, _p, _p, _sz,
                                 _u32, _p], st),
+            "impconv_conv2d_noalloc": ([ctypes.c_int, ctypes.c_int, _i64, _i64, _p, _p, _p, _p, _p, _u32, _p],
+                                       st),
+            "impconv_noalloc_capacity": ([], _sz),
             "impconv_ragged_plan_create": ([ctypes.c_int, _i64, _p, _p, ctypes.POINTER(_p)], st),
             "impconv_ragged_workspace": ([_p, ctypes.POINTER(_sz)], st),
             "impconv_ragged_execute": ([_p, _p, _p, _p, _p, _sz, _u32, _p], st),
@@ -311,6 +314,44 @@ def conv2d(f, g, kind: str = "complex", m=None, symmetrize: bool = True, method:
     flags |= 0 if symmetrize else NO_SYMMETRIZE
     flags |= {"implicit": 0, "explicit": EXPLICIT_PADDED, "pruned": EXPLICIT_PADDED | EXPLICIT_PRUNED}[method]
     return _convnd(2, f, g, kind, m, flags)
+
+
+def conv2d_noalloc(f, g, kind: str = "complex", m=None, symmetrize: bool = True, out=None, flags: int = 0):
+    """impconv_conv2d_noalloc: conv2d (implicit method) whose work arrays are
+    the library's fixed per-device region instead of memory allocated here.
+    Pass `out` (shape (B, n0, n1), or (n0, n1) for unbatched inputs) to
+    allocate nothing at all.  impconv_init runs first on the current device."""
+    flags |= 0 if symmetrize else NO_SYMMETRIZE
+    k = {"complex": COMPLEX, "hermitian": HERMITIAN}[kind]
+    if f.shape != g.shape or f.dtype != g.dtype:
+        raise ValueError("f and g must share shape and dtype")
+    dev = _dev(f, g)
+    if f.dim() not in (2, 3, 4):
+        raise ValueError("inputs must be (n0, n1), (B, n0, n1) or (B, M, n0, n1)")
+    n = tuple(f.shape[-2:])
+    B = 1 if f.dim() == 2 else f.shape[0]
+    M = f.shape[1] if f.dim() == 4 else 1
+    if m is None:
+        if k != COMPLEX:
+            raise ValueError("Hermitian 2D convolutions need the logical sizes m")
+        m = n
+    m = tuple(int(x) for x in m)
+    h = torch.empty((B, *n), dtype=f.dtype, device=dev) if out is None else out
+    if h.shape != (B, *n) and not (f.dim() == 2 and h.shape == n):
+        raise ValueError(f"out must have shape {(B, *n)}")
+    if h.dtype != f.dtype or h.device != dev or not h.is_contiguous():
+        raise ValueError("out must be a contiguous tensor of the inputs' dtype on their device")
+    with torch.cuda.device(dev):
+        _check(lib().impconv_init(), "impconv_init")
+        _check(lib().impconv_conv2d_noalloc(k, _dtype_code(f), B, M, (ctypes.c_int64 * 2)(*m),
+                                            (ctypes.c_int64 * 2)(*n), _ptr(f), _ptr(g), _ptr(h), flags,
+                                            ctypes.c_void_p(_stream(dev))), "conv2d_noalloc")
+    return h.view(*n) if f.dim() == 2 and out is None else h
+
+
+def noalloc_capacity() -> int:
+    """Bytes of work memory impconv_conv2d_noalloc has on each device."""
+    return int(lib().impconv_noalloc_capacity())
 
 
 def conv2d_ternary(f, g, e, m, symmetrize: bool = True, method: str = "implicit"):

@@ -21,7 +21,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-I", os.path.join(HERE, "..", "include")]
 SOURCES = ["k_row_complex.hip", "k_row_comp.hip", "k_row_herm.hip", "k_row_pq.hip", "k_col_pad.hip", "k_col_comp.hip", "k_col_cen.hip", "k_col_ter.hip",
            "k_col_fft.hip", "k_col_fs.hip", "k_misc.hip", "twiddle.hip", "multid.hip",
-           "ragged.hip", "plan.hip", "abi.hip"]
+           "ragged.hip", "plan.hip", "noalloc.hip", "abi.hip"]
 
 
 def _compile(src: str) -> str:

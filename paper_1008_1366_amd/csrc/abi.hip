@@ -253,7 +253,8 @@ const char* impconv_last_error(void) { return g_err.c_str(); }
 
 impconv_status impconv_init(void)
 {
-    return tables() ? IMPCONV_OK : IMPCONV_E_HIP;
+    if (!tables()) return IMPCONV_E_HIP;
+    return noalloc_setup();
 }
 
 impconv_status impconv_conv1d_workspace(int kind, int dtype, int64_t batch, int64_t M, int64_t m,

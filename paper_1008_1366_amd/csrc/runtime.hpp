@@ -39,6 +39,10 @@ const DevTables* tables();
 // split (synchronous; nullptr on HIP failure).
 const void* fs_twiddles(int dt, int64_t N2, int64_t N1);
 
+// Resolves, once per device, the device address of the fixed work memory of
+// impconv_conv2d_noalloc on the current device (impconv_init calls it).
+impconv_status noalloc_setup();
+
 // FP64 host generation, exposed for the host-side unit test.
 void gen_roots(int64_t denom, int64_t count, double* out_re_im);
 
