@@ -540,7 +540,8 @@ def wl_c5(args):
     # schedule: the four-step split of each long class is autotuned at plan
     # creation, outside the timed region
     plan = ic.RaggedPlan(ms, offs, dtype=cdt, autotune=not args.no_autotune)
-    sched = [{k: c[k] for k in ("N", "pairs", "method", "N1", "N2") if k in c} for c in plan.schedule()]
+    info = plan.schedule_info()
+    sched = [{k: c[k] for k in ("N", "pairs", "method", "E", "N1", "N2", "source") if k in c} for c in info["classes"]]
     cs = 8 if cdt == torch.complex64 else 16
 
     def run():
@@ -557,12 +558,17 @@ def wl_c5(args):
     # writes m).  Three executions per step: forward, grad f, grad g.
     Ns = 2 ** np.ceil(np.log2(ms)).astype(np.int64)
     small = Ns <= 8192
-    kb = {"k_conv1d_complex": 3 * int(ms[small].sum()) * cs,
+    # the fused classes run as one work-queue launch (k_ragged_queue) or one
+    # k_conv1d_complex launch per class, as the autotuner chose
+    qd = small & (Ns <= (8192 if cdt == torch.complex64 else 4096)) if info["fused_launch"] == "queue" else small & False
+    kb = {"k_conv1d_complex": 3 * int(ms[small & ~qd].sum()) * cs,
+          "k_ragged_queue": 3 * int(ms[qd].sum()) * cs,
           "colpass_fourstep_bwd": 2 * int((ms[~small] + 2 * Ns[~small]).sum()) * cs,
           "k_conv1d_cyclic": 6 * int(Ns[~small].sum()) * cs,
           "colpass_fourstep_fwd": int((2 * Ns[~small] + ms[~small]).sum()) * cs}
     kbytes_step = {k: 3 * v for k, v in kb.items()}
-    kflops_step = {"k_conv1d_complex": 3 * float(sum(flops_row_complex(int(n)) for n in Ns[small]))}
+    kflops_step = {"k_conv1d_complex": 3 * float(sum(flops_row_complex(int(n)) for n in Ns[small & ~qd])),
+                   "k_ragged_queue": 3 * float(sum(flops_row_complex(int(n)) for n in Ns[qd]))}
     step_bytes = 9 * tot * cs  # compulsory: f, g, h of each execution
 
     def cpu_baseline(h_gpu):
@@ -606,6 +612,7 @@ def wl_c5(args):
     cfg = {"workload": f"{len(ms)} uneven complex 1D pairs, m = 2^round(U(6,16)), packed, forward + backward "
                        f"(both gradients) per step, {'complex64' if cdt == torch.complex64 else 'complex128'}",
            "pairs": int(len(ms)), "sum_m": tot, "dtype": args.dtype, "schedule": sched,
+           "fused_launch": info["fused_launch"], "fused_tuned_ms": info.get("fused_tuned_ms"),
            "autotuned": not args.no_autotune}
     def graph_step():
         """The same step captured once in a hipGraph (forward, backward and

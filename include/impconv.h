@@ -321,7 +321,16 @@ impconv_status impconv_conv2d_ternary(int dtype, int64_t batch, const int64_t* m
  * arrays (pairs must not overlap).  The plan copies the descriptors to the
  * device once (synchronously, at creation) and groups pairs by FFT size;
  * executing it launches nothing but kernels, so it may be captured in a
- * hipGraph.  The size classes run concurrently: the device has three
+ * hipGraph.  The fused size classes (N <= 8192; complex128: N <= 4096) run
+ * together in one persistent launch by default: items of as many pairs of
+ * one class as fill a 512-thread workgroup, numbered longest class first,
+ * are taken from an atomic counter by one workgroup per compute unit until
+ * none is left; the counter occupies the first 256 bytes of the workspace
+ * and is cleared by a one-thread kernel at the start of every execution
+ * (so work must be 16-byte aligned, and executions that may overlap on the
+ * GPU need distinct workspaces).  impconv_ragged_plan_set_fused or the
+ * autotuner may choose one launch per class instead.  The size classes
+ * (the queue launch counting as one) run concurrently: the device has three
  * auxiliary streams (default priority) and events, created with its first
  * ragged plan and kept until the process ends (shared by all plans of the
  * device); execute forks them from `stream` with an event and joins them
@@ -333,8 +342,10 @@ impconv_status impconv_conv2d_ternary(int dtype, int64_t batch, const int64_t* m
  * that may overlap on the GPU need distinct workspaces.  While one thread
  * captures an execution, no other thread may execute a ragged plan on the
  * same device without IMPCONV_ONE_STREAM (the auxiliary streams are part of
- * the capture until it ends).  Only impconv_ragged_plan_autotune changes a plan
- * (its schedule, never its results' definition).  REV_F / CONJ_G / REV_OUT apply per pair
+ * the capture until it ends).  Only impconv_ragged_plan_autotune and
+ * impconv_ragged_plan_set_fused change a plan (its schedule, never its
+ * results' definition); call them while no execution of the plan is
+ * pending.  REV_F / CONJ_G / REV_OUT apply per pair
  * as in impconv_conv1d_complex.  IMPCONV_ONE_STREAM runs the size classes one
  * after another on `stream` alone (no fork or join; the auxiliary streams
  * stay idle) with the same kernels, so its results are bitwise those of the
@@ -357,29 +368,60 @@ impconv_status impconv_ragged_execute(const impconv_ragged_plan* plan, const voi
  * must not be launched after the plan is destroyed.  NULL is accepted. */
 impconv_status impconv_ragged_plan_destroy(impconv_ragged_plan* plan);
 
-/* Autotuner of the plan's schedule.  Size classes whose FFT size N exceeds
- * one workgroup's transform (N > 8192) run the four-step form, whose split
- * N = N1 x N2 sets the FFT sizes (and radices) of its row and column passes.
- * For each such class this call times every supported split (16 <= N2 <=
- * 4096, 16 <= N1 <= 8192) on zero-filled temporary arrays of the plan's
- * packed extent, three executions each after one warm-up, on `stream`, and
- * keeps the fastest in the plan.  It allocates and frees device memory
- * (3 x extent elements plus the workspace size) and synchronizes the stream:
- * call it outside graph capture.  Results of a tuned plan equal those of the
- * untuned one up to rounding.  Errors: E_ARG (null plan, other device),
- * E_HIP (allocation, launch or timing failure; the plan keeps its previous
- * schedule for the classes not yet tuned).  A plan without four-step classes
- * returns IMPCONV_OK at once. */
+/* Autotuner of the plan's schedule, timed on zero-filled temporary arrays
+ * of the plan's packed extent (three executions per candidate after one
+ * warm-up, on `stream`):
+ *  - four-step classes (N > 8192): every supported split N = N1 x N2
+ *    (16 <= N2 <= 4096, 16 <= N1 <= 8192), which sets the FFT sizes and
+ *    radices of their row and column passes;
+ *  - classes in the work queue: both supported values per thread E (the row
+ *    kernels' choice and half of it), which set the radices and the pairs
+ *    per item, each timed as a queue launch of that class alone;
+ *  - then the fused classes as one queue launch against one launch per
+ *    class, keeping the faster.
+ * Each class's winner is recorded in the process-wide schedule cache under
+ * (architecture, variant "fourstep" or "fused", dtype, N); a class whose
+ * key is already there takes the recorded choice without being timed
+ * (impconv_ragged_plan_schedule reports "source": "cache").  The call
+ * allocates and frees device memory (3 x extent elements plus the
+ * workspace size) and synchronizes the stream: call it outside graph
+ * capture, while no execution of the plan is pending.  Results of a tuned
+ * plan equal those of the untuned one up to rounding.  Errors: E_ARG (null
+ * plan, other device), E_HIP (allocation, launch or timing failure; the
+ * plan keeps its previous schedule for the classes not yet tuned). */
 impconv_status impconv_ragged_plan_autotune(impconv_ragged_plan* plan, void* stream);
 
-/* The plan's schedule as JSON text: one object per size class, longest
- * first, with its FFT size N, pair count, method ("fused" or "four-step"),
- * the split N1, N2 in use and the autotuner's times per candidate N2 (ms).
- * Writes at most cap - 1 characters and a terminating NUL to buf (buf may be
- * NULL with cap 0) and the full length to *len.  Errors: E_ARG (null plan or
- * len). */
+/* Fixes how the plan's fused classes run: queue = 1 one persistent
+ * work-queue launch, 0 one launch of the fused row kernel per class; elems
+ * = values per thread in the queue for every queued class that supports it
+ * (the row kernels' choice or half of it), 0 = the row kernels' choice.
+ * Copies the queue's class table to the device (synchronous): call it
+ * outside graph capture, while no execution of the plan is pending.
+ * Errors: E_ARG (null plan, other device, queue not 0/1, elems < 0), E_HIP. */
+impconv_status impconv_ragged_plan_set_fused(impconv_ragged_plan* plan, int queue, int elems);
+
+/* The plan's schedule as JSON text: {"fused_launch": "queue" or
+ * "per-class", "queue_grid": workgroups of the queue launch, "fused_tuned_ms":
+ * {"queue": ms, "per-class": ms} (after autotuning), "classes": [...]}, one
+ * object per size class, longest first, with its FFT size N, pair count,
+ * method ("queue", "fused" or "four-step"), stream lane, values per thread
+ * E (fused) or split N1, N2 (four-step), the source of that choice
+ * ("default", "timed", "cache", "set") and the autotuner's times per
+ * candidate (ms).  Writes at most cap - 1 characters and a terminating NUL to
+ * buf (buf may be NULL with cap 0) and the full length to *len.  Errors:
+ * E_ARG (null plan or len). */
 impconv_status impconv_ragged_plan_schedule(const impconv_ragged_plan* plan, char* buf, size_t cap,
                                             size_t* len);
+
+/* Process-wide schedule cache of the autotuner (host memory, thread-safe).
+ * Export writes a JSON array of {"arch", "variant", "dtype", "N", "choice",
+ * "ms"} (choice: values per thread E for "fused", column length N2 for
+ * "fourstep") to buf as impconv_ragged_plan_schedule does; import merges
+ * such an array (all of it or, on a malformed entry, nothing: E_ARG); clear
+ * empties the cache. */
+impconv_status impconv_schedule_cache_export(char* buf, size_t cap, size_t* len);
+impconv_status impconv_schedule_cache_import(const char* json);
+impconv_status impconv_schedule_cache_clear(void);
 
 /* ----------------------------------------------------------------------
  * Descriptor-based plans: one create / execute pair for every kind and

@@ -26,7 +26,8 @@ import torch
 __all__ = [
     "lib", "available", "ImpconvError", "conv1d_complex", "conv1d_hermitian", "conv1d_ternary",
     "conv2d", "conv3d", "conv2d_noalloc", "noalloc_capacity", "RaggedPlan", "conv1d_complex_ad", "ragged_conv_ad", "workspace_bytes",
-    "timing_enable", "timing_report",
+    "timing_enable", "timing_report", "schedule_cache_export", "schedule_cache_import", "schedule_cache_clear",
+    "schedule_cache_save", "schedule_cache_load",
     "EXPLICIT_PADDED", "REV_F", "CONJ_G", "REV_OUT", "NO_SYMMETRIZE", "ONE_STREAM",
 ]
 
@@ -111,6 +112,10 @@ def lib():
             "impconv_conv1d_complex_ragged_workspace": ([ctypes.c_int, _i64, _p, _p, ctypes.POINTER(_sz)], st),
             "impconv_conv1d_complex_ragged": ([ctypes.c_int, _i64, _p, _p, _p, _p, _p, _p, _sz, _u32, _p], st),
             "impconv_ragged_plan_schedule": ([_p, ctypes.c_char_p, _sz, ctypes.POINTER(_sz)], st),
+            "impconv_ragged_plan_set_fused": ([_p, ctypes.c_int, ctypes.c_int], st),
+            "impconv_schedule_cache_export": ([ctypes.c_char_p, _sz, ctypes.POINTER(_sz)], st),
+            "impconv_schedule_cache_import": ([ctypes.c_char_p], st),
+            "impconv_schedule_cache_clear": ([], st),
             "impconv_timing_enable": ([ctypes.c_int], None),
             "impconv_timing_report": ([ctypes.c_char_p, _sz], _sz),
         }
@@ -424,6 +429,43 @@ def _destroy_deferred() -> None:
         _lib.impconv_ragged_plan_destroy(_deferred_plans.pop())
 
 
+def schedule_cache_export() -> list:
+    """Entries of the process-wide schedule cache: {"arch", "variant"
+    ("fused": values per thread; "fourstep": column length N2), "dtype",
+    "N", "choice", "ms"}."""
+    import json
+    n = _sz()
+    _check(lib().impconv_schedule_cache_export(None, 0, ctypes.byref(n)), "schedule_cache_export")
+    buf = ctypes.create_string_buffer(n.value + 1)
+    _check(lib().impconv_schedule_cache_export(buf, n.value + 1, ctypes.byref(n)), "schedule_cache_export")
+    return json.loads(buf.value.decode())
+
+
+def schedule_cache_import(entries) -> None:
+    """Merges entries (the list schedule_cache_export returns, or its JSON
+    text) into the process-wide schedule cache."""
+    import json
+    text = entries if isinstance(entries, str) else json.dumps(entries)
+    _check(lib().impconv_schedule_cache_import(text.encode()), "schedule_cache_import")
+
+
+def schedule_cache_clear() -> None:
+    _check(lib().impconv_schedule_cache_clear(), "schedule_cache_clear")
+
+
+def schedule_cache_save(path: str) -> None:
+    """Writes the schedule cache to a JSON file."""
+    import json
+    with open(path, "w") as fh:
+        json.dump(schedule_cache_export(), fh, indent=1)
+
+
+def schedule_cache_load(path: str) -> None:
+    """Merges a JSON file written by schedule_cache_save."""
+    with open(path) as fh:
+        schedule_cache_import(fh.read())
+
+
 class RaggedPlan:
     """Uneven-length batch of complex 1D convolutions packed in one array:
     pair j uses elements offsets[j] .. offsets[j] + ms[j] - 1.  With
@@ -459,20 +501,41 @@ class RaggedPlan:
             self.autotune()
 
     def autotune(self):
-        """Time every supported four-step split of the long size classes on
-        this device and keep the fastest (synchronous; not under capture)."""
+        """Time the candidate schedules on this device and keep the fastest
+        (synchronous; not under capture): every supported four-step split of
+        the long size classes, both values-per-thread of every class in the
+        work queue, and the queue against one launch per fused class.  Class
+        choices found in the process-wide schedule cache are taken from it."""
         with torch.cuda.device(self.device):
             _check(lib().impconv_ragged_plan_autotune(self._h, ctypes.c_void_p(_stream(self.device))),
                    "impconv_ragged_plan_autotune")
 
-    def schedule(self) -> list:
-        """Per size class: N, pair count, method, split and autotuner times."""
+    def set_fused(self, queue: bool, elems: int = 0):
+        """Fix how the fused size classes run: one work-queue launch (queue =
+        True) or one launch per class, with `elems` values per thread in the
+        queue for every class that supports it (0: the row kernels' choice).
+        Synchronous; not under capture."""
+        with torch.cuda.device(self.device):
+            _check(lib().impconv_ragged_plan_set_fused(self._h, int(bool(queue)), int(elems)),
+                   "impconv_ragged_plan_set_fused")
+
+    def schedule_info(self) -> dict:
+        """The plan's schedule: how the fused classes launch ("queue": one
+        persistent work-queue launch, or "per-class"), the queue's grid, the
+        autotuner's times of both, and per size class N, pair count, method
+        ("queue", "fused" or "four-step"), stream, values per thread E or
+        split N1 x N2, where the choice came from ("default", "timed",
+        "cache") and the autotuner's times per candidate."""
         import json
         n = _sz()
         _check(lib().impconv_ragged_plan_schedule(self._h, None, 0, ctypes.byref(n)), "schedule")
         buf = ctypes.create_string_buffer(n.value + 1)
         _check(lib().impconv_ragged_plan_schedule(self._h, buf, n.value + 1, ctypes.byref(n)), "schedule")
         return json.loads(buf.value.decode())
+
+    def schedule(self) -> list:
+        """Per size class entries of schedule_info()."""
+        return self.schedule_info()["classes"]
 
     def execute(self, f, g, flags: int = 0, out=None, work=None):
         _dev(f, g)

@@ -19,9 +19,9 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-variable", "-Wno-unused-but-set-variable",
          "-I", os.path.join(HERE, "..", "include")]
-SOURCES = ["k_row_complex.hip", "k_row_comp.hip", "k_row_herm.hip", "k_row_pq.hip", "k_col_pad.hip", "k_col_comp.hip", "k_col_cen.hip", "k_col_ter.hip",
+SOURCES = ["k_row_queue.hip", "k_row_complex.hip", "k_row_comp.hip", "k_row_herm.hip", "k_row_pq.hip", "k_col_pad.hip", "k_col_comp.hip", "k_col_cen.hip", "k_col_ter.hip",
            "k_col_fft.hip", "k_col_fs.hip", "k_misc.hip", "twiddle.hip", "multid.hip",
-           "ragged.hip", "plan.hip", "noalloc.hip", "abi.hip"]
+           "ragged.hip", "schedule.hip", "plan.hip", "noalloc.hip", "abi.hip"]
 
 
 def _compile(src: str) -> str:

@@ -29,6 +29,17 @@ constexpr int kPqMax = 4096;  // complex64; complex128: kPqMax / 2 (register bud
 constexpr int kPqMaxP = 3;
 hipError_t launch_row_pq(int dt, int NP, int P, const RowArgs& a, hipStream_t s);
 
+// Ragged batches: one persistent launch over a work queue of the fused size
+// classes (queue.hpp).  d_cls: ncls class records in device memory, ctr: a
+// counter in device memory (cleared by the launch), grid: workgroups.
+struct QueueClass;
+hipError_t launch_row_queue(int dt, const RowArgs& a, const QueueClass* d_cls, int ncls, unsigned* ctr, int grid,
+                            hipStream_t s);
+// Whether the queue kernel runs FFT size N with E values per thread (the
+// row kernels' choice or half of it), and the row kernels' choice.
+bool queue_supports(int dt, int N, int E);
+int queue_default_E(int dt, int N);
+
 // dst[r][j] = j < copy ? src[r][j] : 0, j < dst_ld
 hipError_t launch_pad_rows(int dt, const void* src, void* dst, int64_t nrows, int64_t src_ld,
                            int64_t copy, int64_t dst_ld, hipStream_t s);

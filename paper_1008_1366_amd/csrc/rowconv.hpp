@@ -150,12 +150,13 @@ __device__ __forceinline__ C<T> ldz(const C<T>* U, int j, int m)
 // One M = 1 row by one group: f and g are read once; both residues r = 0, 1
 // are formed from the same registers (x0 = f, x1 = zeta_{2N}^k f, likewise
 // g) and transformed together, through two exchange buffers (fft2, DUAL) or
-// one after the other through one.
-template <typename T, int N, bool DUAL, bool COMP>
+// one after the other through one.  E values per thread (G = N / E threads
+// per row, t < G).
+template <typename T, int N, int E, bool DUAL, bool COMP>
 __device__ __forceinline__ void conv_complex_row(const RowArgs& a, const RowCtx& c, int t, C<T>* lds,
                                                  C<T>* lds1)
 {
-    constexpr int E = fft_E<T>(N), G = N / E;
+    constexpr int G = N / E;
     const TwSrc<T, COMP> twN = tw_src<T, COMP>(a, tw_off(N));
     const TwSrc<T, COMP> tw2N = tw_src<T, COMP>(a, tw_off(2 * N));
     const C<T>* F = (const C<T>*)a.f + c.of;
@@ -224,7 +225,7 @@ k_conv1d_complex(RowArgs a)
     C<T>* lds = sh + grp * LDSN;
 
     if constexpr (!MD) {
-        conv_complex_row<T, N, DUAL, COMP>(a, c, t, lds, DUAL ? sh + (GPB + grp) * LDSN : lds);
+        conv_complex_row<T, N, E, DUAL, COMP>(a, c, t, lds, DUAL ? sh + (GPB + grp) * LDSN : lds);
         return;
     }
 

@@ -128,6 +128,43 @@ def test_ragged_autotune_and_schedule_null_arguments(L):
     assert L.impconv_ragged_plan_schedule(None, None, 0, ctypes.byref(n)) == 1
 
 
+def test_ragged_set_fused_null_arguments(L):
+    assert L.impconv_ragged_plan_set_fused(None, 1, 0) == 1
+
+
+def test_schedule_cache_roundtrip(L):
+    """The autotuner's schedule cache lives in host memory: import merges a
+    JSON array, export returns every entry once, a malformed import changes
+    nothing, clear empties it."""
+    import json
+
+    import paper_1008_1366_amd as ic
+    ic.schedule_cache_clear()
+    assert ic.schedule_cache_export() == []
+    entries = [{"arch": "gfx950", "variant": "fused", "dtype": "c64", "N": 1024, "choice": 8, "ms": 0.0125},
+               {"arch": "gfx950", "variant": "fourstep", "dtype": "c128", "N": 65536, "choice": 256, "ms": 1.5}]
+    ic.schedule_cache_import(entries)
+    got = sorted(ic.schedule_cache_export(), key=lambda e: e["N"])
+    assert got == sorted(entries, key=lambda e: e["N"])
+    # a later entry of the same key replaces the earlier one
+    ic.schedule_cache_import(json.dumps([dict(entries[0], choice=16, ms=0.01)]))
+    got = {(e["variant"], e["N"]): e["choice"] for e in ic.schedule_cache_export()}
+    assert got == {("fused", 1024): 16, ("fourstep", 65536): 256}
+    # malformed: an unknown variant in the second entry -> E_ARG, nothing merged
+    bad = json.dumps([dict(entries[0], N=2048), dict(entries[0], variant="other")])
+    assert L.impconv_schedule_cache_import(bad.encode()) == 1
+    assert b"variant" in L.impconv_last_error()
+    assert len(ic.schedule_cache_export()) == 2
+    for broken in ('[{"arch": "gfx950", "variant": "fused", "dtype": "c64", "N": 0, "choice": 8}]',
+                   '[{"arch": "gfx950", "variant": "fused", "dtype": "c32", "N": 64, "choice": 8}]',
+                   '[{"arch": "gfx950", "variant": "fused", "dtype": "c64", "N": 64}]',
+                   '[{"arch": "gfx950", "variant": "fused"'):
+        assert L.impconv_schedule_cache_import(broken.encode()) == 1
+    assert len(ic.schedule_cache_export()) == 2
+    ic.schedule_cache_clear()
+    assert ic.schedule_cache_export() == []
+
+
 def test_plan_create_validation(L):
     """The descriptor plan rejects bad descriptors with the one-shot calls'
     codes before touching a device."""
