@@ -275,6 +275,59 @@ def wl_c3(args):
                 kbytes=kbytes, kflops=kflops, cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy())
 
 
+def wl_x3(args):
+    """3D complex 256^3 (Sec. 3.4's complex 3D timing comparison), batch of 2
+    pairs of unit-disk inputs: implicit against the explicitly padded
+    comparator (2m per axis) and its pruned form."""
+    import torch
+    import paper_1008_1366_amd as ic
+    import synth
+    cdt = torch.complex64 if args.dtype == "c64" else torch.complex128
+    m, B = 256, args.batch or 2
+    f = synth.unit_disk((B, m, m, m), 301)
+    g = synth.unit_disk((B, m, m, m), 302)
+    F = torch.from_numpy(f).to("cuda", cdt)
+    G = torch.from_numpy(g).to("cuda", cdt)
+    del f, g
+    cs = 8 if cdt == torch.complex64 else 16
+    S = B * m ** 3 * cs  # one stored batch of inputs
+    run = lambda: ic.conv3d(F, G)
+    expl = lambda: ic.conv3d(F, G, method="explicit")
+    pruned = lambda: ic.conv3d(F, G, method="pruned")
+    # algorithmic bytes per step (m a power of two, so every residue array
+    # has the input's size S): x backward f, g 2S -> 4S; y backward 4S -> 8S;
+    # z rows 8S -> 4S; y forward 4S -> 2S; x forward 2S -> S
+    step_bytes = 39 * S
+
+    def cpu_baseline(h_gpu, h_expl=None):
+        """Oracle direct sums at 32 seeded output points of the first pair
+        (about m^3 / 8 multiply-adds each on average), extrapolated to the
+        whole step by multiply-add count; errors at those points."""
+        import oracle
+        rng = synth.rng(8)
+        pts = rng.integers(0, m, (32, 3))
+        dt_np = np.complex64 if cdt == torch.complex64 else np.complex128
+        fr = np.asarray(F[0].cpu().numpy().astype(dt_np), np.complex128)
+        gr = np.asarray(G[0].cpu().numpy().astype(dt_np), np.complex128)
+        t0 = time.perf_counter()
+        ref = oracle.convnd_complex_at(fr, gr, pts)
+        t = time.perf_counter() - t0
+        macs = float(np.sum(np.prod(pts + 1.0, axis=1)))
+        full = B * (m * (m + 1) / 2.0) ** 3
+        errs = {"implicit": float(np.linalg.norm(h_gpu[0][tuple(pts.T)] - ref) / np.linalg.norm(ref)), "points": 32}
+        if h_expl is not None:
+            errs["explicit"] = float(np.linalg.norm(h_expl[0][tuple(pts.T)] - ref) / np.linalg.norm(ref))
+        return {"value": B / (t / macs * full), "unit": "convs/s", "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": f"32 output points of the first pair, direct FP64 sums ({t:.2f} s), extrapolated "
+                          f"to whole convolutions by multiply-add count"}, errs
+
+    cfg = {"workload": f"3D complex implicit dealiased convolution {m}^3, batch {B} pairs per step, "
+                       f"{'complex64' if cdt == torch.complex64 else 'complex128'}",
+           "m": [m, m, m], "batch": B, "M": 1, "dtype": args.dtype}
+    return dict(run=run, explicit=expl, pruned=pruned, convs=B, step_bytes=step_bytes, kbytes={}, kflops={},
+                cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy(), bound="hbm")
+
+
 def wl_c2(args):
     """1D centered Hermitian m=16384, |k|^-5/6 random phase, batch of B convolutions."""
     import torch
@@ -853,7 +906,7 @@ def wl_t1(args):
                 cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy())
 
 
-WORKLOADS = {"c1": wl_c1, "c2": wl_c2, "c3": wl_c3, "c4": wl_c4, "c5": wl_c5, "t1": wl_t1, "t2": wl_t2,
+WORKLOADS = {"c1": wl_c1, "c2": wl_c2, "c3": wl_c3, "x3": wl_x3, "c4": wl_c4, "c5": wl_c5, "t1": wl_t1, "t2": wl_t2,
              "e2": wl_e2}
 
 

@@ -249,6 +249,14 @@ size_t impconv_timing_report(char* buf, size_t cap);
  * transform sizes with the zero padding fused into the loads, no transform
  * of an all-zero column and the crop fused into the last store (work
  * 2 * batch * M * 2N0 * m1 complex values).
+ * IMPCONV_EXPLICIT_PADDED (3D complex): the same comparator in 3D -- inputs
+ * copied into zero-padded 2N0 x 2N1 x 2N2 arrays, full-size FFTs along all
+ * three axes, product, inverse, crop (work 2 * batch * M * 8 N0 N1 N2
+ * complex values; m0, m1 <= 2048, m2 <= 4096).  With
+ * IMPCONV_EXPLICIT_PRUNED: padding fused into the loads, x transforms of the
+ * m1 x m2 data columns only, y transforms of the m2 data columns, inverse
+ * transforms of the cropped rows only, the last one writing h (work
+ * 2 * batch * M * 4 N0 N1 * m2 complex values).
  * Outer axes support m[d] <= 4096 in this build; the innermost axis
  * m <= 8192 (complex) or m <= 16384 (Hermitian).
  * ---------------------------------------------------------------------- */

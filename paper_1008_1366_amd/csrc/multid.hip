@@ -272,6 +272,15 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
         p->work = size_t(2) * batch * M * vol * size_t(p->Pe[nd - 1] + 1) * cs;
         return IMPCONV_OK;
     }
+    if ((flags & IMPCONV_EXPLICIT_PADDED) && kind == IMPCONV_COMPLEX && nd == 3) {
+        // padded f and g, [b][2N0][2N1][M][2N2] (pruned: only the m2 data
+        // columns of the last axis, [b][2N0][2N1][M][m2])
+        const int64_t P0 = 2 * p->Np[0], P1 = 2 * p->Np[1], P2 = 2 * p->Np[2];
+        if (P0 > kColMax || P1 > kColMax || P2 > kRowMax)
+            return fail(IMPCONV_E_UNSUPPORTED, "explicit 3D complex comparator supports m0, m1 <= 2048, m2 <= 4096");
+        p->work = size_t(2) * batch * M * P0 * P1 * ((flags & IMPCONV_EXPLICIT_PRUNED) ? m[2] : P2) * cs;
+        return IMPCONV_OK;
+    }
     if ((flags & IMPCONV_EXPLICIT_PADDED) && kind == IMPCONV_COMPLEX) {
         // padded f and g, [b][2N0][M][2N1] (pruned: only the m1 data columns, [b][2N0][M][m1])
         const int64_t P0 = 2 * p->Np[0], P1 = 2 * p->Np[1];
@@ -701,6 +710,129 @@ impconv_status run_herm_explicit(const DevTables& tb, const PlanND& p, const voi
     return IMPCONV_OK;
 }
 
+// Conventional 3D complex comparator (Sec. 3.4 timing comparison): inputs
+// zero padded to P_d = 2 N_d per axis (N_d = 2^ceil(log2 m_d)), full-size
+// FFTs along x, y and z, product summed over the M terms, inverse
+// transforms, crop.  Padded arrays W[q] are [b][P0][P1][M][Z], Z = P2.
+// Pruned: the padding is never materialized and no all-zero column is
+// transformed -- the x FFTs read the m0 stored rows of the m1 x m2 data
+// columns straight from f and g, the y FFTs run on the m2 data columns of
+// every x' plane, the z rows read their m2 data entries (zero beyond, Z =
+// m2 stored) and keep m2 outputs, and the inverse y / x FFTs produce only
+// the m1 / m0 rows the crop keeps, the last one writing h directly.
+impconv_status run_complex3d_explicit(const DevTables& tb, const PlanND& p, const void* f, const void* g,
+                                      void* h, char* w, hipStream_t s, bool pruned)
+{
+    const int dt = p.dt;
+    const int64_t B = p.batch, M = p.M;
+    const size_t cs = csize(dt);
+    const int64_t m0 = p.m[0], m1 = p.m[1], m2 = p.m[2];
+    const int64_t P0 = 2 * p.Np[0], P1 = 2 * p.Np[1], P2 = 2 * p.Np[2];
+    const int64_t Z = pruned ? m2 : P2;                 // stored last-axis entries of W
+    const int64_t plane = P1 * M * Z;                   // one x' plane of W
+    const size_t arr = size_t(B) * P0 * plane * cs;     // one padded input
+    void* W[2] = {w, w + arr};
+    const void* src[2] = {f, g};
+    const int64_t sin_i = m0 * m1 * m2, sin_b = M * sin_i;  // input strides: term, batch
+    auto atw = [&](void* base, int64_t elems) { return static_cast<char*>(base) + elems * int64_t(cs); };
+    auto atc = [&](const void* base, int64_t elems) { return static_cast<const char*>(base) + elems * int64_t(cs); };
+    for (int q = 0; q < 2; ++q) {
+        if (!pruned) {
+            HIPCHK(launch_copy2d(dt, W[q], W[q], 1, 1, 0, 0, 0, 0, 0, Z, 0, 0, B * P0 * P1 * M, Z, s), "explicit zero");
+            // per batch entry: slabs (x < m0, i), blocks of m1 rows (y) x m2 columns (z)
+            for (int64_t b = 0; b < B; ++b)
+                HIPCHK(launch_copy2d(dt, atc(src[q], b * sin_b), atw(W[q], b * P0 * plane), m0 * M, M, m1 * m2, sin_i, m2,
+                                     plane, Z, M * Z, m1, m2, m1, m2, s), "explicit pad");
+            // x FFT over every (y', i, z) column of each batch entry
+            ColArgs a = col_args(tb, dt);
+            a.in[0] = a.out[0] = W[q];
+            a.nslab = B;
+            a.in_bs = a.out_bs = P0 * plane;
+            a.ncols = plane;
+            a.in_ld = a.out_ld = plane;
+            a.n_in = a.n_out = int(P0);
+            HIPCHK(launch_col(dt, int(P0), kFft, 1, a, s), "explicit x FFT");
+        } else {
+            // x FFT of the data columns (y < m1, z < m2) read from the input:
+            // per batch entry, slabs (i, y), columns z
+            for (int64_t b = 0; b < B; ++b) {
+                ColArgs a = col_args(tb, dt);
+                a.in[0] = atc(src[q], b * sin_b);
+                a.out[0] = atw(W[q], b * P0 * plane);
+                a.nslab = M * m1;
+                a.nsub = m1;
+                a.in_bs = sin_i;
+                a.in_bs2 = m2;
+                a.out_bs = Z;
+                a.out_bs2 = M * Z;
+                a.ncols = m2;
+                a.in_ld = m1 * m2;
+                a.out_ld = plane;
+                a.n_in = int(m0);
+                a.n_out = int(P0);
+                HIPCHK(launch_col(dt, int(P0), kFft, 1, a, s), "explicit x FFT");
+            }
+        }
+        // y FFT in every (b, x') plane over its (i, z) columns (pruned: the m1
+        // data rows in, P1 rows out)
+        ColArgs c = col_args(tb, dt);
+        c.in[0] = c.out[0] = W[q];
+        c.nslab = B * P0;
+        c.in_bs = c.out_bs = plane;
+        c.ncols = M * Z;
+        c.in_ld = c.out_ld = M * Z;
+        c.n_in = int(pruned ? m1 : P1);
+        c.n_out = int(P1);
+        HIPCHK(launch_col(dt, int(P1), kFft, 1, c, s), "explicit y FFT");
+    }
+    // z rows: cyclic convolution of length P2, summed over the M terms, into term 0 of W[0]
+    RowArgs ra = row_args(tb, dt);
+    ra.f = W[0]; ra.g = W[1]; ra.h = W[0];
+    ra.nrows = B * P0 * P1;
+    ra.m = Z;
+    ra.m_out = pruned ? m2 : P2;
+    ra.M = M;
+    ra.f_row = ra.g_row = ra.h_row = M * Z;
+    ra.f_i = ra.g_i = Z;
+    ra.scale = 1.0 / double(P0 * P1 * P2);
+    HIPCHK(launch_row_cyclic(dt, int(P2), ra, s), "explicit z rows");
+    // inverse y FFT of term 0 in every (b, x') plane, columns z < m2 (the
+    // ones the crop keeps); pruned: only the m1 rows the crop keeps
+    ColArgs c = col_args(tb, dt);
+    c.in[0] = c.out[0] = W[0];
+    c.nslab = B * P0;
+    c.in_bs = c.out_bs = plane;
+    c.ncols = m2;
+    c.in_ld = c.out_ld = M * Z;
+    c.n_in = int(P1);
+    c.n_out = int(pruned ? m1 : P1);
+    HIPCHK(launch_col(dt, int(P1), kFft, -1, c, s), "explicit inverse y FFT");
+    // inverse x FFT of term 0: per batch entry, slabs y < m1, columns z < m2;
+    // pruned: m0 rows straight into h, else in place and cropped after
+    for (int64_t b = 0; b < B; ++b) {
+        ColArgs a = col_args(tb, dt);
+        void* wb = atw(W[0], b * P0 * plane);
+        a.in[0] = wb;
+        a.out[0] = pruned ? static_cast<void*>(static_cast<char*>(h) + b * m0 * m1 * m2 * int64_t(cs)) : wb;
+        a.nslab = m1;
+        a.in_bs = M * Z;
+        a.out_bs = pruned ? m2 : M * Z;
+        a.ncols = m2;
+        a.in_ld = plane;
+        a.out_ld = pruned ? m1 * m2 : plane;
+        a.n_in = int(P0);
+        a.n_out = int(m0);
+        HIPCHK(launch_col(dt, int(P0), kFft, -1, a, s), "explicit inverse x FFT");
+    }
+    if (!pruned) {
+        // crop: rows (b, x < m0) of m1 x m2 blocks of term 0
+        for (int64_t b = 0; b < B; ++b)
+            HIPCHK(launch_copy2d(dt, atw(W[0], b * P0 * plane), static_cast<char*>(h) + b * m0 * m1 * m2 * int64_t(cs), m0,
+                                 1, plane, 0, M * Z, m1 * m2, 0, m2, m1, m2, m1, m2, s), "explicit crop");
+    }
+    return IMPCONV_OK;
+}
+
 impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const int64_t* m,
                      const int64_t* n, const void* f, const void* g, void* h, void* work, size_t wb,
                      uint32_t flags, void* stream)
@@ -733,6 +865,8 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
 
     if ((flags & IMPCONV_EXPLICIT_PADDED) && herm)
         return run_herm_explicit(tb, p, f, g, h, w, s, flags & IMPCONV_EXPLICIT_PRUNED);
+    if ((flags & IMPCONV_EXPLICIT_PADDED) && nd == 3)
+        return run_complex3d_explicit(tb, p, f, g, h, w, s, flags & IMPCONV_EXPLICIT_PRUNED);
     if ((flags & IMPCONV_EXPLICIT_PADDED) && (flags & IMPCONV_EXPLICIT_PRUNED)) {
         // Pruned conventional method: the padded transforms with the zero
         // padding fused into the loads and no transform of an all-zero

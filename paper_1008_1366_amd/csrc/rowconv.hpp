@@ -141,6 +141,31 @@ __device__ __forceinline__ C<T> ldz(const C<T>* U, int j, int m)
     return ok ? v : zero<T>();
 }
 
+// The same value, loaded unconditionally and masked.  With the condition in
+// view the compiler may turn ldz's selection back into a load under the
+// condition (a branch per element); here the clamped index and the
+// all-ones / zero mask pass through an empty asm statement, so the load
+// always executes, and the mask clears the bits (+0 whatever U[0] holds).
+template <typename T>
+__device__ __forceinline__ T mask_bits(T x, int mask)
+{
+    if constexpr (sizeof(T) == 4) {
+        return __uint_as_float(__float_as_uint(x) & unsigned(mask));
+    } else {
+        return __longlong_as_double(__double_as_longlong(x) & (long long)mask);
+    }
+}
+template <typename T>
+__device__ __forceinline__ C<T> ldz_masked(const C<T>* U, int j, int m)
+{
+    const bool ok = unsigned(j) < unsigned(m);  // 0 <= j < m
+    int jj = ok ? j : 0;
+    int mask = ok ? -1 : 0;
+    asm volatile("" : "+v"(jj), "+v"(mask));
+    const C<T> v = U[jj];
+    return C<T>{mask_bits(v.re, mask), mask_bits(v.im, mask)};
+}
+
 // ======================================================================
 // Complex 1D convolution, 1/2 padding rule (Sec. 2.1, fftpadBackward /
 // fftpadForward / cconv): the 2N-padded backward transform splits into two
@@ -638,6 +663,68 @@ __device__ __forceinline__ void herm_build3(const C<T>* U, int m, int t, C<T>* l
     }
 }
 
+// This thread's entries of the Hermitian half U (length m, zero beyond):
+// lo[e] = U_k, hi[e] = U_{NC+k}, k = t + e G.
+template <typename T, int NC, int E>
+__device__ __forceinline__ void herm_load(const C<T>* U, int m, int t, C<T> (&lo)[E], C<T> (&hi)[E])
+{
+    constexpr int G = NC / E;
+    const int z = opaque_zero();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        lo[e] = ldz(U + z, t + e * G, m);
+        hi[e] = ldz(U + z, NC + t + e * G, m);
+    }
+}
+
+// herm_build3 from entries already loaded by herm_load (lo, hi are consumed;
+// the prefetching form of the row kernel).
+template <typename T, int NC, int E, bool PAIRED = false>
+__device__ __forceinline__ void herm_build3_from(C<T> (&lo)[E], C<T> (&hi)[E], int t, C<T>* lds,
+                                                 const C<T>* tw3N, const C<T>* twN, C<T> (&z0)[E],
+                                                 C<T> (&z1)[E], C<T> (&z2)[E], T dc = T(1),
+                                                 C<T>* lds1 = nullptr)
+{
+    constexpr int N = 2 * NC, G = NC / E;
+    const T h3 = T(0.86602540378443864676), sq3 = T(1.73205080756887729353);
+    C<T> lom[E], him[E];
+    // U_0 scaled by dc (the adjoint's doubled mean; only its real part is read)
+    if (t == 0) lo[0] = scale(lo[0], dc);
+    // lom[e] = U_{(NC - k) mod NC}, him[e] = U_{NC + (NC - k) mod NC}
+    if constexpr (PAIRED) {
+        mirror2<T, NC, E>(lo, lom, hi, him, t, lds, lds1);
+    } else {
+        mirror<T, NC, E>(lo, lom, t, lds);
+        mirror<T, NC, E>(hi, him, t, lds);
+    }
+    const int z = opaque_zero();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = t + e * G;
+        const bool k0 = e == 0 && k == 0;
+        const C<T> a = lo[e];                         // U_k
+        const C<T> b = k0 ? zero<T>() : him[e];       // U_{N-k}
+        const C<T> c = k0 ? hi[e] : lom[e];           // U_{NC-k}
+        const C<T> d = hi[e];                         // U_{NC+k}
+        const C<T> wk = tw3N[k + z], wc = tw3N[NC - k + z], w2 = twN[k + z];
+        // r = 0
+        C<T> p = a + conj(b), q = c + conj(d);
+        if (k0) { p = C<T>{a.re, T(0)}; q = C<T>{T(2) * c.re, T(0)}; }
+        z0[e] = c2r_pre(p, q, w2);
+        // r = +1: zeta_3^{-1} = (-1/2, -sqrt3/2)
+        const C<T> z3p{T(-0.5), -h3}, z3m{T(-0.5), h3};
+        p = wk * (a + z3p * conj(b));
+        q = wc * (c + z3p * conj(d));
+        if (k0) { p = C<T>{a.re, T(0)}; q = C<T>{c.re - sq3 * c.im, T(0)}; }
+        z1[e] = c2r_pre(p, q, w2);
+        // r = -1: zeta_3^{+1}, conjugate shifts
+        p = mulc(a + z3m * conj(b), wk);
+        q = mulc(c + z3m * conj(d), wc);
+        if (k0) { p = C<T>{a.re, T(0)}; q = C<T>{c.re + sq3 * c.im, T(0)}; }
+        z2[e] = c2r_pre(p, q, w2);
+    }
+}
+
 // ======================================================================
 // Centered Hermitian 1D convolution, 2/3 padding rule (Sec. 2.3).  The input
 // half U_0..U_{N-1} (N = 2 NC >= m, zero beyond m) is implicitly padded to
@@ -681,14 +768,29 @@ k_conv1d_hermitian(RowArgs a)
     };
     C<T> P0[E], P1[E], P2[E];
     const int64_t nM = MD ? a.M : 1;
+    // complex64 rows of up to 256 points: g's entries are loaded before f's
+    // transforms, so that the loads are in flight while the wave computes
+    // (measured faster on the 512 x 512 x 257 z rows; in complex128, and in
+    // longer rows, the extra live registers cost more than the latency they
+    // hide)
+    constexpr bool PREFETCH = sizeof(T) == 4 && NC <= 128;
     for (int64_t i = 0; i < nM; ++i) {
-        C<T> x0[E], x1[E], x2[E];
-        herm_build3<T, NC, E, TRI>((const C<T>*)a.f + c.of + i * a.f_i, m, t, lds, tw3N, twN, x0, x1, x2,
-                                   (a.flags & kHermAdj) ? T(2) : T(1), lds1);
-        fft3x(x0, x1, x2, std::integral_constant<int, +1>{});
-        C<T> y0[E], y1[E], y2[E];
-        herm_build3<T, NC, E, TRI>((const C<T>*)a.g + c.og + i * a.g_i, m, t, lds, tw3N, twN, y0, y1, y2,
-                                   T(1), lds1);
+        C<T> x0[E], x1[E], x2[E], y0[E], y1[E], y2[E];
+        const C<T>* Fi = (const C<T>*)a.f + c.of + i * a.f_i;
+        const C<T>* Gi = (const C<T>*)a.g + c.og + i * a.g_i;
+        const T dc = (a.flags & kHermAdj) ? T(2) : T(1);
+        if constexpr (PREFETCH) {
+            C<T> lo[E], hi[E];
+            herm_load<T, NC, E>(Fi, m, t, lo, hi);
+            herm_build3_from<T, NC, E, TRI>(lo, hi, t, lds, tw3N, twN, x0, x1, x2, dc, lds1);
+            herm_load<T, NC, E>(Gi, m, t, lo, hi);
+            fft3x(x0, x1, x2, std::integral_constant<int, +1>{});
+            herm_build3_from<T, NC, E, TRI>(lo, hi, t, lds, tw3N, twN, y0, y1, y2, T(1), lds1);
+        } else {
+            herm_build3<T, NC, E, TRI>(Fi, m, t, lds, tw3N, twN, x0, x1, x2, dc, lds1);
+            fft3x(x0, x1, x2, std::integral_constant<int, +1>{});
+            herm_build3<T, NC, E, TRI>(Gi, m, t, lds, tw3N, twN, y0, y1, y2, T(1), lds1);
+        }
         fft3x(y0, y1, y2, std::integral_constant<int, +1>{});
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -748,7 +850,192 @@ k_conv1d_hermitian(RowArgs a)
     }
 }
 
-// ======================================================================
+// The same convolution for rows whose transform would take a whole
+// 1024-thread workgroup in the register-resident kernel (G = 1024: its build
+// of three residues of two inputs exceeds the 128 registers such a
+// workgroup leaves each thread).  Here one row takes 512 threads of NC / 512
+// values each, and the residues are formed and convolved one at a time: for residue
+// R every thread builds its entries of w_{k,R} from U_k, U_{NC+k} and the
+// mirrored U_{NC-k}, U_{N-k}, read from the input row itself, transforms
+// them, and the forward transform of the products is folded into the output
+// before the next residue starts.  Each input row is read twice per residue
+// (its own and its mirrored entries); all but the first read are served by
+// the caches.  Where two exchange-sized LDS buffers fit, the transformed f
+// waits in the second one while g is built and transformed, and the output
+// accumulates in registers; otherwise (complex128, NC = 8192) f stays in
+// registers and the output accumulates in h itself (stored for R = 0, read,
+// added to and stored again for R = +1, -1 by the same thread).
+template <typename T, int NC>
+__host__ __device__ constexpr bool herm_staged()
+{
+    // complex128 only: in complex64 the register-resident kernel, spills and
+    // all, measured faster (m = 16384: 0.172 against 0.178 ms for 256 rows,
+    // one row per compute unit, where the time is one row's latency)
+    return sizeof(T) == 8 && NC > 1 && row_G<T, 1>(NC) == 1024;
+}
+// The staged kernel's threads per row: 512, each holding NC / 512 values
+// (twice the register-resident kernel's), which leaves every thread 256
+// registers.
+constexpr int kHermStagedThreads = 1024;
+
+// The thread index through an empty asm statement: addresses computed from
+// the result are recomputed where they are used instead of being computed
+// once and kept live (or spilled) across the whole kernel.
+__device__ __forceinline__ int fresh_tid(int t)
+{
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
+// Packed c2r input of residue R at frequency k (the per-residue part of
+// herm_build3) from the half U (length m, zero beyond; U_0 scaled by dc).
+template <typename T, int NC, int R>
+__device__ __forceinline__ C<T> herm_build_one(const C<T>* U, int m, int k, T dc, const C<T>* tw3N,
+                                               const C<T>* twN)
+{
+    const T h3 = T(0.86602540378443864676), sq3 = T(1.73205080756887729353);
+    const bool k0 = k == 0;
+    // unconditional loads (a load under a condition would become a branch):
+    // at k = 0, U_{N-k} = U_N lies beyond m <= N and reads as 0, and
+    // U_{NC-k} is U_NC, as the k = 0 terms need
+    C<T> a = ldz_masked(U, k, m);                                      // U_k
+    const C<T> d = ldz_masked(U, NC + k, m);                           // U_{NC+k}
+    const C<T> b = ldz_masked(U, 2 * NC - k, m);                       // U_{N-k}
+    const C<T> c = ldz_masked(U, NC - k, m);                           // U_{NC-k}
+    a = k0 ? scale(a, dc) : a;
+    const C<T> w2 = twN[k];
+    C<T> p, q;
+    if constexpr (R == 0) {
+        p = a + conj(b);
+        q = c + conj(d);
+        if (k0) { p = C<T>{a.re, T(0)}; q = C<T>{T(2) * c.re, T(0)}; }
+    } else if constexpr (R > 0) {
+        const C<T> z3p{T(-0.5), -h3};
+        p = tw3N[k] * (a + z3p * conj(b));
+        q = tw3N[NC - k] * (c + z3p * conj(d));
+        if (k0) { p = C<T>{a.re, T(0)}; q = C<T>{c.re - sq3 * c.im, T(0)}; }
+    } else {
+        const C<T> z3m{T(-0.5), h3};
+        p = mulc(a + z3m * conj(b), tw3N[k]);
+        q = mulc(c + z3m * conj(d), tw3N[NC - k]);
+        if (k0) { p = C<T>{a.re, T(0)}; q = C<T>{c.re + sq3 * c.im, T(0)}; }
+    }
+    return c2r_pre(p, q, w2);
+}
+
+template <typename T, int NC, bool MD>
+__global__ void __launch_bounds__(kHermStagedThreads, kHermStagedThreads / 256)
+k_conv1d_hermitian_staged(RowArgs a)
+{
+    constexpr int N = 2 * NC, G = kHermStagedThreads, E = NC / G, LDSN = lpad_size(NC);
+    static_assert(E >= 2 && NC % G == 0, "staged Hermitian rows: NC / 512 values per thread");
+    constexpr bool XLDS = 2 * LDSN * int(sizeof(C<T>)) <= 160 * 1024;  // f's transform waits in LDS
+    constexpr int EO = XLDS ? E : 1;                                   // output accumulators in registers
+    __shared__ C<T> sh[(XLDS ? 2 : 1) * LDSN];
+    static_assert(sizeof(sh) <= 160 * 1024, "LDS footprint exceeds 160 KB");
+    C<T>* A = sh;           // exchange buffer
+    C<T>* X = sh + LDSN;    // transformed f (XLDS)
+    const int t = threadIdx.x;
+    const RowCtx c = row_ctx(a, (int64_t)blockIdx.x);
+    const C<T>* twb = (const C<T>*)a.tw;
+    const C<T>* twNC = twb + tw_off(NC);
+    const C<T>* twN = twb + tw_off(N);
+    const C<T>* tw3N = (const C<T>*)a.tw3 + tw_off(N);
+    const int m = c.m;
+    const int64_t nM = MD ? a.M : 1;
+    const bool adj = a.flags & kHermAdj;
+    const T dc = adj ? T(2) : T(1);
+    const T s = T(1) / T(3 * N);
+    C<T>* H = (C<T>*)a.h + c.oh;
+    C<T> olo[EO], ohi[EO], ocen = zero<T>();
+    const T h3 = T(0.86602540378443864676);
+    static_for<3>([&](auto ri) {
+        constexpr int R = decltype(ri)::value == 0 ? 0 : (decltype(ri)::value == 1 ? 1 : -1);
+        C<T> P[E];
+        for (int64_t i = 0; i < nM; ++i) {
+            C<T> x[E];
+            {
+                const int z = opaque_zero();
+                const int tt = fresh_tid(t);
+                const C<T>* U = (const C<T>*)a.f + c.of + i * a.f_i + z;
+#pragma unroll
+                for (int e = 0; e < E; ++e) x[e] = herm_build_one<T, NC, R>(U, m, tt + e * G, dc, tw3N + z, twN + z);
+            }
+            fft<T, NC, E, +1>(x, t, A, 1, twNC);
+            if constexpr (XLDS) {
+                // each thread keeps its own entries: no barrier
+                const int tt = fresh_tid(t);
+#pragma unroll
+                for (int e = 0; e < E; ++e) X[lpad(tt + e * G)] = x[e];
+            }
+            C<T> y[E];
+            {
+                const int z = opaque_zero();
+                const int tt = fresh_tid(t);
+                const C<T>* U = (const C<T>*)a.g + c.og + i * a.g_i + z;
+#pragma unroll
+                for (int e = 0; e < E; ++e) y[e] = herm_build_one<T, NC, R>(U, m, tt + e * G, T(1), tw3N + z, twN + z);
+            }
+            fft<T, NC, E, +1>(y, t, A, 1, twNC);
+            const int tt = fresh_tid(t);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const C<T> xv = XLDS ? X[lpad(tt + e * G)] : x[e];
+                const C<T> p{xv.re * y[e].re, xv.im * y[e].im};
+                P[e] = (MD && i > 0) ? P[e] + p : p;
+            }
+        }
+        fft<T, NC, E, -1>(P, t, A, 1, twNC);
+        // P_R(NC - k) through A, then this residue's share of H_k, H_{N-k}, H_NC
+        const int tt = fresh_tid(t);
+#pragma unroll
+        for (int e = 0; e < E; ++e) A[lpad(tt + e * G)] = P[e];
+        __syncthreads();
+        const C<T> z3 = R == 0 ? C<T>{T(1), T(0)} : (R > 0 ? C<T>{T(-0.5), -h3} : C<T>{T(-0.5), h3});
+        const int zo = opaque_zero();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = tt + e * G;
+            const C<T> Pm = A[lpad((NC - k) & (NC - 1))];
+            const C<T> V = r2c_post(P[e], Pm, twN[k + zo]);
+            C<T> lo = V, hi = conj(V);
+            if constexpr (R != 0) {
+                const C<T> w = tw3N[k + zo];
+                lo = R > 0 ? mulc(V, w) : V * w;
+                hi = z3 * (R > 0 ? w * conj(V) : mulc(conj(V), w));
+            }
+            if constexpr (XLDS) {
+                olo[e] = R == 0 ? lo : olo[e] + lo;
+                ohi[e] = R == 0 ? hi : ohi[e] + hi;
+            } else {
+                // H_0 of the adjoint form is real and halved
+                const C<T> vlo = (e == 0 && k == 0 && adj) ? C<T>{T(0.5) * s * lo.re, T(0)} : scale(lo, s);
+                if (k < m) H[k] = R == 0 ? vlo : H[k] + vlo;
+                if (k > 0 && N - k < m) H[N - k] = R == 0 ? scale(hi, s) : H[N - k] + scale(hi, s);
+            }
+            if (e == 0 && k == 0) {
+                const C<T> z6 = R == 0 ? C<T>{T(1), T(0)} : (R > 0 ? C<T>{T(0.5), -h3} : C<T>{T(0.5), h3});
+                const C<T> cen = z6 * C<T>{P[e].re - P[e].im, T(0)};
+                ocen = R == 0 ? cen : ocen + cen;
+            }
+        }
+        __syncthreads();  // A is the exchange buffer of the next residue's transforms
+    });
+    if constexpr (XLDS) {
+        const int tt = fresh_tid(t);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = tt + e * G;
+            if (k < m) H[k] = (e == 0 && k == 0 && adj) ? C<T>{T(0.5) * s * olo[e].re, T(0)} : scale(olo[e], s);
+            if (k > 0 && N - k < m) H[N - k] = scale(ohi[e], s);
+        }
+    }
+    if (t == 0 && NC < m) H[NC] = scale(ocen, s);
+    if (c.act) {
+        for (int64_t j = m + t; j < a.h_pad; j += G) H[j] = zero<T>();
+    }
+}
+
 // Centered Hermitian ternary convolution (Sec. 4.2, tconv).  With the input
 // half U_0..U_{N-1} (N >= m) padded to Fourier size 4N: for r in {0, 1} the
 // sequence {zeta_{4N}^{rk} U_k : k = 0..N}, U_N = 0, is transformed

@@ -112,3 +112,15 @@ def test_ternary_2d(L, mx, my):
     ws = words(L, TERNARY, (mx, my), n)
     assert ws <= formula("ternary_2d_implicit", mx=mx, my=my)
     assert ws + 4 * prod(n) <= formula("ternary_2d_explicit", mx=mx, my=my)
+
+
+@pytest.mark.parametrize("m", [32, 256])
+def test_complex_3d_explicit_comparator(L, m):
+    """The conventional comparator's padded f and g are the paper's explicit
+    3D complex storage, 16 mx my mz words (2m per axis, two arrays); its
+    pruned form stores only the m data columns of the last axis."""
+    EXPLICIT_PADDED, EXPLICIT_PRUNED = 1, 64
+    ws = words(L, COMPLEX, (m, m, m), (m, m, m), flags=EXPLICIT_PADDED)
+    assert ws == formula("complex_3d_explicit", mx=m, my=m, mz=m)
+    wp = words(L, COMPLEX, (m, m, m), (m, m, m), flags=EXPLICIT_PADDED | EXPLICIT_PRUNED)
+    assert wp == ws // 2
