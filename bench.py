@@ -478,9 +478,17 @@ def wl_c4(args):
     G = torch.from_numpy(g).to("cuda", cdt)
     cs = 8 if cdt == torch.complex64 else 16
     S = int(np.prod(n)) * cs
-    run = lambda: ic.conv3d(F, G, kind="hermitian", m=m)
+    # the per-launch timing pass runs every launch in order on one stream
+    # (ONE_STREAM: same kernels), so that a launch's duration is its own and
+    # not shared with the rows of one chunk that overlap the next chunk's y pass
+    mode = {"flags": 0}
+    run = lambda: ic.conv3d(F, G, kind="hermitian", m=m, flags=mode["flags"])
     expl = lambda: ic.conv3d(F, G, kind="hermitian", m=m, method="explicit")
     pruned = lambda: ic.conv3d(F, G, kind="hermitian", m=m, method="pruned")
+
+    def kernel_timing_mode(on):
+        mode["flags"] = ic.ONE_STREAM if on else 0
+        return "launches in order on one stream (ONE_STREAM) for the per-launch timing pass" if on else None
     # Sec. 3.4 five-pass schedule, algorithmic bytes per step (S = one stored
     # array): x back 6S -> 9S and y back 9S -> 13.5S (colpass_cen_bwd), z
     # convolutions 13.5S -> 2.25S (3 m_x x 3 m_y rows, M = 3 per row), y
@@ -568,7 +576,7 @@ def wl_c4(args):
            "m": list(m), "n": list(n), "M": 3, "dtype": args.dtype}
     return dict(run=run, explicit=expl, pruned=pruned, convs=1, step_bytes=step_bytes, kbytes_step=kbytes_step,
                 kflops_step=kflops_step, cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy(),
-                bound="hbm", leg=c64_leg)
+                bound="hbm", leg=c64_leg, kernel_timing_mode=kernel_timing_mode)
 
 
 def wl_c5(args):
@@ -932,6 +940,9 @@ def main():
     ap.add_argument("--cpu-points", type=int, default=65536, help="c3: sampled output points over the batch")
     ap.add_argument("--cpu-rows", type=int, default=0, help="c1/c2: convolutions (0: workload default)")
     ap.add_argument("--cpu-macs", type=float, default=4e10, help="c5: multiply-add budget")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="c4/c5: every launch in order on one stream in the timed steps too (for profiling, so "
+                         "that a traced kernel's duration matches the per-launch timing pass)")
     ap.add_argument("--profile-copy", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -947,6 +958,10 @@ def main():
     torch.cuda.set_device(0)
     note(f"workload {args.workload} {args.dtype}: preparing inputs")
     W = WORKLOADS[args.workload](args)
+    if args.one_stream and "kernel_timing_mode" in W:
+        W["kernel_timing_mode"](True)
+        W["kernel_timing_mode"] = lambda on: ("every launch in order on one stream (ONE_STREAM) in all steps"
+                                              if on else None)
     note("timing the implicit path")
 
     # implicit path, with per-launch event timing inside the library

@@ -79,7 +79,7 @@ typedef enum impconv_kind {
 #define IMPCONV_HERMITIAN_ADJOINT (1u << 5) /* Hermitian 1D/nD: vector-Jacobian product edits (see below) */
 #define IMPCONV_EXPLICIT_PRUNED (1u << 6) /* with EXPLICIT_PADDED: skip all-zero transforms, fuse padding */
 #define IMPCONV_COMPENSATED (1u << 7)     /* complex64 complex convolutions: compensated twiddle products */
-#define IMPCONV_ONE_STREAM (1u << 8)      /* ragged batches: size classes one after another on `stream` */
+#define IMPCONV_ONE_STREAM (1u << 8)      /* ragged batches, 3D: every launch in order on `stream` alone */
 
 /* Version as 10000*major + 100*minor + patch. */
 int impconv_version(void);
@@ -257,6 +257,14 @@ size_t impconv_timing_report(char* buf, size_t cap);
  * m1 x m2 data columns only, y transforms of the m2 data columns, inverse
  * transforms of the cropped rows only, the last one writing h (work
  * 2 * batch * M * 4 N0 N1 * m2 complex values).
+ * 3D: the y backward pass, the rows and the y forward pass run over chunks
+ * of the (batch, x residue) planes; the rows and y forward pass of one chunk
+ * run on the device's first auxiliary stream (the one of the ragged
+ * batches, created once per device) while the caller's stream runs the y
+ * backward pass of the next chunk, forked and joined by events (capturable;
+ * the same threading caveat as for ragged batches applies).  With
+ * IMPCONV_ONE_STREAM every launch runs in order on `stream`, with the same
+ * kernels and bitwise the same result.
  * Outer axes support m[d] <= 4096 in this build; the innermost axis
  * m <= 8192 (complex) or m <= 16384 (Hermitian).
  * ---------------------------------------------------------------------- */

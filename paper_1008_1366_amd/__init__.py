@@ -36,7 +36,7 @@ LIB_PATH = os.path.join(HERE, "libimpconv.so")
 
 EXPLICIT_PADDED, REV_F, CONJ_G, REV_OUT, NO_SYMMETRIZE, HERMITIAN_ADJOINT, EXPLICIT_PRUNED = 1, 2, 4, 8, 16, 32, 64
 COMPENSATED = 128  # complex64: compensated twiddle products (complex convolutions)
-ONE_STREAM = 256  # ragged batches: size classes one after another on the caller's stream
+ONE_STREAM = 256  # ragged batches and 3D: every launch in order on the caller's stream
 COMPLEX, HERMITIAN, TERNARY = 0, 1, 2
 C64, C128 = 0, 1
 

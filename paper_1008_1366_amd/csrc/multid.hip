@@ -192,14 +192,14 @@ struct PlanND {
 };
 
 // 3D: the y backward pass, the innermost rows and the y forward pass run
-// over chunks of the (b, x') planes, one chunk after another, with one set of
-// y-residue arrays sized for a chunk.  kYChunks chunks (fewer when there are
-// fewer planes) keep that region at 1 / kYChunks of the full y-residue
-// volume, which brings the 3D work memory under the explicitly padded
+// over chunks of the (b, x') planes, with two sets of y-residue arrays sized
+// for a chunk, used by the chunks in turn.  kYChunks chunks (fewer when there
+// are fewer planes) keep that region at 2 / kYChunks of the full y-residue
+// volume, which keeps the 3D work memory under the explicitly padded
 // method's storage (Sec. 3.4 storage counts) while every launch still spans
 // many planes.
 #ifndef IMPCONV_3D_YCHUNKS
-#define IMPCONV_3D_YCHUNKS 4
+#define IMPCONV_3D_YCHUNKS 8
 #endif
 constexpr int64_t kYChunks = IMPCONV_3D_YCHUNKS;
 int64_t y_chunk_planes(int64_t planes)
@@ -219,7 +219,7 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
     if (batch < 0 || M < 1) return fail(IMPCONV_E_SIZE, "batch must be >= 0 and M >= 1");
     const uint32_t adj = IMPCONV_REV_F | IMPCONV_CONJ_G | IMPCONV_REV_OUT;
     const uint32_t known = IMPCONV_NO_SYMMETRIZE | IMPCONV_EXPLICIT_PADDED | IMPCONV_EXPLICIT_PRUNED | adj |
-                           IMPCONV_HERMITIAN_ADJOINT | IMPCONV_COMPENSATED;
+                           IMPCONV_HERMITIAN_ADJOINT | IMPCONV_COMPENSATED | IMPCONV_ONE_STREAM;
     if (flags & ~known) return fail(IMPCONV_E_ARG, "unsupported flag for an nD convolution");
     if ((flags & IMPCONV_COMPENSATED) && (kind != IMPCONV_COMPLEX || (flags & IMPCONV_EXPLICIT_PADDED)))
         return fail(IMPCONV_E_ARG, "COMPENSATED applies to implicit complex nD convolutions");
@@ -305,13 +305,14 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
         p->work = size_t(2) * R * batch * M * p->Np[0] * n[1] * cs;
     } else {
         // x-residue arrays of f and g (the y-forward output of each plane is
-        // written back into its own x-residue plane), plus the y-residue
-        // arrays of one chunk of planes, reused by every chunk and x residue
+        // written back into its own x-residue plane), plus two sets of
+        // y-residue arrays of one chunk of planes, used by the chunks in turn
+        // (the rows of one chunk run beside the y pass of the next)
         const size_t X = size_t(2) * R * batch * M * p->Np[0] * n[1] * n[2];
         const int64_t planes = batch * p->Np[0];
         p->ychunk = y_chunk_planes(planes);
         const size_t Y = size_t(2) * R * p->ychunk * M * p->Np[1] * n[2];
-        p->work = (X + Y) * cs;
+        p->work = (X + 2 * Y) * cs;
     }
     return IMPCONV_OK;
 }
@@ -1024,11 +1025,14 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
         Xg[r] = w + (R + (r < R ? r : R - 1)) * xa;
     }
     char* yb = w + 2 * R * xa;
-    void* Yf[3]; void* Yg[3];
+    void* Yf[3]; void* Yg[3];    // y-residue set 0
+    void* Yf1[3]; void* Yg1[3];  // y-residue set 1
     for (int ry = 0; ry < 3; ++ry) {
         const int rr = ry < R ? ry : R - 1;
         Yf[ry] = yb + size_t(rr) * ya;
         Yg[ry] = yb + size_t(R + rr) * ya;
+        Yf1[ry] = yb + size_t(2 * R + rr) * ya;
+        Yg1[ry] = yb + size_t(3 * R + rr) * ya;
     }
     // x pass over columns (y, z): valid columns skip the zero slots of y and z
     const int ylo = herm ? int(n1 - (2 * m1 - 1)) : 0;
@@ -1038,7 +1042,7 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
     if ((st = outer_bwd(tb, p, g, Xg, batch, M * n0 * n1 * n2, n0, m0, N0, n1 * n2, sym ? 2 : 0, n2,
                         int(n1 - m1), int(n1), mask_nz, ylo, int(n1), int(m2), s, fs_g))) return st;
     // y backward pass of np planes: slabs (plane, i) of [n1][n2] -> [plane][y'][i][n2]
-    auto ypass = [&](const void* src, void* const* dst, int64_t np, uint32_t fsf) -> impconv_status {
+    auto ypass = [&](const void* src, void* const* dst, int64_t np, uint32_t fsf, hipStream_t q) -> impconv_status {
         ColArgs c = col_args(tb, dt);
         c.fsflags = fsf;
         c.in[0] = src;
@@ -1056,36 +1060,87 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
         c.m = int(m1);
         c.off_in = int(n1 - m1);
         if (herm) { c.mask_nz = n2; c.mask_ylo = 0; c.mask_yhi = 1; c.mask_zhi = int(m2); }
-        HIPCHK(launch_col(dt, int(N1), herm ? kCenBwd : kPadBwd, 1, c, s), "y backward pass");
+        HIPCHK(launch_col(dt, int(N1), herm ? kCenBwd : kPadBwd, 1, c, q), "y backward pass");
         return IMPCONV_OK;
     };
-    for (int rx = 0; rx < R; ++rx) {
-        for (int64_t p0 = 0; p0 < nplanes; p0 += P) {
+    // rows and y forward pass of np planes from y-residue set Y into the
+    // planes' term 0 in Xf[rx] at xf
+    auto rows_fwd = [&](void* const* YF, void* const* YG, char* xf, int64_t np, hipStream_t q) -> impconv_status {
+        impconv_status st2;
+        for (int ry = 0; ry < R; ++ry)
+            if ((st2 = inner_rows(tb, p, YF[ry], YG[ry], np * N1, q, rowfl))) return st2;
+        // y forward: [plane][y'][i = 0][n2] (R residues) -> term 0 of the plane in Xf[rx]
+        ColArgs c = col_args(tb, dt);
+        for (int r = 0; r < 3; ++r) c.in[r] = YF[r];
+        c.out[0] = xf;
+        c.nslab = np;
+        c.in_bs = N1 * M * n2;
+        c.out_bs = plane;
+        c.ncols = n2;
+        c.in_ld = M * n2;
+        c.out_ld = n2;
+        c.n_out = int(n1);
+        c.m = int(m1);
+        c.off_out = int(n1 - m1);
+        c.scale = 1.0 / double((herm ? 3 : 2) * N1);
+        c.fsflags = fs_o;
+        HIPCHK(launch_col(dt, int(N1), herm ? kCenFwd : kPadFwd, 1, c, q), "y forward pass");
+        return IMPCONV_OK;
+    };
+    // Chunk j runs its y backward passes on the caller's stream s into
+    // y-residue set j mod 2, and its rows and y forward pass on the device's
+    // first auxiliary stream, so that the rows of chunk j (latency-bound)
+    // overlap the y backward pass of chunk j + 1 (bandwidth-bound).  Events:
+    // pipe[b] = set b filled (s -> aux), pipe[2 + b] = set b consumed (aux -> s).
+    // The two streams touch disjoint memory: chunk j's y forward pass writes
+    // term 0 of chunk j's planes, the y pass of chunk j + 1 reads chunk j + 1's.
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorInvalidDevice, "hipGetDevice");
+    // IMPCONV_ONE_STREAM: every launch in order on s (no fork, no events)
+    const bool one = (p.flags & IMPCONV_ONE_STREAM) != 0;
+    DevLanes* L = one ? nullptr : device_lanes(dev);
+    if (!one && !L) return IMPCONV_E_HIP;
+    std::unique_lock<std::mutex> lanes_lock;
+    if (!one) lanes_lock = std::unique_lock<std::mutex>(L->mu);
+    hipStream_t q = one ? s : L->aux[0];
+    if (!one) {
+        hipError_t e = hipEventRecord(L->fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(q, L->fork, 0);
+        if (e != hipSuccess) return hip_fail(e, "3D fork");
+    }
+    int64_t j = 0;
+    for (int rx = 0; rx < R && !st; ++rx) {
+        for (int64_t p0 = 0; p0 < nplanes && !st; p0 += P, ++j) {
             const int64_t np = std::min(P, nplanes - p0);
+            const int bset = int(j & 1);
             char* xf = static_cast<char*>(Xf[rx]) + size_t(p0) * plane * cs;
             const char* xg = static_cast<const char*>(Xg[rx]) + size_t(p0) * plane * cs;
-            if ((st = ypass(xf, Yf, np, fs_f))) return st;
-            if ((st = ypass(xg, Yg, np, cb))) return st;
-            for (int ry = 0; ry < R; ++ry)
-                if ((st = inner_rows(tb, p, Yf[ry], Yg[ry], np * N1, s, rowfl))) return st;
-            // y forward: [plane][y'][i = 0][n2] (R residues) -> term 0 of the plane in Xf[rx]
-            ColArgs c = col_args(tb, dt);
-            for (int r = 0; r < 3; ++r) c.in[r] = Yf[r];
-            c.out[0] = xf;
-            c.nslab = np;
-            c.in_bs = N1 * M * n2;
-            c.out_bs = plane;
-            c.ncols = n2;
-            c.in_ld = M * n2;
-            c.out_ld = n2;
-            c.n_out = int(n1);
-            c.m = int(m1);
-            c.off_out = int(n1 - m1);
-            c.scale = 1.0 / double((herm ? 3 : 2) * N1);
-            c.fsflags = fs_o;
-            HIPCHK(launch_col(dt, int(N1), herm ? kCenFwd : kPadFwd, 1, c, s), "y forward pass");
+            void* const* YF = bset ? Yf1 : Yf;
+            void* const* YG = bset ? Yg1 : Yg;
+            hipError_t e = hipSuccess;
+            if (!one && j >= 2) e = hipStreamWaitEvent(s, L->pipe[2 + bset], 0);
+            if (e != hipSuccess) { st = hip_fail(e, "3D pipeline wait"); break; }
+            if ((st = ypass(xf, YF, np, fs_f, s))) break;
+            if ((st = ypass(xg, YG, np, cb, s))) break;
+            if (!one) {
+                e = hipEventRecord(L->pipe[bset], s);
+                if (e == hipSuccess) e = hipStreamWaitEvent(q, L->pipe[bset], 0);
+                if (e != hipSuccess) { st = hip_fail(e, "3D pipeline event"); break; }
+            }
+            if ((st = rows_fwd(YF, YG, xf, np, q))) break;
+            if (!one && (e = hipEventRecord(L->pipe[2 + bset], q)) != hipSuccess) {
+                st = hip_fail(e, "3D pipeline event");
+                break;
+            }
         }
     }
+    // join, also after a failure part way: s waits for everything queued on q
+    if (!one) {
+        hipError_t e = hipEventRecord(L->join[0], q);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, L->join[0], 0);
+        if (e != hipSuccess && !st) st = hip_fail(e, "3D join");
+    }
+    if (st) return st;
     // x forward: term 0 of Xf[rx], [b][x'][(i = 0) y z] -> h [b][n0][n1 n2]
     PlanND px = p;
     px.M = 1;

@@ -74,57 +74,14 @@ struct impconv_ragged_plan {
 };
 
 namespace {
-constexpr int kRaggedLanes = 4;  // the caller's stream and three auxiliary streams
+constexpr int kRaggedLanes = kAuxStreams + 1;  // the caller's stream and the auxiliary streams
 
 // The size classes of a plan run concurrently: the caller's stream forks to
-// three auxiliary streams through an event and joins them back at the end,
-// so the short fused classes overlap the long multi-pass ones (one launch of
-// a short class fills only part of the chip).  The auxiliary streams
-// (default priority) and the fork / join events belong to the device, not to
-// a plan: they are created once, on the first plan of the device, and kept
-// until the process ends, so that creating and destroying plans creates and
-// destroys no streams.  `mu` serializes the executions that enqueue through
-// them (the events are re-recorded by every execution).
-struct Lanes {
-    hipStream_t aux[kRaggedLanes - 1];
-    hipEvent_t fork;
-    hipEvent_t join[kRaggedLanes - 1];
-    std::mutex mu;
-};
-std::mutex g_lanes_mu;
-Lanes* g_lanes[64];
-
-Lanes* device_lanes(int dev)
-{
-    if (dev < 0 || dev >= 64) {
-        hip_fail(hipErrorInvalidDevice, "ragged streams");
-        return nullptr;
-    }
-    std::lock_guard<std::mutex> lk(g_lanes_mu);
-    if (g_lanes[dev]) return g_lanes[dev];
-    auto* L = new Lanes();
-    int streams = 0, joins = 0;
-    hipError_t e = hipEventCreateWithFlags(&L->fork, hipEventDisableTiming);
-    if (e != hipSuccess) L->fork = nullptr;
-    for (int l = 0; l < kRaggedLanes - 1 && e == hipSuccess; ++l) {
-        e = hipStreamCreateWithFlags(&L->aux[l], hipStreamNonBlocking);
-        if (e != hipSuccess) break;
-        ++streams;
-        e = hipEventCreateWithFlags(&L->join[l], hipEventDisableTiming);
-        if (e == hipSuccess) ++joins;
-    }
-    if (e != hipSuccess) {
-        // (nothing has used them yet: safe to release)
-        for (int l = 0; l < streams; ++l) (void)hipStreamDestroy(L->aux[l]);
-        for (int l = 0; l < joins; ++l) (void)hipEventDestroy(L->join[l]);
-        if (L->fork) (void)hipEventDestroy(L->fork);
-        delete L;
-        hip_fail(e, "ragged streams");
-        return nullptr;
-    }
-    g_lanes[dev] = L;
-    return L;
-}
+// the device's three auxiliary streams (runtime.hpp DevLanes) through an
+// event and joins them back at the end, so the short fused classes overlap
+// the long multi-pass ones (one launch of a short class fills only part of
+// the chip).
+using Lanes = DevLanes;
 
 // Destroys a plan that was never executed (creation failed part way).
 void free_unused(impconv_ragged_plan* p)
@@ -226,6 +183,48 @@ RowArgs ragged_row_args(const DevTables& tb, int dt, const void* f, const void* 
     return a;
 }
 }  // namespace
+
+namespace impconv {
+namespace {
+std::mutex g_lanes_mu;
+DevLanes* g_lanes[64];
+}  // namespace
+
+DevLanes* device_lanes(int dev)
+{
+    if (dev < 0 || dev >= 64) {
+        hip_fail(hipErrorInvalidDevice, "auxiliary streams");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_lanes_mu);
+    if (g_lanes[dev]) return g_lanes[dev];
+    auto* L = new DevLanes();
+    std::vector<hipEvent_t> evs;
+    int streams = 0;
+    hipError_t e = hipSuccess;
+    for (int l = 0; l < kAuxStreams && e == hipSuccess; ++l) {
+        e = hipStreamCreateWithFlags(&L->aux[l], hipStreamNonBlocking);
+        if (e == hipSuccess) ++streams;
+    }
+    hipEvent_t* slots[] = {&L->fork, &L->join[0], &L->join[1], &L->join[2],
+                           &L->pipe[0], &L->pipe[1], &L->pipe[2], &L->pipe[3]};
+    for (hipEvent_t* ev : slots) {
+        if (e != hipSuccess) break;
+        e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+        if (e == hipSuccess) evs.push_back(*ev);
+    }
+    if (e != hipSuccess) {
+        // (nothing has used them yet: safe to release)
+        for (int l = 0; l < streams; ++l) (void)hipStreamDestroy(L->aux[l]);
+        for (hipEvent_t ev : evs) (void)hipEventDestroy(ev);
+        delete L;
+        hip_fail(e, "auxiliary streams");
+        return nullptr;
+    }
+    g_lanes[dev] = L;
+    return L;
+}
+}  // namespace impconv
 
 namespace {
 #define HIPCHK(expr, what)                                   \

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <mutex>
 #include <string>
 
 #include "../../include/impconv.h"
@@ -38,6 +39,24 @@ const DevTables* tables();
 // (j2 < N2, c < N1, F = N1 N2), created on first use per device, dtype and
 // split (synchronous; nullptr on HIP failure).
 const void* fs_twiddles(int dt, int64_t N2, int64_t N1);
+
+// Auxiliary streams of a device and the events that fork work onto them and
+// join it back into the caller's stream: created once, with the first call
+// that needs them on the device, and kept until the process ends (no call
+// creates or destroys streams).  `mu` is held while a call enqueues through
+// them (the events are re-recorded by every call).  Used by ragged batches
+// (size classes on separate streams) and by the 3D convolutions (rows of
+// one chunk of planes beside the outer pass of the next).
+constexpr int kAuxStreams = 3;
+struct DevLanes {
+    hipStream_t aux[kAuxStreams];
+    hipEvent_t fork;
+    hipEvent_t join[kAuxStreams];
+    hipEvent_t pipe[4];  // 3D pipeline: y stage of a buffer done (0, 1), buffer free again (2, 3)
+    std::mutex mu;
+};
+// The current device's lanes (nullptr with the error set on HIP failure).
+DevLanes* device_lanes(int dev);
 
 // Resolves, once per device, the device address of the fixed work memory of
 // impconv_conv2d_noalloc on the current device (impconv_init calls it).

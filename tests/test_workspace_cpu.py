@@ -86,9 +86,10 @@ def test_hermitian_3d(L, m, zs, dt):
     data = 3 * prod(n)
     assert ws + data < formula("hermitian_3d_explicit", mx=m, my=m, mz=m)
     # the x residues of f and g take 12 m^3 (the paper's f, g, U, V); the
-    # y-stage region is a fraction of it
+    # y-stage region (two sets of y residues for a quarter of the planes,
+    # 2 x 1/4 x (power-of-two y size) / (y storage)) is a fraction of it
     x_res = 6 * m * prod(n[1:])
-    assert x_res <= ws <= 1.25 * x_res
+    assert x_res <= ws <= 1.3 * x_res
 
 
 def test_hermitian_3d_mdot_scales_with_terms(L):
