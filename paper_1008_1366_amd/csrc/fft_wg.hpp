@@ -362,6 +362,62 @@ __device__ __forceinline__ void fft(C<T> (&v)[E], int t, C<T>* lds, int LS, TW t
     if constexpr (N > 1) fft_stage<T, N, E, DIR, 1, TW>(v, t, lds, LS, tw);
 }
 
+// The same transform over two exchange buffers used in turn (rows, LS = 1,
+// G > 64): stage s writes the buffer that stage s - 1 did not read from, so
+// one barrier per stage suffices -- every wave has finished reading that
+// buffer (at stage s - 2) before it arrived at the barrier of stage s - 1.
+// One barrier at the end lets the caller reuse both buffers.
+template <typename T, int N, int E, int DIR, int NS, typename TW>
+__device__ __forceinline__ void fft_pp_stage(C<T> (&v)[E], int t, C<T>* lds, C<T>* ldsn, TW tw)
+{
+    constexpr int R = (N / NS < E) ? (N / NS) : E;
+    constexpr bool LAST = (NS * R == N);
+    constexpr int G = N / E;
+    constexpr int Q = E / R;
+    static_assert(E % R == 0 && R >= 2, "radix must divide the per-thread element count");
+    int zoff = 0;
+    asm volatile("" : "+s"(zoff));
+    asm volatile("" : "+v"(t));
+    const TW tws = tw + zoff;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int b = t + q * G;
+        const int k = b & (NS - 1);
+        C<T> u[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) u[r] = v[q + r * Q];
+        if constexpr (NS > 1) {
+            const int ks = k * (N / (NS * R));
+#pragma unroll
+            for (int r = 1; r < R; ++r) u[r] = mulw<DIR>(u[r], tws[r * ks]);
+        }
+        DFT<R, DIR, T>::run(u);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q + r * Q] = u[r];
+        } else {
+            C<T>* wp = lds + lpad((b - k) * R + k);
+#pragma unroll
+            for (int r = 0; r < R; ++r) wp[r * NS + ((r * NS) >> 4)] = u[r];
+        }
+    }
+    if constexpr (!LAST) {
+        __syncthreads();
+        const C<T>* rp = lds + lpad(t);
+#pragma unroll
+        for (int i = 0; i < E; ++i) v[i] = rp[i * G + ((i * G) >> 4)];
+        fft_pp_stage<T, N, E, DIR, NS * R, TW>(v, t, ldsn, lds, tw);
+    }
+}
+
+template <typename T, int N, int E, int DIR, typename TW>
+__device__ __forceinline__ void fft_pp(C<T> (&v)[E], int t, C<T>* lds0, C<T>* lds1, TW tw)
+{
+    static_assert(N % E == 0 && N / E > 64, "ping-pong exchanges serve workgroup-wide transforms");
+    fft_pp_stage<T, N, E, DIR, 1, TW>(v, t, lds0, lds1, tw);
+    __syncthreads();
+}
+
 // Compile-time loop: f(std::integral_constant<int, i>{}) for i = 0..n-1.
 template <typename F, int... I>
 __device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>)

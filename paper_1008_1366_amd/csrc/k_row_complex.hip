@@ -10,6 +10,15 @@ static hipError_t go_complex(const RowArgs& a, hipStream_t s)
     constexpr int threads = row_block<T>(N);
     const int64_t blocks = (a.nrows + row_GPB<T>(N) - 1) / row_GPB<T>(N);
     if (blocks == 0) return hipSuccess;
+    if constexpr (complex_serial<T, N>()) {
+        if (a.M == 1) {
+            // one row per 1024-thread workgroup, residues one after the other
+            timing_begin(s);
+            hipLaunchKernelGGL((k_conv1d_complex_serial<T, N>), dim3(a.nrows), dim3(1024), 0, s, a);
+            timing_end("k_conv1d_complex", s);
+            return hipGetLastError();
+        }
+    }
     if (a.M == 1) {
         constexpr bool accg = !regs_fit<T>(3, fft_E<T>(N), threads);
         timing_begin(s);

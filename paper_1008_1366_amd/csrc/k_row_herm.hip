@@ -11,8 +11,21 @@ static hipError_t go_herm(const RowArgs& a, hipStream_t s)
     const int64_t blocks = (a.nrows + row_GPB<T, 1>(NC) - 1) / row_GPB<T, 1>(NC);
     if (blocks == 0) return hipSuccess;
     timing_begin(s);
+    // in place (the staged kernel accumulates its output in h): the
+    // register-resident kernel, which reads every input before it stores
+    const bool inplace = a.h == a.f || a.h == a.g;
     if constexpr (herm_staged<T, NC>()) {
-        // one row per 512-thread workgroup, residues one at a time
+        if (inplace) {
+            if (a.M == 1)
+                hipLaunchKernelGGL((k_conv1d_hermitian<T, NC, false>), dim3(blocks), dim3(threads), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_conv1d_hermitian<T, NC, true>), dim3(blocks), dim3(threads), 0, s, a);
+            timing_end("k_conv1d_hermitian", s);
+            return hipGetLastError();
+        }
+    }
+    if constexpr (herm_staged<T, NC>()) {
+        // one row per 1024-thread workgroup, residues one at a time
         const dim3 st(kHermStagedThreads);
         if (a.M == 1)
             hipLaunchKernelGGL((k_conv1d_hermitian_staged<T, NC, false>), dim3(a.nrows), st, 0, s, a);

@@ -316,6 +316,113 @@ k_conv1d_complex(RowArgs a)
     }
 }
 
+// One M = 1 row per 1024-thread workgroup for the lengths whose transform
+// takes G = 1024 threads (complex128 N = 8192), where the paired form above
+// (both residues of f and g live at once) exceeds the 128 registers per
+// thread such a workgroup leaves and spills.  The residues run one
+// after the other through one exchange buffer: residue 0 is transformed,
+// multiplied and transformed back; then residue 1's entries of f and g are
+// read (from the caches) before residue 0's share of h_k is stored, so that
+// h may be f or g; residue 1 follows and its share is added to the stored
+// one (each thread reads back only what it stored itself).
+template <typename T, int N>
+__host__ __device__ constexpr bool complex_serial()
+{
+    return N / fft_E<T>(N) == 1024;
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(1024, 1)
+k_conv1d_complex_serial(RowArgs a)
+{
+    constexpr int E = fft_E<T>(N), G = N / E, LDSN = lpad_size(N);
+    static_assert(G == 1024, "serial complex rows take one 1024-thread workgroup per row");
+    __shared__ C<T> lds[LDSN];
+    static_assert(sizeof(lds) <= 160 * 1024, "LDS footprint exceeds 160 KB");
+    const int t = threadIdx.x;
+    const RowCtx c = row_ctx(a, (int64_t)blockIdx.x);
+    const C<T>* twN = (const C<T>*)a.tw + tw_off(N);
+    const C<T>* tw2N = (const C<T>*)a.tw + tw_off(2 * N);
+    const C<T>* F = (const C<T>*)a.f + c.of;
+    const C<T>* Gp = (const C<T>*)a.g + c.og;
+    C<T>* H = (C<T>*)a.h + c.oh;
+    const bool revf = a.flags & kRevF, cjg = a.flags & kConjG, revo = a.flags & kRevOut;
+    const T s = T(1) / T(2 * N);
+    // a fresh copy of t per phase keeps the addresses from being computed
+    // once and held across the whole kernel
+    auto fresh = [](int v) {
+        asm volatile("" : "+v"(v));
+        return v;
+    };
+    auto load_f = [&](C<T>* v) {
+        const int tt = fresh(t), z = opaque_zero();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = tt + e * G;
+            v[e] = ldz(F + z, revf ? c.m - 1 - k : k, c.m);
+        }
+    };
+    auto load_g = [&](C<T>* v) {
+        const int tt = fresh(t), z = opaque_zero();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const C<T> u = ldz(Gp + z, tt + e * G, c.m);
+            v[e] = cjg ? conj(u) : u;
+        }
+    };
+    // multiply by zeta_{2N}^{+-k}: the shift of residue 1
+    auto shift = [&](C<T>* v, bool inv) {
+        const int tt = fresh(t), z = opaque_zero();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const C<T> w = tw2N[tt + e * G + z];
+            v[e] = inv ? mulw<-1>(v[e], w) : mulw<+1>(v[e], w);
+        }
+    };
+    auto store = [&](const C<T>* v, bool add) {
+        const int tt = fresh(t);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = tt + e * G;
+            if (k < c.m) {
+                C<T>* hp = H + (revo ? c.m - 1 - k : k);
+                const C<T> u = scale(v[e], s);
+                *hp = add ? *hp + u : u;
+            }
+        }
+    };
+    C<T> x[E];
+    {
+        // residue 0
+        C<T> y[E];
+        load_f(x);
+        fft<T, N, E, +1>(x, t, lds, 1, twN);
+        load_g(y);
+        fft<T, N, E, +1>(y, t, lds, 1, twN);
+#pragma unroll
+        for (int e = 0; e < E; ++e) x[e] = x[e] * y[e];
+        fft<T, N, E, -1>(x, t, lds, 1, twN);
+    }
+    C<T> x1[E], y1[E];
+    load_f(x1);
+    load_g(y1);
+    // every thread's reads of the row have completed before any thread
+    // stores into it
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    store(x, false);
+    // residue 1
+    shift(x1, false);
+    fft<T, N, E, +1>(x1, t, lds, 1, twN);
+    shift(y1, false);
+    fft<T, N, E, +1>(y1, t, lds, 1, twN);
+#pragma unroll
+    for (int e = 0; e < E; ++e) x1[e] = x1[e] * y1[e];
+    fft<T, N, E, -1>(x1, t, lds, 1, twN);
+    shift(x1, true);
+    store(x1, true);
+}
+
 // ======================================================================
 // Complex 1D convolution with general p/q padding (Sec. 2.4).  The inputs
 // (zero beyond m) are taken as P blocks of NP values, P NP >= m, and padded
@@ -742,14 +849,16 @@ k_conv1d_hermitian(RowArgs a)
     constexpr int N = 2 * NC;
     constexpr int E = row_E<T, 1>(NC), G = NC / E, GPB = row_GPB<T, 1>(NC), LDSN = row_lds<T, 1>(NC);
     // three exchange buffers per row (the three residues transformed
-    // together) where they fit in LDS
+    // together) where they fit in LDS; else, for workgroup-wide transforms,
+    // two used in turn (one barrier per stage) where those fit
     constexpr bool TRI = 3 * GPB * LDSN * int(sizeof(C<T>)) <= 160 * 1024;
-    __shared__ C<T> sh[(TRI ? 3 : 1) * GPB * LDSN];
+    constexpr bool PP = !TRI && G > 64 && 2 * GPB * LDSN * int(sizeof(C<T>)) <= 160 * 1024;
+    __shared__ C<T> sh[(TRI ? 3 : (PP ? 2 : 1)) * GPB * LDSN];
     static_assert(sizeof(sh) <= 160 * 1024, "LDS footprint exceeds 160 KB");
     const int grp = threadIdx.x / G, t = threadIdx.x % G;
     const RowCtx c = row_ctx(a, (int64_t)blockIdx.x * GPB + grp);
     C<T>* lds = sh + grp * LDSN;
-    C<T>* lds1 = TRI ? sh + (GPB + grp) * LDSN : lds;
+    C<T>* lds1 = (TRI || PP) ? sh + (GPB + grp) * LDSN : lds;
     C<T>* lds2 = TRI ? sh + (2 * GPB + grp) * LDSN : lds;
     const C<T>* twb = (const C<T>*)a.tw;
     const C<T>* twNC = twb + tw_off(NC);
@@ -760,6 +869,10 @@ k_conv1d_hermitian(RowArgs a)
         constexpr int D = decltype(dir)::value;
         if constexpr (TRI) {
             fft3<T, NC, E, D>(v0, v1, v2, t, lds, lds1, lds2, 1, twNC);
+        } else if constexpr (PP) {
+            fft_pp<T, NC, E, D>(v0, t, lds, lds1, twNC);
+            fft_pp<T, NC, E, D>(v1, t, lds, lds1, twNC);
+            fft_pp<T, NC, E, D>(v2, t, lds, lds1, twNC);
         } else {
             fft<T, NC, E, D>(v0, t, lds, 1, twNC);
             fft<T, NC, E, D>(v1, t, lds, 1, twNC);
@@ -853,23 +966,23 @@ k_conv1d_hermitian(RowArgs a)
 // The same convolution for rows whose transform would take a whole
 // 1024-thread workgroup in the register-resident kernel (G = 1024: its build
 // of three residues of two inputs exceeds the 128 registers such a
-// workgroup leaves each thread).  Here one row takes 512 threads of NC / 512
-// values each, and the residues are formed and convolved one at a time: for residue
-// R every thread builds its entries of w_{k,R} from U_k, U_{NC+k} and the
-// mirrored U_{NC-k}, U_{N-k}, read from the input row itself, transforms
-// them, and the forward transform of the products is folded into the output
-// before the next residue starts.  Each input row is read twice per residue
-// (its own and its mirrored entries); all but the first read are served by
-// the caches.  Where two exchange-sized LDS buffers fit, the transformed f
-// waits in the second one while g is built and transformed, and the output
-// accumulates in registers; otherwise (complex128, NC = 8192) f stays in
-// registers and the output accumulates in h itself (stored for R = 0, read,
-// added to and stored again for R = +1, -1 by the same thread).
+// workgroup leaves each thread).  Here the residues are formed and convolved
+// one at a time: for residue R every thread builds its entries of w_{k,R}
+// from U_k, U_{NC+k} and the mirrored U_{NC-k}, U_{N-k}, read from the input
+// row itself, transforms them, and the forward transform of the products is
+// folded into the output before the next residue starts.  Each input row is
+// read twice per residue (its own and its mirrored entries); all but the
+// first read are served by the caches.  Where two exchange-sized LDS buffers
+// fit, the transformed f waits in the second one while g is built and
+// transformed; otherwise (complex128, NC = 8192) it stays in registers.  The
+// output accumulates in h itself (stored for R = 0, read, added to and
+// stored again for R = +1, -1 by the same thread): accumulators in
+// registers made the build spill.
 template <typename T, int NC>
 __host__ __device__ constexpr bool herm_staged()
 {
     // complex128 only: in complex64 the register-resident kernel, spills and
-    // all, measured faster (m = 16384: 0.172 against 0.178 ms for 256 rows,
+    // all, measured faster (m = 16384: 0.166 against 0.181 ms for 256 rows,
     // one row per compute unit, where the time is one row's latency)
     return sizeof(T) == 8 && NC > 1 && row_G<T, 1>(NC) == 1024;
 }
@@ -923,14 +1036,20 @@ __device__ __forceinline__ C<T> herm_build_one(const C<T>* U, int m, int k, T dc
     return c2r_pre(p, q, w2);
 }
 
+// Whether the staged kernel keeps f's transform in LDS (else in registers).
+template <typename T, int NC>
+__host__ __device__ constexpr bool herm_staged_xlds()
+{
+    return 2 * lpad_size(NC) * int(sizeof(C<T>)) <= 160 * 1024;
+}
+
 template <typename T, int NC, bool MD>
 __global__ void __launch_bounds__(kHermStagedThreads, kHermStagedThreads / 256)
 k_conv1d_hermitian_staged(RowArgs a)
 {
     constexpr int N = 2 * NC, G = kHermStagedThreads, E = NC / G, LDSN = lpad_size(NC);
     static_assert(E >= 2 && NC % G == 0, "staged Hermitian rows: NC / 512 values per thread");
-    constexpr bool XLDS = 2 * LDSN * int(sizeof(C<T>)) <= 160 * 1024;  // f's transform waits in LDS
-    constexpr int EO = XLDS ? E : 1;                                   // output accumulators in registers
+    constexpr bool XLDS = herm_staged_xlds<T, NC>();  // f's transform waits in LDS
     __shared__ C<T> sh[(XLDS ? 2 : 1) * LDSN];
     static_assert(sizeof(sh) <= 160 * 1024, "LDS footprint exceeds 160 KB");
     C<T>* A = sh;           // exchange buffer
@@ -947,7 +1066,7 @@ k_conv1d_hermitian_staged(RowArgs a)
     const T dc = adj ? T(2) : T(1);
     const T s = T(1) / T(3 * N);
     C<T>* H = (C<T>*)a.h + c.oh;
-    C<T> olo[EO], ohi[EO], ocen = zero<T>();
+    C<T> ocen = zero<T>();
     const T h3 = T(0.86602540378443864676);
     static_for<3>([&](auto ri) {
         constexpr int R = decltype(ri)::value == 0 ? 0 : (decltype(ri)::value == 1 ? 1 : -1);
@@ -1004,10 +1123,7 @@ k_conv1d_hermitian_staged(RowArgs a)
                 lo = R > 0 ? mulc(V, w) : V * w;
                 hi = z3 * (R > 0 ? w * conj(V) : mulc(conj(V), w));
             }
-            if constexpr (XLDS) {
-                olo[e] = R == 0 ? lo : olo[e] + lo;
-                ohi[e] = R == 0 ? hi : ohi[e] + hi;
-            } else {
+            {
                 // H_0 of the adjoint form is real and halved
                 const C<T> vlo = (e == 0 && k == 0 && adj) ? C<T>{T(0.5) * s * lo.re, T(0)} : scale(lo, s);
                 if (k < m) H[k] = R == 0 ? vlo : H[k] + vlo;
@@ -1021,15 +1137,6 @@ k_conv1d_hermitian_staged(RowArgs a)
         }
         __syncthreads();  // A is the exchange buffer of the next residue's transforms
     });
-    if constexpr (XLDS) {
-        const int tt = fresh_tid(t);
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int k = tt + e * G;
-            if (k < m) H[k] = (e == 0 && k == 0 && adj) ? C<T>{T(0.5) * s * olo[e].re, T(0)} : scale(olo[e], s);
-            if (k > 0 && N - k < m) H[N - k] = scale(ohi[e], s);
-        }
-    }
     if (t == 0 && NC < m) H[NC] = scale(ocen, s);
     if (c.act) {
         for (int64_t j = m + t; j < a.h_pad; j += G) H[j] = zero<T>();

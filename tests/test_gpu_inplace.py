@@ -2,12 +2,13 @@
 be f, g or e itself when the arrays have the same extent.  Every path -- row
 kernels, the general p/q rule, the three-pass long 1D form, the multi-pass
 2D/3D forms, the explicit comparators and a ragged batch -- must give, in
-place, bit for bit what it gives out of place."""
+place, bit for bit what it gives out of place (complex128 Hermitian rows of
+more than 4096 modes: to rounding, another kernel runs in place)."""
 import numpy as np
 import pytest
 
 import synth
-from gpu_util import need_gpu, say
+from gpu_util import need_gpu, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -34,6 +35,11 @@ CASES = [
     ("complex", "c64", (40, 33), None, 2, 0),
     ("hermitian", "c128", (5, 6, 4), (9, 12, 5), 2, 0),
     ("ternary", "c64", (12, 9), (24, 10), 2, 0),
+    ("complex", "c128", (8192,), None, 2, 0),       # 1024-thread row kernel, residues in turn
+    ("hermitian", "c64", (16384,), None, 2, 0),
+    ("hermitian", "c128", (8000,), None, 2, 0),     # staged rows, f's transform in LDS
+    ("hermitian", "c128", (16384,), None, 2, 0),    # staged rows accumulate in h: another kernel in place
+    ("hermitian", "c128", (3000,), None, 2, 0),
     ("complex", "c64", (500,), None, 2, 1),         # explicit comparator
     ("hermitian", "c64", (20, 17), (40, 18), 2, 1),  # explicit comparator
 ]
@@ -68,7 +74,12 @@ def test_in_place_equals_out_of_place(idx):
         out = {"f": F2, "g": G2, "e": E2}[which]
         plan.execute(F2, G2, e=E2, out=out)
         torch.cuda.synchronize()
-        assert torch.equal(out, ref), which
+        if kind == "hermitian" and len(m) == 1 and dts == "c128" and m[0] > 4096:
+            # in place, the register-resident kernel stands in for the staged
+            # one: the same sums in another order
+            assert rel(out.cpu().numpy(), ref.cpu().numpy()) < 1e-14, which
+        else:
+            assert torch.equal(out, ref), which
 
 
 def test_ragged_in_place():
