@@ -212,10 +212,12 @@ def wl_c3(args):
     expl = lambda: ic.conv2d(F, G, method="explicit")
     pruned = lambda: ic.conv2d(F, G, method="pruned")
     comp = (lambda: ic.conv2d(F, G, flags=ic.COMPENSATED)) if cdt == torch.complex64 else None
-    # algorithmic bytes per launch: every pass moves 3 S (Sec. 3.1 schedule)
-    kbytes = {"colpass_pad_bwd": 3 * S, "k_conv1d_complex": 3 * S, "colpass_pad_fwd": 3 * S}
-    # the row kernel convolves 2 m_x rows per pair (one launch per x residue)
-    kflops = {"k_conv1d_complex": B * mx * flops_row_complex(my)}
+    # algorithmic bytes: every column pass moves 3 S per launch (Sec. 3.1
+    # schedule); the rows of both x residues (2 m_x rows per pair, 3 S per
+    # residue) run in one launch
+    kbytes = {"colpass_pad_bwd": 3 * S, "colpass_pad_fwd": 3 * S}
+    kbytes_step = {"k_conv1d_complex": 6 * S}
+    kflops_step = {"k_conv1d_complex": 2 * B * mx * flops_row_complex(my)}
     step_bytes = 15 * S
 
     def cpu_baseline(h_gpu, h_expl=None, h_comp=None):
@@ -272,7 +274,8 @@ def wl_c3(args):
                        f"{'complex64' if cdt == torch.complex64 else 'complex128'}",
            "m": [mx, my], "batch": B, "M": 1, "dtype": args.dtype}
     return dict(run=run, explicit=expl, pruned=pruned, compensated=comp, convs=B, step_bytes=step_bytes,
-                kbytes=kbytes, kflops=kflops, cfg=cfg, cpu=cpu_baseline, out=lambda: run().cpu().numpy())
+                kbytes=kbytes, kbytes_step=kbytes_step, kflops_step=kflops_step, cfg=cfg, cpu=cpu_baseline,
+                out=lambda: run().cpu().numpy())
 
 
 def wl_x3(args):

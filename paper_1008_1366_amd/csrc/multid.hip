@@ -385,7 +385,28 @@ impconv_status outer_fwd(const DevTables& tb, const PlanND& p, void* const* src,
 
 // Innermost-axis row convolutions over nrows rows, in place in f.
 impconv_status inner_rows(const DevTables& tb, const PlanND& p, void* f, const void* g,
-                          int64_t nrows, hipStream_t s, uint32_t rowflags = 0)
+                          int64_t nrows, hipStream_t s, uint32_t rowflags = 0);
+
+// The rows of R residue arrays: one launch over all of them where the arrays
+// lie back to back (the rows then have one uniform stride), else one launch
+// per residue.  Fewer, longer launches leave less of the chip idle at each
+// launch's tail.
+impconv_status inner_rows_residues(const DevTables& tb, const PlanND& p, void* const* f, const void* const* g,
+                                   int R, int64_t nrows, hipStream_t s, uint32_t rowflags = 0)
+{
+    const size_t arr = size_t(nrows) * p.M * p.n[p.nd - 1] * csize(p.dt);
+    bool contiguous = true;
+    for (int r = 1; r < R; ++r)
+        contiguous = contiguous && static_cast<const char*>(f[r]) == static_cast<const char*>(f[0]) + r * arr &&
+                     static_cast<const char*>(g[r]) == static_cast<const char*>(g[0]) + r * arr;
+    if (contiguous) return inner_rows(tb, p, f[0], g[0], R * nrows, s, rowflags);
+    impconv_status st = IMPCONV_OK;
+    for (int r = 0; r < R && !st; ++r) st = inner_rows(tb, p, f[r], g[r], nrows, s, rowflags);
+    return st;
+}
+
+impconv_status inner_rows(const DevTables& tb, const PlanND& p, void* f, const void* g,
+                          int64_t nrows, hipStream_t s, uint32_t rowflags)
 {
     const int nd = p.nd;
     const int64_t m = p.m[nd - 1], n = p.n[nd - 1];
@@ -999,8 +1020,7 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
                             mask_nz, 0, 1, int(m1), s, fs_f | ha))) return st;
         if ((st = outer_bwd(tb, p, g, Wg, batch, M * n0 * n1, n0, m0, N0, n1, sym ? 1 : 0, 0, 0, 0,
                             mask_nz, 0, 1, int(m1), s, fs_g))) return st;
-        for (int r = 0; r < R; ++r)
-            if ((st = inner_rows(tb, p, Wf[r], Wg[r], batch * N0, s, rowfl))) return st;
+        if ((st = inner_rows_residues(tb, p, Wf, Wg, R, batch * N0, s, rowfl))) return st;
         if ((st = outer_fwd(tb, p, Wf, h, batch, N0 * M * n1, M * n1, n0, m0, N0, n1, s, fs_o | ha,
                             ha ? 1 : 0))) return st;
         return IMPCONV_OK;
@@ -1066,9 +1086,17 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
     // rows and y forward pass of np planes from y-residue set Y into the
     // planes' term 0 in Xf[rx] at xf
     auto rows_fwd = [&](void* const* YF, void* const* YG, char* xf, int64_t np, hipStream_t q) -> impconv_status {
-        impconv_status st2;
-        for (int ry = 0; ry < R; ++ry)
-            if ((st2 = inner_rows(tb, p, YF[ry], YG[ry], np * N1, q, rowfl))) return st2;
+        // complex64: one launch over the R residues (3D Hermitian 512^2 x 257,
+        // M = 3: 10.23 -> 9.95 ms per step); complex128: one launch per
+        // residue, which leaves the next chunk's y backward pass room to
+        // start between them (one launch: 17.79 -> 18.10 ms)
+        impconv_status st2 = IMPCONV_OK;
+        if (dt == IMPCONV_C64) {
+            st2 = inner_rows_residues(tb, p, YF, YG, R, np * N1, q, rowfl);
+        } else {
+            for (int ry = 0; ry < R && !st2; ++ry) st2 = inner_rows(tb, p, YF[ry], YG[ry], np * N1, q, rowfl);
+        }
+        if (st2) return st2;
         // y forward: [plane][y'][i = 0][n2] (R residues) -> term 0 of the plane in Xf[rx]
         ColArgs c = col_args(tb, dt);
         for (int r = 0; r < 3; ++r) c.in[r] = YF[r];
