@@ -193,18 +193,23 @@ struct PlanND {
 
 // 3D: the y backward pass, the innermost rows and the y forward pass run
 // over chunks of the (b, x') planes, with two sets of y-residue arrays sized
-// for a chunk, used by the chunks in turn.  kYChunks chunks (fewer when there
-// are fewer planes) keep that region at 2 / kYChunks of the full y-residue
-// volume, which keeps the 3D work memory under the explicitly padded
-// method's storage (Sec. 3.4 storage counts) while every launch still spans
-// many planes.
+// for a chunk, used by the chunks in turn.  With c chunks (fewer when there
+// are fewer planes) that region is 2 / c of the full y-residue volume.
+// Centered Hermitian: c = 8 keeps the 3D work memory under the explicitly
+// padded method's storage (Sec. 3.4 storage counts; c = 4 would exceed it)
+// while every launch still spans many planes.  Complex: the y residues are
+// fewer (two per axis) and the bound holds for any c; c = 2 (256^3, batch 2:
+// 2.93 -> 2.80 ms in complex64, 5.10 -> 4.79 ms in complex128 against c = 8)
+// keeps the launches long and still lets one chunk's rows run beside the
+// other chunk's y backward pass.
 #ifndef IMPCONV_3D_YCHUNKS
 #define IMPCONV_3D_YCHUNKS 8
 #endif
 constexpr int64_t kYChunks = IMPCONV_3D_YCHUNKS;
-int64_t y_chunk_planes(int64_t planes)
+constexpr int64_t kYChunksComplex = 2;
+int64_t y_chunk_planes(int64_t planes, int64_t chunks)
 {
-    return std::max<int64_t>(1, (planes + kYChunks - 1) / kYChunks);
+    return std::max<int64_t>(1, (planes + chunks - 1) / chunks);
 }
 
 impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t* n, int64_t batch,
@@ -310,7 +315,7 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
         // (the rows of one chunk run beside the y pass of the next)
         const size_t X = size_t(2) * R * batch * M * p->Np[0] * n[1] * n[2];
         const int64_t planes = batch * p->Np[0];
-        p->ychunk = y_chunk_planes(planes);
+        p->ychunk = y_chunk_planes(planes, kind == IMPCONV_COMPLEX ? kYChunksComplex : kYChunks);
         const size_t Y = size_t(2) * R * p->ychunk * M * p->Np[1] * n[2];
         p->work = (X + 2 * Y) * cs;
     }
