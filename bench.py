@@ -740,8 +740,11 @@ def wl_t2(args):
     cs = 8 if cdt == torch.complex64 else 16
     S = B * n[0] * n[1] * cs
     run = lambda: ic.conv2d_ternary(F, G, E, m)
-    expl = (lambda: ic.conv2d_ternary(F, G, E, m, method="explicit")) if mm <= 1024 else None
-    pruned = (lambda: ic.conv2d_ternary(F, G, E, m, method="pruned")) if mm <= 1024 else None
+    # the comparator's x transforms have 4 N0' points: up to 16384 (complex64)
+    # or 4096 (complex128)
+    cmp_ok = mm <= (4096 if cdt == torch.complex64 else 1024)
+    expl = (lambda: ic.conv2d_ternary(F, G, E, m, method="explicit")) if cmp_ok else None
+    pruned = (lambda: ic.conv2d_ternary(F, G, E, m, method="pruned")) if cmp_ok else None
     P0 = 2 * (1 << int(np.ceil(np.log2(mm))))
     # per launch: x backward reads one input (S) and writes two residues (2S);
     # rows read three residue arrays and write one; x forward reads 2S, writes S
@@ -785,7 +788,13 @@ def wl_t2(args):
             us.append(u)
         h1 = ic.conv2d_ternary(*(torch.from_numpy(u).to("cuda", cdt) for u in us), m).cpu().numpy()
         xfull = np.convolve(np.convolve(vecs[0], vecs[1]), vecs[2])[2 * (mm - 1):4 * (mm - 1) + 1]
-        yref = oracle.conv1d_ternary(*ys)
+        if mm <= 1024:
+            yref = oracle.conv1d_ternary(*ys)
+        else:
+            # the oracle's direct triple sum is O(m^3); the same sum over the
+            # conjugate-extended halves by two numpy convolutions, k = 0..m-1
+            yf = [np.concatenate([np.conj(b[:0:-1]), b]) for b in ys]
+            yref = np.convolve(np.convolve(yf[0], yf[1]), yf[2])[3 * (mm - 1):3 * (mm - 1) + mm]
         r1 = np.zeros(n, complex)
         r1[1:, :mm] = np.outer(xfull, yref)
         err = {"rank_one_full_field": float(np.linalg.norm(h1 - r1) / np.linalg.norm(r1)),

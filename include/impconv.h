@@ -317,13 +317,14 @@ size_t impconv_noalloc_capacity(void);
  * residues of the centered transform padded to 4 N0', N0' = 2^ceil(log2 m0),
  * transforms of size 2 N0'), every row the 1D ternary convolution.  Workspace
  * (impconv_convnd_workspace with kind IMPCONV_TERNARY, ndim 2, M = 1):
- * 8 * batch * 2 N0' * n1 complex values.  This build: m0 <= 2048,
- * m1 <= 8192; E_UNSUPPORTED beyond.
+ * 8 * batch * 2 N0' * n1 complex values.  This build: m0 <= 4096 in
+ * complex64, 2048 in complex128; m1 <= 8192; E_UNSUPPORTED beyond.
  * IMPCONV_EXPLICIT_PADDED: the conventional comparator -- f, g, e copied into
  * zero-padded [4 N0'][2 N1' + 1] arrays (x wavenumbers wrapped modulo 4 N0'),
  * full-size complex FFTs along x, real cyclic triple products of length
  * 4 N1' along y, inverse x FFT, crop; it reads the k_y = 0 line as its
- * Hermitian projection (m0 <= 1024, m1 <= 4096; workspace
+ * Hermitian projection (m0 <= 4096 in complex64, 1024 in complex128;
+ * m1 <= 4096; workspace
  * 3 * batch * 4 N0' * (2 N1' + 1) complex values).  IMPCONV_EXPLICIT_PRUNED
  * as well: the all-zero columns k_y >= m1 are not transformed. */
 impconv_status impconv_conv2d_ternary(int dtype, int64_t batch, const int64_t* m, const int64_t* n,

@@ -23,6 +23,10 @@ hipError_t launch_col_fft(int dt, int N, int dir, const ColArgs& a, hipStream_t 
                                     : (dt ? go<double, n, -1>(a, s) : go<float, n, -1>(a, s));
         IMPCONV_COL_CASES(X)
 #undef X
+        // the explicit tconv2 comparator's x transform at m_x up to 4096
+        // (complex64: tiles of two and one columns)
+        case 8192: return dt ? hipErrorInvalidValue : (dir > 0 ? go<float, 8192, 1>(a, s) : go<float, 8192, -1>(a, s));
+        case 16384: return dt ? hipErrorInvalidValue : (dir > 0 ? go<float, 16384, 1>(a, s) : go<float, 16384, -1>(a, s));
     }
     return hipErrorInvalidValue;
 }

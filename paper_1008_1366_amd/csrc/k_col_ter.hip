@@ -23,6 +23,9 @@ hipError_t launch_col_ter(int dt, int N, int mode, const ColArgs& a, hipStream_t
                                         : (dt ? go<double, n, kTerFwd>(a, s) : go<float, n, kTerFwd>(a, s));
         IMPCONV_COL_CASES(X)
 #undef X
+        // complex64 tconv2 with m_x up to 4096: tiles of two columns
+        case 8192: return dt ? hipErrorInvalidValue : (mode == kTerBwd ? go<float, 8192, kTerBwd>(a, s)
+                                                                     : go<float, 8192, kTerFwd>(a, s));
     }
     return hipErrorInvalidValue;
 }

@@ -49,8 +49,13 @@ hipError_t launch_copy2d(int dt, const void* src, void* dst, int64_t nb, int64_t
                          int64_t sbs2, int64_t sld, int64_t dbs, int64_t dbs2, int64_t dld, int64_t cx,
                          int64_t cy, int64_t dx, int64_t dy, hipStream_t s);
 
-// Column passes (colpass.hpp); N <= kColMax.
+// Column passes (colpass.hpp); N <= kColMax, except, in complex64, the
+// ternary passes (N <= 8192: tconv2 with m_x up to 4096, tiles of two
+// columns) and the plain FFT pass of the comparators (N <= 16384, tiles of
+// one column).  Indexed by dtype.
 constexpr int kColMax = 4096;
+constexpr int kTerColMax[2] = {8192, 4096};
+constexpr int kFftColMax[2] = {16384, 4096};
 struct ColArgs;
 hipError_t launch_col(int dt, int N, int mode, int dir, const ColArgs& a, hipStream_t s);
 hipError_t launch_col_pad(int dt, int N, int mode, const ColArgs& a, hipStream_t s);

@@ -251,8 +251,9 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
         }
         p->Np[d] = next_pow2(m[d]);
         if (!last && p->Np[d] > kColMax) return fail(IMPCONV_E_UNSUPPORTED, "outer axis too long (m <= 4096)");
-        if (!last && kind == IMPCONV_TERNARY && 2 * p->Np[d] > kColMax)
-            return fail(IMPCONV_E_UNSUPPORTED, "ternary outer axis too long (m <= 2048)");
+        if (!last && kind == IMPCONV_TERNARY && 2 * p->Np[d] > kTerColMax[dt])
+            return fail(IMPCONV_E_UNSUPPORTED, dt ? "ternary outer axis too long (complex128: m <= 2048)"
+                                                  : "ternary outer axis too long (complex64: m <= 4096)");
         if (last) {
             int64_t L = kind == IMPCONV_COMPLEX || kind == IMPCONV_TERNARY ? p->Np[d]
                                                                           : std::max<int64_t>(p->Np[d], 2) / 2;
@@ -296,8 +297,9 @@ impconv_status plannd(int kind, int dt, int nd, const int64_t* m, const int64_t*
     if (kind == IMPCONV_TERNARY && (flags & IMPCONV_EXPLICIT_PADDED)) {
         // padded f, g, e: [b][4 Np0][2 Np1 + 1] (x padded to 4 Np0, y real length 4 Np1)
         const int64_t P0 = 4 * p->Np[0], L = 2 * p->Np[1] + 1;
-        if (P0 > kColMax || 2 * p->Np[1] > kRowMax)
-            return fail(IMPCONV_E_UNSUPPORTED, "explicit ternary 2D comparator supports m0 <= 1024, m1 <= 4096");
+        if (P0 > kFftColMax[dt] || 2 * p->Np[1] > kRowMax)
+            return fail(IMPCONV_E_UNSUPPORTED, dt ? "explicit ternary 2D comparator supports m0 <= 1024, m1 <= 4096"
+                                                  : "explicit ternary 2D comparator supports m0 <= 4096, m1 <= 4096");
         p->work = size_t(3) * batch * P0 * L * cs;
     } else if (kind == IMPCONV_TERNARY) {
         // x residues of f, g, e (2 each, 2 Np0 rows); the rows write their

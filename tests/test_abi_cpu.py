@@ -183,8 +183,9 @@ def test_plan_create_validation(L):
     assert create(M=0) == 2
     assert create(batch=-1) == 2
     assert create(kind=2, ndim=3, m=(4, 4, 4), n=(8, 8, 5)) == 5  # ternary is 1D or 2D
-    assert create(kind=2, ndim=2, m=(4096, 4, 0), n=(8192, 5, 0)) == 5  # ternary x axis m <= 2048
-    assert create(kind=2, ndim=2, m=(2048, 4, 0), n=(4096, 5, 0), flags=1) == 5  # explicit: m0 <= 1024
+    assert create(kind=2, ndim=2, m=(8192, 4, 0), n=(16384, 5, 0)) == 5  # ternary x axis m <= 4096
+    # explicit: m0 <= 4096 in complex64, 2048 in complex128
+    assert create(kind=2, dtype=1, ndim=2, m=(4096, 4, 0), n=(8192, 5, 0), flags=1) == 5
     assert create(kind=1, ndim=2, m=(4, 4, 0), n=(9, 5, 0)) == 2  # centered axis needs 2m-1 or 2m
     assert create(kind=0, ndim=2, m=(4, 4, 0), n=(4, 5, 0)) == 2  # complex storage n == m
     assert create(flags=1 << 8) == 1  # ONE_STREAM is for ragged batches only

@@ -1,8 +1,10 @@
 """GPU parity of the 2D centered Hermitian ternary convolution (Sec. 4,
 tconv2) against the FP64 oracle: full fields on small grids spanning several
-tiles, odd and even storage and ragged sizes; the symmetrization readings; a
-rank-one input on a 2048-mode x axis checked on the full field against
-outer products of 1D oracle results; sampled outputs of random inputs."""
+tiles, odd and even storage and ragged sizes; the symmetrization readings;
+rank-one inputs on x axes of 2048 to 4096 modes checked on the full field
+against outer products of 1D oracle results (with the comparator); random
+inputs on the longest x axes with a narrow y axis; sampled outputs of
+random inputs."""
 import numpy as np
 import pytest
 
@@ -54,6 +56,94 @@ def test_tconv2_symmetrization_readings():
     assert rel(h, oracle.convnd_ternary(f, g, e, m)) < 1e-12
     hp = ic.conv2d_ternary(F, G, E, m, symmetrize=False).cpu().numpy()
     assert rel(hp, oracle.convnd_ternary(f, g, e, m, symmetrize=False)) < 1e-12
+
+
+def rank_one_case(mx, my, n, dt):
+    """Rank-one inputs U = A (x) b (A a centered Hermitian vector, b a half
+    with b_0 real) and the exact result: a full centered ternary sum in x
+    (two numpy convolutions of the FP64 vectors) times the 1D Hermitian
+    ternary oracle in y."""
+    vecs = []
+    for s in (321, 322, 323):
+        a = synth.unit_disk(mx, s)
+        a[0] = a[0].real
+        vecs.append(np.concatenate([np.conj(a[:0:-1]), a]))  # k = -mx+1 .. mx-1
+    ys = []
+    for s in (324, 325, 326):
+        b = synth.unit_disk(my, s)
+        b[0] = b[0].real
+        ys.append(b)
+    off = n[0] - (2 * mx - 1)  # storage row of k_x = -mx+1
+    fields = []
+    for A, b in zip(vecs, ys):
+        u = np.zeros(n, complex)
+        u[off:, :my] = np.outer(A, b)
+        fields.append(u)
+    Ar = [rounded(A, dt) for A in vecs]
+    br = [rounded(b, dt) for b in ys]
+    xfull = np.convolve(np.convolve(Ar[0], Ar[1]), Ar[2])[2 * (mx - 1):4 * (mx - 1) + 1]
+    ref = np.zeros(n, complex)
+    ref[off:, :my] = np.outer(xfull, oracle.conv1d_ternary(*br))
+    return fields, ref
+
+
+@pytest.mark.parametrize("mx,my,n", [(2049, 8, (4097, 8)), (3000, 64, (5999, 64)), (4096, 256, (8192, 257))])
+def test_tconv2_rank_one_longest_x(mx, my, n):
+    """Complex64 x axes of 2049 to 4096 modes (transforms of 8192 points
+    along x, column tiles of two columns), full field against the factored
+    exact result; the explicit comparator and its pruned form as well
+    (x FFTs of 4 N0' = 16384 points, one column per tile)."""
+    dt = np.complex64
+    ic = need_gpu()
+    say(f"tconv2 rank one {mx} x {my} {dt.__name__}")
+    fields, ref = rank_one_case(mx, my, n, dt)
+    args = [to_dev(u, dt) for u in fields]
+    h = ic.conv2d_ternary(*args, (mx, my)).cpu().numpy()
+    assert rel(h, ref) < TOL[dt]
+    if n[0] == 2 * mx:
+        assert np.all(h[0] == 0)
+    if n[1] == my + 1:
+        assert np.all(h[:, my] == 0)
+    for method in ("explicit", "pruned"):
+        he = ic.conv2d_ternary(*args, (mx, my), method=method).cpu().numpy()
+        assert rel(he, ref) < TOL[dt], method
+
+
+def test_tconv2_longest_x_limits():
+    """Beyond the column passes: complex128 x axes stop at 2048 modes (1024
+    for the comparator), complex64 at 4096."""
+    ic = need_gpu()
+    import torch
+    for dt, mx, method in [(torch.complex128, 2049, "implicit"), (torch.complex128, 1025, "explicit"),
+                           (torch.complex64, 4097, "implicit"), (torch.complex64, 4097, "explicit")]:
+        z = torch.zeros((1, 2 * mx, 3), dtype=dt, device="cuda")
+        with pytest.raises(ic.ImpconvError):
+            ic.conv2d_ternary(z, z, z, (mx, 2), method=method)
+
+
+@pytest.mark.parametrize("m,n", [((4096, 1), (8192, 1)), ((3000, 1), (5999, 1))])
+def test_tconv2_longest_x_random(m, n):
+    """Random inputs on the longest x axes with a one-mode y axis: the whole
+    field is the k_y = 0 line, symmetrized on load from its k_x >= 0 half
+    (Im of the origin dropped), so the result is the full centered ternary
+    sum of the symmetrized x vectors (two numpy convolutions in FP64);
+    complex64, the dtype whose x axis reaches 4096 modes."""
+    dt = np.complex64
+    ic = need_gpu()
+    say(f"tconv2 random m={m} n={n} {dt.__name__}")
+    mx = m[0]
+    off = n[0] - mx  # storage row of k_x = 0
+    us = [storage(m, n, s) for s in (361, 362, 363)]
+    h = ic.conv2d_ternary(*(to_dev(u, dt) for u in us), m).cpu().numpy()
+    full = []
+    for u in us:
+        a = rounded(u[off:off + mx, 0], dt).copy()
+        a[0] = a[0].real
+        full.append(np.concatenate([np.conj(a[:0:-1]), a]))
+    x = np.convolve(np.convolve(full[0], full[1]), full[2])[2 * (mx - 1):4 * (mx - 1) + 1]
+    ref = np.zeros(n, complex)
+    ref[n[0] - (2 * mx - 1):, 0] = x
+    assert rel(h, ref) < TOL[dt]
 
 
 @pytest.mark.parametrize("dt", DT)
