@@ -418,6 +418,78 @@ __device__ __forceinline__ void fft_pp(C<T> (&v)[E], int t, C<T>* lds0, C<T>* ld
     __syncthreads();
 }
 
+// Two independent transforms advanced together (as fft2_stage) over two
+// pairs of exchange buffers used in turn (as fft_pp_stage): one barrier per
+// stage for both.
+template <typename T, int N, int E, int DIR, int NS, typename TW>
+__device__ __forceinline__ void fft2_pp_stage(C<T> (&v0)[E], C<T> (&v1)[E], int t, C<T>* l0, C<T>* l1, C<T>* n0,
+                                              C<T>* n1, TW tw)
+{
+    constexpr int R = (N / NS < E) ? (N / NS) : E;
+    constexpr bool LAST = (NS * R == N);
+    constexpr int G = N / E;
+    constexpr int Q = E / R;
+    int zoff = 0;
+    asm volatile("" : "+s"(zoff));
+    asm volatile("" : "+v"(t));
+    const TW tws = tw + zoff;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int b = t + q * G;
+        const int k = b & (NS - 1);
+        C<T> u0[R], u1[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            u0[r] = v0[q + r * Q];
+            u1[r] = v1[q + r * Q];
+        }
+        if constexpr (NS > 1) {
+            const int ks = k * (N / (NS * R));
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const auto w = tws[r * ks];
+                u0[r] = mulw<DIR>(u0[r], w);
+                u1[r] = mulw<DIR>(u1[r], w);
+            }
+        }
+        DFT<R, DIR, T>::run(u0);
+        DFT<R, DIR, T>::run(u1);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                v0[q + r * Q] = u0[r];
+                v1[q + r * Q] = u1[r];
+            }
+        } else {
+            const int wb = lpad((b - k) * R + k);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                l0[wb + r * NS + ((r * NS) >> 4)] = u0[r];
+                l1[wb + r * NS + ((r * NS) >> 4)] = u1[r];
+            }
+        }
+    }
+    if constexpr (!LAST) {
+        __syncthreads();
+        const int rb = lpad(t);
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            v0[i] = l0[rb + i * G + ((i * G) >> 4)];
+            v1[i] = l1[rb + i * G + ((i * G) >> 4)];
+        }
+        fft2_pp_stage<T, N, E, DIR, NS * R, TW>(v0, v1, t, n0, n1, l0, l1, tw);
+    }
+}
+
+template <typename T, int N, int E, int DIR, typename TW>
+__device__ __forceinline__ void fft2_pp(C<T> (&v0)[E], C<T> (&v1)[E], int t, C<T>* l0, C<T>* l1, C<T>* n0,
+                                        C<T>* n1, TW tw)
+{
+    static_assert(N % E == 0 && N / E > 64, "ping-pong exchanges serve workgroup-wide transforms");
+    fft2_pp_stage<T, N, E, DIR, 1, TW>(v0, v1, t, l0, l1, n0, n1, tw);
+    __syncthreads();
+}
+
 // Compile-time loop: f(std::integral_constant<int, i>{}) for i = 0..n-1.
 template <typename F, int... I>
 __device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>)

@@ -1232,7 +1232,10 @@ k_conv1d_ternary(RowArgs a)
 {
     constexpr int E = row_E<T, 1>(NN), G = NN / E, GPB = row_GPB<T, 1>(NN), LDSN = row_lds<T, 1>(NN);
     constexpr bool DUALS = !ACCG && 2 * GPB * LDSN * int(sizeof(C<T>)) <= 160 * 1024;
-    __shared__ C<T> sh[(DUALS ? 2 : 1) * GPB * LDSN];
+    // transforms of 256 threads or more: two pairs of exchange buffers used
+    // in turn (one barrier per stage) where they fit
+    constexpr bool PP2 = DUALS && G >= 256 && 4 * GPB * LDSN * int(sizeof(C<T>)) <= 160 * 1024;
+    __shared__ C<T> sh[(PP2 ? 4 : (DUALS ? 2 : 1)) * GPB * LDSN];
     static_assert(sizeof(sh) <= 160 * 1024, "LDS footprint exceeds 160 KB");
     const int grp = threadIdx.x / G, t = threadIdx.x % G;
     const RowCtx c = row_ctx(a, (int64_t)blockIdx.x * GPB + grp);
@@ -1255,7 +1258,10 @@ k_conv1d_ternary(RowArgs a)
         const int mm = m < NN ? m : NN;
         auto pair = [&](auto& a0, auto& a1, auto dir) {
             constexpr int D = decltype(dir)::value;
-            if constexpr (DUAL) {
+            if constexpr (PP2) {
+                fft2_pp<T, NN, E, D>(a0, a1, t, lds, lds1, sh + (2 * GPB + grp) * LDSN, sh + (3 * GPB + grp) * LDSN,
+                                     twNN);
+            } else if constexpr (DUAL) {
                 fft2<T, NN, E, D>(a0, a1, t, lds, lds1, 1, twNN);
             } else {
                 fft<T, NN, E, D>(a0, t, lds, 1, twNN);

@@ -41,6 +41,22 @@ def test_hermitian_1d_backward_vs_oracle(m):
             assert rel(G.grad[b, i].cpu().numpy(), herm_adj_ref(w[b], f[b, i])) < 1e-12
 
 
+@pytest.mark.parametrize("dt", [np.complex128, np.complex64])
+@pytest.mark.parametrize("m", [6000, 16384])
+def test_hermitian_1d_adjoint_flag_long_rows(dt, m):
+    """HERMITIAN_ADJOINT on the long-row kernels (complex64: the
+    register-resident kernel with two-buffer exchanges at 8192 modes;
+    complex128: the staged kernel), against the oracle-evaluated adjoint."""
+    ic = need_gpu()
+    say(f"hermitian adjoint flag m={m} {dt.__name__}")
+    w = synth.unit_disk((2, 1, m), 366)
+    g = synth.unit_disk((2, 1, m), 367)
+    got = ic.conv1d_hermitian(to_dev(w[:, 0], dt), to_dev(g[:, 0], dt), flags=ic.HERMITIAN_ADJOINT).cpu().numpy()
+    ref = herm_adj_ref(rounded(w, dt), rounded(g, dt))
+    assert rel(got, ref) < TOL[dt]
+    assert np.all(got[:, 0].imag == 0)
+
+
 def test_hermitian_1d_gradcheck():
     ic = need_gpu()
     import torch
