@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import TOL, need_gpu, rel, rounded, say, to_dev
+from gpu_util import TOL, need_gpu, rel, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
