@@ -63,6 +63,8 @@ def test_workspace_query_and_size_errors(L):
     assert ws(L, 5, 0, 1, 1, 8)[0] == 1                # bad kind
     assert ws(L, 1, 0, 1, 1, 8, 2)[0] == 1             # REV flag on Hermitian
     assert ws(L, 0, 0, 1, 1, 1 << 20)[0] == 5          # beyond the four-step range
+    assert ws(L, 0, 0, 1, 1, 1 << 17) == (0, 4 * (1 << 17) * 8)  # its last length
+    assert ws(L, 0, 0, 1, 1, (1 << 17) + 1)[0] == 5
     assert ws(L, 1, 0, 1, 1, 16384)[0] == 0
     assert ws(L, 1, 0, 1, 1, 16385)[0] == 5
     # EXPLICIT_PRUNED: complex 1D with EXPLICIT_PADDED only; no workspace

@@ -40,7 +40,7 @@ def test_complex_1d_mdot(dt, m):
 
 
 @pytest.mark.parametrize("dt", DT)
-@pytest.mark.parametrize("m", [8193, 16384, 65536])
+@pytest.mark.parametrize("m", [8193, 16384, 65536, 131072])
 def test_complex_1d_fourstep(dt, m):
     """Lengths past one workgroup: four-step passes, sampled oracle outputs."""
     ic = need_gpu()
