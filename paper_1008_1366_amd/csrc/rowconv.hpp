@@ -842,6 +842,9 @@ __device__ __forceinline__ void herm_build3_from(C<T> (&lo)[E], C<T> (&hi)[E], i
 //   3N H_k = sum_r zeta_{3N}^{-rk} V_r(k),  V_r(N-k) = conj V_r(k).
 // Each input row is read once; the three residues are built from registers.
 // ======================================================================
+#ifndef IMPCONV_HERM_TW_LDS
+#define IMPCONV_HERM_TW_LDS 1
+#endif
 template <typename T, int NC, bool MD>
 __global__ void __launch_bounds__((row_block<T, 1>(NC)), row_waves<T>(NC))
 k_conv1d_hermitian(RowArgs a)
@@ -855,6 +858,14 @@ k_conv1d_hermitian(RowArgs a)
     constexpr bool PP = !TRI && G > 64 && 2 * GPB * LDSN * int(sizeof(C<T>)) <= 160 * 1024;
     __shared__ C<T> sh[(TRI ? 3 : (PP ? 2 : 1)) * GPB * LDSN];
     static_assert(sizeof(sh) <= 160 * 1024, "LDS footprint exceeds 160 KB");
+    // short rows: the twiddle tables a row uses (zeta_NC, zeta_N, zeta_3N:
+    // NC + 2N values) are copied into LDS once per workgroup, so that every
+    // transform stage and residue shift reads them there instead of waiting
+    // on global loads; only where the workgroup's LDS stays within 40 KB
+    // (four workgroups per compute unit)
+    constexpr bool TWL = IMPCONV_HERM_TW_LDS && NC >= 2 && NC <= 256 &&
+                         int(sizeof(sh)) + (NC + 2 * N) * int(sizeof(C<T>)) <= 40 * 1024;
+    __shared__ C<T> twl[TWL ? NC + 2 * N : 1];
     const int grp = threadIdx.x / G, t = threadIdx.x % G;
     const RowCtx c = row_ctx(a, (int64_t)blockIdx.x * GPB + grp);
     C<T>* lds = sh + grp * LDSN;
@@ -864,6 +875,14 @@ k_conv1d_hermitian(RowArgs a)
     const C<T>* twNC = twb + tw_off(NC);
     const C<T>* twN = twb + tw_off(N);
     const C<T>* tw3N = (const C<T>*)a.tw3 + tw_off(N);
+    if constexpr (TWL) {
+        for (int j = threadIdx.x; j < NC + 2 * N; j += blockDim.x)
+            twl[j] = j < NC ? twNC[j] : (j < NC + N ? twN[j - NC] : tw3N[j - NC - N]);
+        __syncthreads();
+        twNC = twl;
+        twN = twl + NC;
+        tw3N = twl + NC + N;
+    }
     const int m = c.m;
     auto fft3x = [&](C<T> (&v0)[E], C<T> (&v1)[E], C<T> (&v2)[E], auto dir) {
         constexpr int D = decltype(dir)::value;
