@@ -65,7 +65,8 @@ __device__ __forceinline__ void queue_item(RowArgs a, const QueueClass& k, int64
     a.nrows = k.count;
     a.m = k.maxm;
     const RowCtx c = row_ctx(a, j * GQ + grp);
-    conv_complex_row<T, N, E, true, false>(a, c, t, sh + grp * LDSN, sh + (GQ + grp) * LDSN);
+    conv_complex_row<T, N, E, true, false>(a, c, t, sh + grp * LDSN, sh + (GQ + grp) * LDSN,
+                                           tw_src<T, false>(a, tw_off(N)), tw_src<T, false>(a, tw_off(2 * N)));
 }
 
 // Item j of class k: dispatch on (N, E), uniform over the workgroup.

@@ -179,11 +179,9 @@ __device__ __forceinline__ C<T> ldz_masked(const C<T>* U, int j, int m)
 // per row, t < G).
 template <typename T, int N, int E, bool DUAL, bool COMP>
 __device__ __forceinline__ void conv_complex_row(const RowArgs& a, const RowCtx& c, int t, C<T>* lds,
-                                                 C<T>* lds1)
+                                                 C<T>* lds1, TwSrc<T, COMP> twN, TwSrc<T, COMP> tw2N)
 {
     constexpr int G = N / E;
-    const TwSrc<T, COMP> twN = tw_src<T, COMP>(a, tw_off(N));
-    const TwSrc<T, COMP> tw2N = tw_src<T, COMP>(a, tw_off(2 * N));
     const C<T>* F = (const C<T>*)a.f + c.of;
     const C<T>* Gp = (const C<T>*)a.g + c.og;
     C<T>* H = (C<T>*)a.h + c.oh;
@@ -236,6 +234,12 @@ __device__ __forceinline__ void conv_complex_row(const RowArgs& a, const RowCtx&
     }
 }
 
+#ifndef IMPCONV_ROW_TW_LDS
+#define IMPCONV_ROW_TW_LDS 1
+#endif
+#ifndef IMPCONV_ROW_TW_LDS_MAX
+#define IMPCONV_ROW_TW_LDS_MAX (40 * 1024)
+#endif
 template <typename T, int N, bool ACCG, bool MD, bool COMP = false>
 __global__ void __launch_bounds__(row_block<T>(N), row_waves<T>(N))
 k_conv1d_complex(RowArgs a)
@@ -245,17 +249,30 @@ k_conv1d_complex(RowArgs a)
     constexpr bool DUAL = !MD && 2 * GPB * LDSN * int(sizeof(C<T>)) <= 160 * 1024;
     __shared__ C<T> sh[(DUAL ? 2 : 1) * GPB * LDSN];
     static_assert(sizeof(sh) <= 160 * 1024, "LDS footprint exceeds 160 KB");
+    // short rows, several per workgroup: the twiddle tables a row uses
+    // (zeta_N^j and zeta_2N^k, j, k < N) are copied into LDS once per
+    // workgroup, where every transform stage and residue shift reads them,
+    // where the workgroup's LDS stays within IMPCONV_ROW_TW_LDS_MAX bytes
+    constexpr bool TWL = IMPCONV_ROW_TW_LDS && !COMP && N >= 2 && GPB > 1 &&
+                         int(sizeof(sh)) + 2 * N * int(sizeof(C<T>)) <= IMPCONV_ROW_TW_LDS_MAX;
+    __shared__ C<T> twl[TWL ? 2 * N : 1];
     const int grp = threadIdx.x / G, t = threadIdx.x % G;
     const RowCtx c = row_ctx(a, (int64_t)blockIdx.x * GPB + grp);
     C<T>* lds = sh + grp * LDSN;
+    TwSrc<T, COMP> twN = tw_src<T, COMP>(a, tw_off(N));
+    TwSrc<T, COMP> tw2N = tw_src<T, COMP>(a, tw_off(2 * N));
+    if constexpr (TWL) {
+        for (int j = threadIdx.x; j < 2 * N; j += blockDim.x) twl[j] = j < N ? twN[j] : tw2N[j - N];
+        __syncthreads();
+        twN = twl;
+        tw2N = twl + N;
+    }
 
     if constexpr (!MD) {
-        conv_complex_row<T, N, E, DUAL, COMP>(a, c, t, lds, DUAL ? sh + (GPB + grp) * LDSN : lds);
+        conv_complex_row<T, N, E, DUAL, COMP>(a, c, t, lds, DUAL ? sh + (GPB + grp) * LDSN : lds, twN, tw2N);
         return;
     }
 
-    const TwSrc<T, COMP> twN = tw_src<T, COMP>(a, tw_off(N));
-    const TwSrc<T, COMP> tw2N = tw_src<T, COMP>(a, tw_off(2 * N));
     const C<T>* F = (const C<T>*)a.f + c.of;
     const C<T>* Gp = (const C<T>*)a.g + c.og;
     C<T>* H = (C<T>*)a.h + c.oh;
