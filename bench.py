@@ -96,7 +96,7 @@ def kernel_source_hash(kernel: str = "") -> str:
     if kernel.startswith("colpass"):
         own = lambda fn: fn == "colpass.hpp" or fn.startswith("k_col_")
     elif kernel.startswith("k_conv1d"):
-        own = lambda fn: fn == "rowconv.hpp" or fn.startswith("k_row_")
+        own = lambda fn: fn in ("rowconv.hpp", "queue.hpp") or fn.startswith("k_row_")
     else:
         own = lambda fn: True
     for fn in sorted(os.listdir(csrc)):

@@ -140,6 +140,32 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t nblocks)
     return lg < nblocks ? lg : -1;
 }
 
+#ifndef IMPCONV_COL_TW_LDS
+#define IMPCONV_COL_TW_LDS 1
+#endif
+#ifndef IMPCONV_COL_TW_LDS_MAXN
+#define IMPCONV_COL_TW_LDS_MAXN 512
+#endif
+// Whether k_colpass<T, N, MODE> keeps its twiddle tables in LDS: plain
+// (not compensated) tables of the padded, centered and ternary modes, for
+// columns of up to IMPCONV_COL_TW_LDS_MAXN points transformed across threads,
+// where the 2N table entries leave the number of workgroups the LDS admits
+// per compute unit unchanged or the workgroup within 64 KB (two or more per
+// compute unit).  Where the copy costs a workgroup per compute unit (the
+// complex128 padded backward pass at 256 points: 0.257 -> 0.295 ms per
+// launch on its own), the 3D step that overlaps it with the rows is still
+// faster (256^3 complex128: 4.63 -> 4.57 ms).
+template <typename T, int N, int MODE, bool COMP>
+constexpr bool COL_TWL = [] {
+    constexpr int E = col_E<T, MODE>(N), TC = col_TC<T, MODE>(N);
+    constexpr int sh = (N > E ? lpad_size(N) * TC : 1) * int(sizeof(C<T>));
+    constexpr int tw = 2 * N * int(sizeof(C<T>));
+    return IMPCONV_COL_TW_LDS && !COMP && N > E && N <= IMPCONV_COL_TW_LDS_MAXN &&
+           (MODE == kPadBwd || MODE == kPadFwd || MODE == kCenBwd || MODE == kCenFwd || MODE == kTerBwd ||
+            MODE == kTerFwd) &&
+           ((160 * 1024) / sh == (160 * 1024) / (sh + tw) || sh + tw <= 64 * 1024);
+}();
+
 template <typename T, int N, int MODE, int DIR, bool COMP = false>
 __global__ void __launch_bounds__((col_block<T, MODE>(N)))
 k_colpass(ColArgs a)
@@ -170,9 +196,23 @@ k_colpass(ColArgs a)
         if constexpr (COMP) return CompTw<T>{twb + off, (const C<T>*)a.twlo + off};
         else return twb + off;
     };
-    const TWT twN = twsrc(tw_off(N));
-    const TWT tw2N = twsrc(tw_off(2 * N));
+    TWT twN = twsrc(tw_off(N));
+    TWT tw2N = twsrc(tw_off(2 * N));
     const C<T>* tw3N = (const C<T>*)a.tw3 + tw_off(N);
+    const C<T>* tw2Np = twb + tw_off(2 * N);  // plain zeta_2N table (ternary modes)
+    // short columns: the two tables a pass reads (zeta_N^j for the transform
+    // stages; zeta_2N^k or, centered modes, zeta_3N^k, for the residue
+    // shifts; j, k < N) are copied into LDS once per workgroup, where no
+    // fewer workgroups then fit a compute unit
+    if constexpr (COL_TWL<T, N, MODE, COMP>) {
+        __shared__ C<T> twl[2 * N];
+        const C<T>* t2 = (MODE == kCenBwd || MODE == kCenFwd) ? tw3N : twb + tw_off(2 * N);
+        for (int j = threadIdx.x; j < 2 * N; j += blockDim.x) twl[j] = j < N ? twb[tw_off(N) + j] : t2[j - N];
+        __syncthreads();
+        twN = twl;
+        if constexpr (MODE == kCenBwd || MODE == kCenFwd) tw3N = twl + N;
+        else { tw2N = twl + N; tw2Np = twl + N; }
+    }
     const int64_t ib = s1 * a.in_bs + s2 * a.in_bs2 + cc, ob = s1 * a.out_bs + s2 * a.out_bs2 + cc;
     auto ldrow = [&](int q, int row, int nrows) -> C<T> {  // in[q] at (row, c), zero outside
         const C<T>* p = (const C<T>*)a.in[q] + ib;
@@ -369,7 +409,7 @@ k_colpass(ColArgs a)
         constexpr int NH = N / 2;
         const bool plane = a.sym == 1 && c == 0;
         const C<T>* base = (const C<T>*)a.in[0] + s1 * a.in_bs + s2 * a.in_bs2;
-        const C<T>* tw2N = twb + tw_off(2 * N);
+        const C<T>* tw2N = tw2Np;
         int tl = t;
         asm volatile("" : "+v"(tl));
         C<T> x[E];
@@ -399,7 +439,7 @@ k_colpass(ColArgs a)
         for (int e = 0; e < E; ++e) strow(1, t + e * G, x[e]);
     } else if constexpr (MODE == kTerFwd) {
         constexpr int NH = N / 2;
-        const C<T>* tw2N = twb + tw_off(2 * N);
+        const C<T>* tw2N = tw2Np;
         C<T> x[E], y[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) x[e] = ldrow(0, t + e * G, N);
