@@ -144,17 +144,20 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t nblocks)
 #define IMPCONV_COL_TW_LDS 1
 #endif
 #ifndef IMPCONV_COL_TW_LDS_MAXN
-#define IMPCONV_COL_TW_LDS_MAXN 512
+#define IMPCONV_COL_TW_LDS_MAXN 2048
 #endif
 // Whether k_colpass<T, N, MODE> keeps its twiddle tables in LDS: plain
 // (not compensated) tables of the padded, centered and ternary modes, for
 // columns of up to IMPCONV_COL_TW_LDS_MAXN points transformed across threads,
 // where the 2N table entries leave the number of workgroups the LDS admits
-// per compute unit unchanged or the workgroup within 64 KB (two or more per
-// compute unit).  Where the copy costs a workgroup per compute unit (the
-// complex128 padded backward pass at 256 points: 0.257 -> 0.295 ms per
-// launch on its own), the 3D step that overlaps it with the rows is still
-// faster (256^3 complex128: 4.63 -> 4.57 ms).
+// per compute unit unchanged, or the workgroup within 64 KB (columns of up
+// to 512 points: two or more workgroups per compute unit), or within the
+// 160 KB of one compute unit (1024 and 2048 points: workgroups of 512 or
+// 1024 threads, of which the registers admit one or two).  Where the copy
+// costs a workgroup per compute unit (the complex128 padded backward pass at
+// 256 points: 0.257 -> 0.295 ms per launch on its own), the 3D step that
+// overlaps it with the rows is still faster (256^3 complex128: 4.63 -> 4.57
+// ms); at 2048 points the 2D Euler step goes 0.711 -> 0.685 ms.
 template <typename T, int N, int MODE, bool COMP>
 constexpr bool COL_TWL = [] {
     constexpr int E = col_E<T, MODE>(N), TC = col_TC<T, MODE>(N);
@@ -163,7 +166,7 @@ constexpr bool COL_TWL = [] {
     return IMPCONV_COL_TW_LDS && !COMP && N > E && N <= IMPCONV_COL_TW_LDS_MAXN &&
            (MODE == kPadBwd || MODE == kPadFwd || MODE == kCenBwd || MODE == kCenFwd || MODE == kTerBwd ||
             MODE == kTerFwd) &&
-           ((160 * 1024) / sh == (160 * 1024) / (sh + tw) || sh + tw <= 64 * 1024);
+           ((160 * 1024) / sh == (160 * 1024) / (sh + tw) || sh + tw <= (N >= 1024 ? 160 : 64) * 1024);
 }();
 
 template <typename T, int N, int MODE, int DIR, bool COMP = false>
