@@ -146,6 +146,9 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t nblocks)
 #ifndef IMPCONV_COL_TW_LDS_MAXN
 #define IMPCONV_COL_TW_LDS_MAXN 2048
 #endif
+#ifndef IMPCONV_COL_TW_LDS_FS
+#define IMPCONV_COL_TW_LDS_FS 1
+#endif
 // Whether k_colpass<T, N, MODE> keeps its twiddle tables in LDS: plain
 // (not compensated) tables of the padded, centered and ternary modes, for
 // columns of up to IMPCONV_COL_TW_LDS_MAXN points transformed across threads,
@@ -158,14 +161,20 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t nblocks)
 // 256 points: 0.257 -> 0.295 ms per launch on its own), the 3D step that
 // overlaps it with the rows is still faster (256^3 complex128: 4.63 -> 4.57
 // ms); at 2048 points the 2D Euler step goes 0.711 -> 0.685 ms.
+// Tables of N entries a mode reads with N-independent indices: the stage
+// table, and for the padded, centered and ternary modes the residue shifts.
+__host__ __device__ constexpr int col_tw_tables(int mode)
+{
+    return (mode == kFsBwd || mode == kFsFwd || mode == kFft) ? 1 : 2;
+}
 template <typename T, int N, int MODE, bool COMP>
 constexpr bool COL_TWL = [] {
     constexpr int E = col_E<T, MODE>(N), TC = col_TC<T, MODE>(N);
     constexpr int sh = (N > E ? lpad_size(N) * TC : 1) * int(sizeof(C<T>));
-    constexpr int tw = 2 * N * int(sizeof(C<T>));
+    constexpr int tw = col_tw_tables(MODE) * N * int(sizeof(C<T>));
     return IMPCONV_COL_TW_LDS && !COMP && N > E && N <= IMPCONV_COL_TW_LDS_MAXN &&
            (MODE == kPadBwd || MODE == kPadFwd || MODE == kCenBwd || MODE == kCenFwd || MODE == kTerBwd ||
-            MODE == kTerFwd) &&
+            MODE == kTerFwd || (IMPCONV_COL_TW_LDS_FS && (MODE == kFsBwd || MODE == kFsFwd || MODE == kFft))) &&
            ((160 * 1024) / sh == (160 * 1024) / (sh + tw) || sh + tw <= (N >= 1024 ? 160 : 64) * 1024);
 }();
 
@@ -208,13 +217,15 @@ k_colpass(ColArgs a)
     // shifts; j, k < N) are copied into LDS once per workgroup, where no
     // fewer workgroups then fit a compute unit
     if constexpr (COL_TWL<T, N, MODE, COMP>) {
-        __shared__ C<T> twl[2 * N];
+        // the four-step and plain FFT modes copy the stage table only
+        constexpr int NT = col_tw_tables(MODE) * N;
+        __shared__ C<T> twl[NT];
         const C<T>* t2 = (MODE == kCenBwd || MODE == kCenFwd) ? tw3N : twb + tw_off(2 * N);
-        for (int j = threadIdx.x; j < 2 * N; j += blockDim.x) twl[j] = j < N ? twb[tw_off(N) + j] : t2[j - N];
+        for (int j = threadIdx.x; j < NT; j += blockDim.x) twl[j] = j < N ? twb[tw_off(N) + j] : t2[j - N];
         __syncthreads();
         twN = twl;
         if constexpr (MODE == kCenBwd || MODE == kCenFwd) tw3N = twl + N;
-        else { tw2N = twl + N; tw2Np = twl + N; }
+        else if constexpr (NT == 2 * N) { tw2N = twl + N; tw2Np = twl + N; }
     }
     const int64_t ib = s1 * a.in_bs + s2 * a.in_bs2 + cc, ob = s1 * a.out_bs + s2 * a.out_bs2 + cc;
     auto ldrow = [&](int q, int row, int nrows) -> C<T> {  // in[q] at (row, c), zero outside
