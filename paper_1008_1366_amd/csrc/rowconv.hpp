@@ -572,6 +572,16 @@ k_conv1d_cyclic(RowArgs a)
     const RowCtx c = row_ctx(a, (int64_t)blockIdx.x * GPB + grp);
     C<T>* lds = sh + grp * LDSN;
     const C<T>* twN = (const C<T>*)a.tw + tw_off(N);
+    // several rows per workgroup: the stage table (N entries) is copied
+    // into LDS once per workgroup, as in k_conv1d_complex
+    constexpr bool TWL = IMPCONV_ROW_TW_LDS && GPB > 1 && N > E &&
+                         int(sizeof(sh)) + N * int(sizeof(C<T>)) <= IMPCONV_ROW_TW_LDS_MAX;
+    __shared__ C<T> twl[TWL ? N : 1];
+    if constexpr (TWL) {
+        for (int j = threadIdx.x; j < N; j += blockDim.x) twl[j] = twN[j];
+        __syncthreads();
+        twN = twl;
+    }
     const C<T>* F = (const C<T>*)a.f + c.of;
     const C<T>* Gp = (const C<T>*)a.g + c.og;
     C<T>* H = (C<T>*)a.h + c.oh;
