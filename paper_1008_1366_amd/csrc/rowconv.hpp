@@ -872,6 +872,18 @@ __device__ __forceinline__ void herm_build3_from(C<T> (&lo)[E], C<T> (&hi)[E], i
 #ifndef IMPCONV_HERM_TW_LDS
 #define IMPCONV_HERM_TW_LDS 1
 #endif
+#ifndef IMPCONV_HERM_TW_LDS_MAXNC
+#define IMPCONV_HERM_TW_LDS_MAXNC 256
+#endif
+#ifndef IMPCONV_HERM_TW_LDS_BYTES
+#define IMPCONV_HERM_TW_LDS_BYTES (40 * 1024)
+#endif
+#ifndef IMPCONV_TER_TW_LDS
+#define IMPCONV_TER_TW_LDS 1
+#endif
+#ifndef IMPCONV_TER_TW_LDS_BYTES
+#define IMPCONV_TER_TW_LDS_BYTES (40 * 1024)
+#endif
 template <typename T, int NC, bool MD>
 __global__ void __launch_bounds__((row_block<T, 1>(NC)), row_waves<T>(NC))
 k_conv1d_hermitian(RowArgs a)
@@ -890,8 +902,8 @@ k_conv1d_hermitian(RowArgs a)
     // transform stage and residue shift reads them there instead of waiting
     // on global loads; only where the workgroup's LDS stays within 40 KB
     // (four workgroups per compute unit)
-    constexpr bool TWL = IMPCONV_HERM_TW_LDS && NC >= 2 && NC <= 256 &&
-                         int(sizeof(sh)) + (NC + 2 * N) * int(sizeof(C<T>)) <= 40 * 1024;
+    constexpr bool TWL = IMPCONV_HERM_TW_LDS && NC >= 2 && NC <= IMPCONV_HERM_TW_LDS_MAXNC &&
+                         int(sizeof(sh)) + (NC + 2 * N) * int(sizeof(C<T>)) <= IMPCONV_HERM_TW_LDS_BYTES;
     __shared__ C<T> twl[TWL ? NC + 2 * N : 1];
     const int grp = threadIdx.x / G, t = threadIdx.x % G;
     const RowCtx c = row_ctx(a, (int64_t)blockIdx.x * GPB + grp);
@@ -1301,6 +1313,21 @@ k_conv1d_ternary(RowArgs a)
         C<T>* lds1 = DUAL ? sh_dual<T>(sh, GPB, LDSN, grp) : lds;
         const C<T>* twb = (const C<T>*)a.tw;
         const C<T>* twNN = twb + tw_off(NN);
+        const C<T>* tw2b = twb + tw_off(2 * NN);  // zeta_2NN^k, k < NN
+        const C<T>* tw4b = twb + tw_off(4 * NN);  // zeta_4NN^k, k < NN
+        // the three tables (3 NN entries) copied into LDS once per
+        // workgroup where the workgroup's LDS stays small
+        constexpr bool TWL = IMPCONV_TER_TW_LDS && NN > E &&
+                             int(sizeof(sh)) + 3 * NN * int(sizeof(C<T>)) <= IMPCONV_TER_TW_LDS_BYTES;
+        __shared__ C<T> twl[TWL ? 3 * NN : 1];
+        if constexpr (TWL) {
+            for (int j = threadIdx.x; j < 3 * NN; j += blockDim.x)
+                twl[j] = j < NN ? twNN[j] : (j < 2 * NN ? tw2b[j - NN] : tw4b[j - 2 * NN]);
+            __syncthreads();
+            twNN = twl;
+            tw2b = twl + NN;
+            tw4b = twl + 2 * NN;
+        }
         const int mm = m < NN ? m : NN;
         auto pair = [&](auto& a0, auto& a1, auto dir) {
             constexpr int D = decltype(dir)::value;
@@ -1319,8 +1346,8 @@ k_conv1d_ternary(RowArgs a)
         auto build = [&](const void* base, int64_t off, C<T> (&z0)[E], C<T> (&z1)[E]) {
             const int q = opaque_zero();
             const C<T>* U = (const C<T>*)base + off + q;
-            const C<T>* tw2N = twb + tw_off(2 * NN) + q;
-            const C<T>* tw4N = twb + tw_off(4 * NN) + q;
+            const C<T>* tw2N = tw2b + q;
+            const C<T>* tw4N = tw4b + q;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const int k = t + e * G;
@@ -1349,8 +1376,8 @@ k_conv1d_ternary(RowArgs a)
         mirror<T, NN, E>(x0, y0, t, lds);
         mirror<T, NN, E>(x1, y1, t, lds);
         const int q = opaque_zero();
-        const C<T>* tw2N = twb + tw_off(2 * NN) + q;
-        const C<T>* tw4N = twb + tw_off(4 * NN) + q;
+        const C<T>* tw2N = tw2b + q;
+        const C<T>* tw4N = tw4b + q;
         const T s = T(1) / T(4 * NN);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
