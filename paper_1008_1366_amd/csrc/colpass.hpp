@@ -153,10 +153,14 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t nblocks)
 // (not compensated) tables of the padded, centered and ternary modes, for
 // columns of up to IMPCONV_COL_TW_LDS_MAXN points transformed across threads,
 // where the 2N table entries leave the number of workgroups the LDS admits
-// per compute unit unchanged, or the workgroup within 64 KB (columns of up
-// to 512 points: two or more workgroups per compute unit), or within the
-// 160 KB of one compute unit (1024 and 2048 points: workgroups of 512 or
-// 1024 threads, of which the registers admit one or two).  Where the copy
+// per compute unit unchanged, or the workgroup within 64 KB (two or more
+// workgroups per compute unit), or, for the padded, centered and ternary
+// passes of 1024 and 2048 points (workgroups of 512 or 1024 threads, of which
+// their registers admit one or two), within the 160 KB of one compute unit.
+// The plain FFT pass of the explicit comparators at 1024 points lost a
+// workgroup per compute unit to the copy and ran slower (3D Hermitian
+// comparator 89 -> 100 ms), so the four-step and FFT modes take only the
+// first two rules.  Where the copy
 // costs a workgroup per compute unit (the complex128 padded backward pass at
 // 256 points: 0.257 -> 0.295 ms per launch on its own), the 3D step that
 // overlaps it with the rows is still faster (256^3 complex128: 4.63 -> 4.57
@@ -175,7 +179,8 @@ constexpr bool COL_TWL = [] {
     return IMPCONV_COL_TW_LDS && !COMP && N > E && N <= IMPCONV_COL_TW_LDS_MAXN &&
            (MODE == kPadBwd || MODE == kPadFwd || MODE == kCenBwd || MODE == kCenFwd || MODE == kTerBwd ||
             MODE == kTerFwd || (IMPCONV_COL_TW_LDS_FS && (MODE == kFsBwd || MODE == kFsFwd || MODE == kFft))) &&
-           ((160 * 1024) / sh == (160 * 1024) / (sh + tw) || sh + tw <= (N >= 1024 ? 160 : 64) * 1024);
+           ((160 * 1024) / sh == (160 * 1024) / (sh + tw) ||
+            sh + tw <= (N >= 1024 && col_tw_tables(MODE) == 2 ? 160 : 64) * 1024);
 }();
 
 template <typename T, int N, int MODE, int DIR, bool COMP = false>
