@@ -1093,16 +1093,10 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
     // rows and y forward pass of np planes from y-residue set Y into the
     // planes' term 0 in Xf[rx] at xf
     auto rows_fwd = [&](void* const* YF, void* const* YG, char* xf, int64_t np, hipStream_t q) -> impconv_status {
-        // complex64: one launch over the R residues (3D Hermitian 512^2 x 257,
-        // M = 3: 10.23 -> 9.95 ms per step); complex128: one launch per
-        // residue, which leaves the next chunk's y backward pass room to
-        // start between them (one launch: 17.79 -> 18.10 ms)
-        impconv_status st2 = IMPCONV_OK;
-        if (dt == IMPCONV_C64) {
-            st2 = inner_rows_residues(tb, p, YF, YG, R, np * N1, q, rowfl);
-        } else {
-            for (int ry = 0; ry < R && !st2; ++ry) st2 = inner_rows(tb, p, YF[ry], YG[ry], np * N1, q, rowfl);
-        }
+        // one launch over the R residues (3D Hermitian 512^2 x 257, M = 3:
+        // complex64 10.23 -> 9.95 ms per step; complex128, with the twiddle
+        // tables in LDS, 17.14 -> 16.72 ms against one launch per residue)
+        const impconv_status st2 = inner_rows_residues(tb, p, YF, YG, R, np * N1, q, rowfl);
         if (st2) return st2;
         // y forward: [plane][y'][i = 0][n2] (R residues) -> term 0 of the plane in Xf[rx]
         ColArgs c = col_args(tb, dt);
