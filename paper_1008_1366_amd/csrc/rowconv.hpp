@@ -811,9 +811,22 @@ __device__ __forceinline__ void herm_load(const C<T>* U, int m, int t, C<T> (&lo
     }
 }
 
+// a if c, else b, selected bit by bit: a select between two array elements
+// may otherwise become a load from a selected address, which keeps the
+// arrays in scratch memory
+template <typename T>
+__device__ __forceinline__ C<T> pick(bool c, C<T> a, C<T> b)
+{
+    int ma = c ? -1 : 0;
+    asm volatile("" : "+v"(ma));
+    const int mb = ~ma;
+    return C<T>{mask_bits(a.re, ma) + mask_bits(b.re, mb), mask_bits(a.im, ma) + mask_bits(b.im, mb)};
+}
+
 // herm_build3 from entries already loaded by herm_load (lo, hi are consumed;
-// the prefetching form of the row kernel).
-template <typename T, int NC, int E, bool PAIRED = false>
+// the prefetching form of the row kernel).  BITSEL: the k = 0 selections
+// through pick.
+template <typename T, int NC, int E, bool PAIRED = false, bool BITSEL = false>
 __device__ __forceinline__ void herm_build3_from(C<T> (&lo)[E], C<T> (&hi)[E], int t, C<T>* lds,
                                                  const C<T>* tw3N, const C<T>* twN, C<T> (&z0)[E],
                                                  C<T> (&z1)[E], C<T> (&z2)[E], T dc = T(1),
@@ -837,8 +850,8 @@ __device__ __forceinline__ void herm_build3_from(C<T> (&lo)[E], C<T> (&hi)[E], i
         const int k = t + e * G;
         const bool k0 = e == 0 && k == 0;
         const C<T> a = lo[e];                         // U_k
-        const C<T> b = k0 ? zero<T>() : him[e];       // U_{N-k}
-        const C<T> c = k0 ? hi[e] : lom[e];           // U_{NC-k}
+        const C<T> b = BITSEL ? pick(k0, zero<T>(), him[e]) : (k0 ? zero<T>() : him[e]);  // U_{N-k}
+        const C<T> c = BITSEL ? pick(k0, hi[e], lom[e]) : (k0 ? hi[e] : lom[e]);          // U_{NC-k}
         const C<T> d = hi[e];                         // U_{NC+k}
         const C<T> wk = tw3N[k + z], wc = tw3N[NC - k + z], w2 = twN[k + z];
         // r = 0
@@ -939,24 +952,27 @@ k_conv1d_hermitian(RowArgs a)
     };
     C<T> P0[E], P1[E], P2[E];
     const int64_t nM = MD ? a.M : 1;
-    // complex64 rows of up to 256 points: g's entries are loaded before f's
+    // rows of up to 256 points: g's entries are loaded before f's
     // transforms, so that the loads are in flight while the wave computes
-    // (measured faster on the 512 x 512 x 257 z rows; in complex128, and in
-    // longer rows, the extra live registers cost more than the latency they
-    // hide)
-    constexpr bool PREFETCH = sizeof(T) == 4 && NC <= 128;
+    // (measured faster on the 512 x 512 x 257 z rows: complex64 10.69 ->
+    // 10.25 ms per step, complex128 16.73 -> 16.68 ms; in complex128 the
+    // k = 0 selections go through pick, without which the compiler kept two
+    // of the arrays in scratch memory and the kernel ran slower; in longer
+    // rows the extra live registers cost more than the latency they hide)
+    constexpr bool PREFETCH = NC <= 128;
     for (int64_t i = 0; i < nM; ++i) {
         C<T> x0[E], x1[E], x2[E], y0[E], y1[E], y2[E];
         const C<T>* Fi = (const C<T>*)a.f + c.of + i * a.f_i;
         const C<T>* Gi = (const C<T>*)a.g + c.og + i * a.g_i;
         const T dc = (a.flags & kHermAdj) ? T(2) : T(1);
         if constexpr (PREFETCH) {
+            constexpr bool BS = sizeof(T) == 8;  // in complex64 pick costs registers (spills)
             C<T> lo[E], hi[E];
             herm_load<T, NC, E>(Fi, m, t, lo, hi);
-            herm_build3_from<T, NC, E, TRI>(lo, hi, t, lds, tw3N, twN, x0, x1, x2, dc, lds1);
+            herm_build3_from<T, NC, E, TRI, BS>(lo, hi, t, lds, tw3N, twN, x0, x1, x2, dc, lds1);
             herm_load<T, NC, E>(Gi, m, t, lo, hi);
             fft3x(x0, x1, x2, std::integral_constant<int, +1>{});
-            herm_build3_from<T, NC, E, TRI>(lo, hi, t, lds, tw3N, twN, y0, y1, y2, T(1), lds1);
+            herm_build3_from<T, NC, E, TRI, BS>(lo, hi, t, lds, tw3N, twN, y0, y1, y2, T(1), lds1);
         } else {
             herm_build3<T, NC, E, TRI>(Fi, m, t, lds, tw3N, twN, x0, x1, x2, dc, lds1);
             fft3x(x0, x1, x2, std::integral_constant<int, +1>{});
