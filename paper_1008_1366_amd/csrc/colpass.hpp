@@ -74,6 +74,10 @@ struct ColArgs {
     int64_t nf;                    // four-step: full 1D length N1 * N
     const int64_t* slab_off;       // four-step, optional: element offset of each s1 slab's 1D data
     const int64_t* slab_m;         // four-step, optional: logical length of each s1 slab
+    int64_t nslab2;                // k_colpass: 0, or the slabs of a first set, the rest (nslab - nslab2)
+                                   // reading in[0] + in2_off and writing out[r] + out2_off (elements),
+                                   // with the same strides and flags
+    int64_t in2_off, out2_off;
     uint32_t fsflags;              // 1 = reverse within m (input of kFsBwd / kPadBwd, output of kFsFwd /
                                    // kPadFwd), 2 = conjugate the input (kFsBwd / kPadBwd), 4 = Hermitian
                                    // adjoint on the k_last = 0 hyperplane (kCenBwd: load U_k + conj U_{-k};
@@ -195,7 +199,12 @@ k_colpass(ColArgs a)
     const int64_t ntile = (a.ncols + TC - 1) / TC;
     const int64_t lg = xcd_tile(a.nslab * ntile);
     if (lg < 0) return;  // whole padding block: no barrier is reached
-    const int64_t slab = lg / ntile, tile = lg - slab * ntile;
+    // two sets in one launch (nslab2 > 0): slabs from nslab2 on read and
+    // write the second set, at element offsets in2_off / out2_off
+    const int64_t slab0 = lg / ntile, tile = lg - slab0 * ntile;
+    const bool set2 = a.nslab2 > 0 && slab0 >= a.nslab2;
+    const int64_t slab = set2 ? slab0 - a.nslab2 : slab0;
+    const int64_t io2 = set2 ? a.in2_off : 0, oo2 = set2 ? a.out2_off : 0;
     const int64_t s1 = slab / a.nsub, s2 = slab - s1 * a.nsub;
     const int64_t c = tile * TC + col;
     const bool cin = c < a.ncols;  // column exists: stores go through
@@ -232,7 +241,7 @@ k_colpass(ColArgs a)
         if constexpr (MODE == kCenBwd || MODE == kCenFwd) tw3N = twl + N;
         else if constexpr (NT == 2 * N) { tw2N = twl + N; tw2Np = twl + N; }
     }
-    const int64_t ib = s1 * a.in_bs + s2 * a.in_bs2 + cc, ob = s1 * a.out_bs + s2 * a.out_bs2 + cc;
+    const int64_t ib = s1 * a.in_bs + s2 * a.in_bs2 + cc + io2, ob = s1 * a.out_bs + s2 * a.out_bs2 + cc + oo2;
     auto ldrow = [&](int q, int row, int nrows) -> C<T> {  // in[q] at (row, c), zero outside
         const C<T>* p = (const C<T>*)a.in[q] + ib;
         const bool ok = cact && row >= 0 && row < nrows;
@@ -299,7 +308,7 @@ k_colpass(ColArgs a)
             const int iym = -ky + a.sym_offy;
             mcol = (iym >= 0 && iym < a.sym_ny) ? int64_t(iym) * a.sym_nz : cc;
         }
-        const C<T>* base = (const C<T>*)a.in[0] + s1 * a.in_bs + s2 * a.in_bs2;
+        const C<T>* base = (const C<T>*)a.in[0] + s1 * a.in_bs + s2 * a.in_bs2 + io2;
         // wavenumber k of this column (|k| < m)
         auto ldk = [&](int k) -> C<T> {
             const bool in = cact && k > -a.m && k < a.m;
@@ -427,7 +436,7 @@ k_colpass(ColArgs a)
         // mirror of the k_last = 0 line (2D rule: column 0)
         constexpr int NH = N / 2;
         const bool plane = a.sym == 1 && c == 0;
-        const C<T>* base = (const C<T>*)a.in[0] + s1 * a.in_bs + s2 * a.in_bs2;
+        const C<T>* base = (const C<T>*)a.in[0] + s1 * a.in_bs + s2 * a.in_bs2 + io2;
         const C<T>* tw2N = tw2Np;
         int tl = t;
         asm volatile("" : "+v"(tl));

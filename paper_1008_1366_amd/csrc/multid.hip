@@ -1069,12 +1069,22 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
     if ((st = outer_bwd(tb, p, g, Xg, batch, M * n0 * n1 * n2, n0, m0, N0, n1 * n2, sym ? 2 : 0, n2,
                         int(n1 - m1), int(n1), mask_nz, ylo, int(n1), int(m2), s, fs_g))) return st;
     // y backward pass of np planes: slabs (plane, i) of [n1][n2] -> [plane][y'][i][n2]
-    auto ypass = [&](const void* src, void* const* dst, int64_t np, uint32_t fsf, hipStream_t q) -> impconv_status {
+    // src2/dst2: a second input and its residue arrays, at the same element
+    // distance from src/dst for every residue, transformed in the same
+    // launch (slabs np M .. 2 np M)
+    auto ypass = [&](const void* src, void* const* dst, int64_t np, uint32_t fsf, hipStream_t q,
+                     const void* src2 = nullptr, void* const* dst2 = nullptr) -> impconv_status {
         ColArgs c = col_args(tb, dt);
         c.fsflags = fsf;
         c.in[0] = src;
         for (int r = 0; r < 3; ++r) c.out[r] = dst[r];
         c.nslab = np * M;
+        if (src2) {
+            c.nslab2 = np * M;
+            c.nslab = 2 * np * M;
+            c.in2_off = (static_cast<const char*>(src2) - static_cast<const char*>(src)) / int64_t(cs);
+            c.out2_off = (static_cast<char*>(dst2[0]) - static_cast<char*>(dst[0])) / int64_t(cs);
+        }
         c.nsub = M;
         c.in_bs = M * n1 * n2;
         c.in_bs2 = n1 * n2;
@@ -1149,8 +1159,20 @@ impconv_status runnd(int kind, int dt, int nd, int64_t batch, int64_t M, const i
             hipError_t e = hipSuccess;
             if (!one && j >= 2) e = hipStreamWaitEvent(s, L->pipe[2 + bset], 0);
             if (e != hipSuccess) { st = hip_fail(e, "3D pipeline wait"); break; }
-            if ((st = ypass(xf, YF, np, fs_f, s))) break;
-            if ((st = ypass(xg, YG, np, cb, s))) break;
+            // centered (Hermitian) passes of f and g in one launch where they
+            // share their flags and the residue arrays of g sit at one
+            // distance from those of f (3D Hermitian 512^2 x 257, M = 3:
+            // twice as many workgroups per launch, a shorter tail)
+            const bool pair = herm && fs_f == cb && static_cast<char*>(YG[1]) - static_cast<char*>(YF[1]) ==
+                                                        static_cast<char*>(YG[0]) - static_cast<char*>(YF[0]) &&
+                              static_cast<char*>(YG[2]) - static_cast<char*>(YF[2]) ==
+                                  static_cast<char*>(YG[0]) - static_cast<char*>(YF[0]);
+            if (pair) {
+                if ((st = ypass(xf, YF, np, fs_f, s, xg, YG))) break;
+            } else {
+                if ((st = ypass(xf, YF, np, fs_f, s))) break;
+                if ((st = ypass(xg, YG, np, cb, s))) break;
+            }
             if (!one) {
                 e = hipEventRecord(L->pipe[bset], s);
                 if (e == hipSuccess) e = hipStreamWaitEvent(q, L->pipe[bset], 0);
