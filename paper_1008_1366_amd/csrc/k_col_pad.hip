@@ -21,9 +21,10 @@ static hipError_t go(const ColArgs& a, hipStream_t s)
     if (nb == 0) return hipSuccess;
     if constexpr (pipe_ok<T>(N)) {
         // one persistent workgroup per CU (the LDS holds one tile), at least
-        // two tiles each
+        // two tiles each; one set of slabs only (k_colpipe has no second set)
         const int64_t grid = int64_t(a.ncu) / 8 * 8;
-        if (grid >= 8 && nb >= 2 * grid && pipe_offsets_fit<T, N>(a.in_ld) && pipe_offsets_fit<T, N>(a.out_ld)) {
+        if (a.nslab2 == 0 && grid >= 8 && nb >= 2 * grid && pipe_offsets_fit<T, N>(a.in_ld) &&
+            pipe_offsets_fit<T, N>(a.out_ld)) {
             timing_begin(s);
             hipLaunchKernelGGL((k_colpipe<T, N, MODE>), dim3(grid), dim3(col_block<T>(N)), 0, s, a);
             timing_end(MODE_NAME(MODE), s);
